@@ -1,0 +1,285 @@
+"""ctypes binding of the FP64 oracle (liborc.so, plain C++ built with g++).
+
+Test infrastructure only.  Builds the library on first use if it is absent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborc.so")
+SOURCES = ["orc_core.cpp", "orc_frame.cpp", "orc_mlp.cpp"]
+
+TAG_UPDATE, TAG_INIT_X, TAG_INIT_V, TAG_PI, TAG_HSEF, TAG_LEARNED = range(6)
+
+
+def build(force: bool = True) -> str:
+    """Compile liborc.so with g++ (no GPU code involved)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", tmp] + srcs
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+dp = C.POINTER(C.c_double)
+ip = C.POINTER(C.c_int32)
+up = C.POINTER(C.c_uint32)
+
+
+class OrcMap(C.Structure):
+    _fields_ = [("width", C.c_double), ("height", C.c_double), ("n_polys", C.c_int32),
+                ("poly_ptr", ip), ("verts", dp), ("start", C.c_double * 2),
+                ("target", C.c_double * 2)]
+
+
+class OrcSwarm(C.Structure):
+    _fields_ = [("G", C.c_int32), ("N", C.c_int32), ("W", C.c_int32), ("T", C.c_int32),
+                ("width", C.c_double), ("height", C.c_double), ("hyper", dp),
+                ("alpha", C.c_double), ("beta", C.c_int32), ("seed", C.c_uint64),
+                ("instance", C.c_uint32), ("X", dp), ("V", dp), ("P", dp), ("f", dp),
+                ("L", dp), ("Q", ip), ("Pf", dp), ("PL", dp), ("PQ", ip), ("gbest_n", ip),
+                ("gbest_f", dp), ("tbest_g", C.c_int32), ("tbest_n", C.c_int32),
+                ("tbest_f", C.c_double), ("k", C.c_int32), ("ctr", C.c_uint32)]
+
+
+class OrcHsef(C.Structure):
+    _fields_ = [("outer_hyper", dp), ("ov", dp), ("op", dp), ("opf", dp), ("otb", C.c_int32),
+                ("epoch_in_frame", C.c_int32), ("T_outer", C.c_int32),
+                ("epoch_ctr", C.c_uint32)]
+
+
+class OrcFrameCfg(C.Structure):
+    _fields_ = [("use_pi", C.c_int32), ("pi_gamma", C.c_double), ("pi_radius", C.c_double),
+                ("at_mode", C.c_int32), ("at_window", C.c_int32), ("at_delta", C.c_double),
+                ("hsef_every", C.c_int32)]
+
+
+class OrcFrameResult(C.Structure):
+    _fields_ = [("cost", C.c_double), ("length", C.c_double), ("crossings", C.c_int32),
+                ("iters", C.c_int32), ("truncated", C.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_philox4x32_10.argtypes = [up, up, up]
+        L.orc_philox_many.argtypes = [C.c_int64, up, up, up]
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_classify.argtypes = [dp, dp, dp, dp, C.c_double]
+        L.orc_classify.restype = C.c_int32
+        L.orc_crosses.argtypes = [dp, dp, dp, dp]
+        L.orc_crosses.restype = C.c_int32
+        L.orc_fitness.argtypes = [C.POINTER(OrcMap), C.c_int32, C.c_int32, dp, C.c_double,
+                                  C.c_int32, C.c_double, dp, dp, ip, ip, ip]
+        for fn in ("orc_eval", "orc_step"):
+            getattr(L, fn).argtypes = [C.POINTER(OrcSwarm), C.POINTER(OrcMap)]
+        for fn in ("orc_bests", "orc_update"):
+            getattr(L, fn).argtypes = [C.POINTER(OrcSwarm)]
+        L.orc_init.argtypes = [C.POINTER(OrcSwarm), C.c_int32, dp, C.c_double, C.c_double]
+        L.orc_hsef_reset_frame.argtypes = [C.POINTER(OrcSwarm), C.POINTER(OrcHsef)]
+        L.orc_hsef_step.argtypes = [C.POINTER(OrcSwarm), C.POINTER(OrcHsef)]
+        L.orc_at_check.argtypes = [dp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32]
+        L.orc_at_check.restype = C.c_int32
+        L.orc_sim_step.argtypes = [C.c_double, C.c_double, C.c_int32, ip, dp, dp, dp, dp, dp]
+        L.orc_plan_frame.argtypes = [C.POINTER(OrcSwarm), C.POINTER(OrcHsef), C.POINTER(OrcMap),
+                                     C.POINTER(OrcFrameCfg), C.c_int32, dp, dp, dp,
+                                     C.POINTER(OrcFrameResult)]
+        _lib = L
+    return _lib
+
+
+def _p(a, t=dp):
+    return a.ctypes.data_as(t)
+
+
+# ---------------------------------------------------------------------------
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c, up), _p(k, up), _p(out, up))
+    return out
+
+
+def philox_many(ctrs, key):
+    c = np.ascontiguousarray(ctrs, dtype=np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros_like(c)
+    lib().orc_philox_many(len(c), _p(c, up), _p(k, up), _p(out, up))
+    return out
+
+
+def u01(word) -> float:
+    return lib().orc_u01(int(word))
+
+
+class Map:
+    """Oracle view of a map (keeps the numpy buffers alive)."""
+
+    def __init__(self, spec):
+        self.spec = spec
+        self.poly_ptr = np.ascontiguousarray(spec.poly_ptr, dtype=np.int32)
+        self.verts = np.ascontiguousarray(spec.verts, dtype=np.float64).reshape(-1, 2)
+        self.s = OrcMap(float(spec.width), float(spec.height), len(self.poly_ptr) - 1,
+                        _p(self.poly_ptr, ip), _p(self.verts),
+                        (C.c_double * 2)(*map(float, spec.start)),
+                        (C.c_double * 2)(*map(float, spec.target)))
+
+    @property
+    def scale(self):
+        return max(self.s.width, self.s.height)
+
+
+def classify(p, q, a, b, tau):
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (p, q, a, b)]
+    return lib().orc_classify(*[_p(x) for x in arr], float(tau))
+
+
+def crosses(p, q, a, b):
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (p, q, a, b)]
+    return lib().orc_crosses(*[_p(x) for x in arr])
+
+
+def fitness(m: Map, X, W, alpha, beta, tau=None):
+    """Returns dict(f, L, Q, q_yes, n_deg) for paths X (n, 2W)."""
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 2 * W)
+    n = len(X)
+    if tau is None:
+        tau = 1e-6 * m.scale ** 2
+    f = np.zeros(n)
+    Lv = np.zeros(n)
+    Q = np.zeros(n, np.int32)
+    yes = np.zeros(n, np.int32)
+    deg = np.zeros(n, np.int32)
+    lib().orc_fitness(C.byref(m.s), n, W, _p(X), float(alpha), int(beta), float(tau), _p(f),
+                      _p(Lv), _p(Q, ip), _p(yes, ip), _p(deg, ip))
+    return dict(f=f, L=Lv, Q=Q, q_yes=yes, n_deg=deg)
+
+
+class Swarm:
+    """Oracle swarm with numpy-owned state."""
+
+    def __init__(self, sw, width, height):
+        G, N, W = sw.groups, sw.particles, sw.waypoints
+        D = 2 * W
+        self.G, self.N, self.W, self.D = G, N, W, D
+        self.sw = sw
+        self.hyper = np.ascontiguousarray(sw.hyper, dtype=np.float64).reshape(G, 6).copy()
+        z = lambda *sh: np.zeros(sh, np.float64)
+        self.X, self.V, self.P = z(G, N, D), z(G, N, D), z(G, N, D)
+        self.f, self.L, self.Pf, self.PL = z(G, N), z(G, N), z(G, N), z(G, N)
+        self.Q = np.zeros((G, N), np.int32)
+        self.PQ = np.zeros((G, N), np.int32)
+        self.gbest_n = np.zeros(G, np.int32)
+        self.gbest_f = z(G)
+        self.s = OrcSwarm(G, N, W, sw.max_iters, float(width), float(height), _p(self.hyper),
+                          float(sw.alpha), int(sw.beta), int(sw.seed), int(sw.instance),
+                          _p(self.X), _p(self.V), _p(self.P), _p(self.f), _p(self.L),
+                          _p(self.Q, ip), _p(self.Pf), _p(self.PL), _p(self.PQ, ip),
+                          _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0, float("inf"), 0, 0)
+        # online self-evolution state
+        self.outer_hyper = np.ascontiguousarray(sw.hsef_hyper, dtype=np.float64).reshape(G, 6)
+        self.ov, self.op, self.opf = z(G, 3), z(G, 3), np.full(G, np.inf)
+        t_outer = -(-sw.max_iters // sw.hsef_every) if sw.hsef_every > 0 else 1
+        self.h = OrcHsef(_p(self.outer_hyper), _p(self.ov), _p(self.op), _p(self.opf), 0, 0,
+                         t_outer, 0)
+        self.cfg = OrcFrameCfg(int(sw.use_pi), float(sw.pi_gamma), float(sw.pi_radius),
+                               int(sw.at_mode), int(sw.at_window), float(sw.at_delta),
+                               int(sw.hsef_every))
+        self.hist = z(max(sw.max_iters, 1))
+        self.prev_path = None
+
+    # scalar state
+    k = property(lambda self: self.s.k)
+    ctr = property(lambda self: self.s.ctr)
+    tbest = property(lambda self: (self.s.tbest_g, self.s.tbest_n, self.s.tbest_f))
+
+    def init(self, frame=0, prev_path=None, gamma=0.25, radius=0.0):
+        pp = None
+        if prev_path is not None:
+            self._pp = np.ascontiguousarray(prev_path, dtype=np.float64)
+            pp = _p(self._pp)
+        lib().orc_init(C.byref(self.s), int(frame), pp, float(gamma), float(radius))
+
+    def eval(self, m: Map):
+        lib().orc_eval(C.byref(self.s), C.byref(m.s))
+
+    def bests(self):
+        lib().orc_bests(C.byref(self.s))
+
+    def update(self):
+        lib().orc_update(C.byref(self.s))
+
+    def step(self, m: Map, n=1):
+        for _ in range(n):
+            lib().orc_step(C.byref(self.s), C.byref(m.s))
+
+    def hsef_reset_frame(self):
+        lib().orc_hsef_reset_frame(C.byref(self.s), C.byref(self.h))
+
+    def hsef_step(self):
+        lib().orc_hsef_step(C.byref(self.s), C.byref(self.h))
+
+    def plan_frame(self, m: Map, frame: int):
+        D = self.D
+        out = np.zeros(D)
+        res = OrcFrameResult()
+        pp = None
+        if self.prev_path is not None:
+            pp = _p(self.prev_path)
+        lib().orc_plan_frame(C.byref(self.s), C.byref(self.h), C.byref(m.s), C.byref(self.cfg),
+                             int(frame), pp, _p(out), _p(self.hist), C.byref(res))
+        self.prev_path = out.copy()
+        return dict(cost=res.cost, length=res.length, crossings=res.crossings, iters=res.iters,
+                    truncated=res.truncated, path=out)
+
+    def set_scalars(self, k=None, ctr=None, tbest=None):
+        if k is not None:
+            self.s.k = int(k)
+        if ctr is not None:
+            self.s.ctr = int(ctr)
+        if tbest is not None:
+            self.s.tbest_g, self.s.tbest_n, self.s.tbest_f = int(tbest[0]), int(tbest[1]), float(tbest[2])
+
+
+def at_check(hist, k, mode, window, delta, q_tbest):
+    h = np.ascontiguousarray(hist, dtype=np.float64)
+    return lib().orc_at_check(_p(h), int(k), int(mode), int(window), float(delta), int(q_tbest))
+
+
+def sim_step(spec):
+    """Advance a MapSpec's obstacles and endpoints by one frame (in place)."""
+    ptr = np.ascontiguousarray(spec.poly_ptr, dtype=np.int32)
+    verts = np.ascontiguousarray(spec.verts, dtype=np.float64)
+    vel = np.ascontiguousarray(spec.poly_vel, dtype=np.float64)
+    s = np.ascontiguousarray(spec.start, dtype=np.float64)
+    t = np.ascontiguousarray(spec.target, dtype=np.float64)
+    ev = np.ascontiguousarray(spec.endpoint_vel, dtype=np.float64)
+    lib().orc_sim_step(float(spec.width), float(spec.height), len(ptr) - 1, _p(ptr, ip),
+                       _p(verts), _p(vel), _p(s), _p(t), _p(ev))
+    spec.verts, spec.poly_vel, spec.start, spec.target, spec.endpoint_vel = verts, vel, s, t, ev
+    return spec
+
+
+def plan_static(spec, sw, iters=None):
+    """Plain static plan (Algorithm 1 from a uniform swarm); returns the final
+    Tbest fitness and the oracle swarm."""
+    m = Map(spec)
+    s = Swarm(sw, spec.width, spec.height)
+    s.init(0)
+    s.step(m, iters if iters is not None else sw.max_iters)
+    return s.s.tbest_f, s
