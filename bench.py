@@ -1,0 +1,163 @@
+"""Benchmark of the SEPSO planner hot path on one MI355X.
+
+A step is one planning frame of every instance of the batched workload:
+1024 independent dynamic instances of uneven size (8-32 waypoints, 4-100
+rectangles, 32-256 particles per group over 8 groups, maps 128-512 cells),
+each frame = device obstacle motion + Priori Initialization + up to 50 fused
+iterations with Auto Truncation and online self-evolution, all in one
+captured HIP graph.  Inputs are resident in HBM before timing starts.
+
+Printed: one JSON line with plans/s (value), segment x edge tests/s, the
+roofline of the dominant kernel (the fused iteration, FP32 VALU bound), the
+FP64 oracle timed on host cores, and the paper-shaped single instance.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "plans/sec at oracle-matched cost; seg×edge tests/s vs FP32 VALU peak"
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published (packed FP32)
+F_TEST = 10.0          # algorithmic FLOP per segment x edge test
+
+
+def batch_workload(n_inst, seed_base=0):
+    from paper_2308_10169_amd import inputs as I
+    specs, sws = [], []
+    for i in range(n_inst):
+        m, shape = I.batch_instance(i, seed_base)
+        sws.append(I.dynamic_swarm(m.scale, seed=seed_base, instance=i, **shape))
+        specs.append(m)
+    return specs, sws
+
+
+def oracle_matched(specs, sws, res, sample):
+    """Reported cost of sampled instances equals the oracle's fitness of the
+    returned path (within 1e-5 where the oracle flags no degenerate test)."""
+    from oracle import pyorc as orc
+    ok = True
+    for i in sample:
+        p = res["paths"][i][None, :].astype(np.float64)
+        chk = orc.fitness(orc.Map(specs[i]), p, sws[i].waypoints, sws[i].alpha, sws[i].beta)
+        if chk["n_deg"][0] == 0:
+            ok &= abs(chk["f"][0] - res["cost"][-1, i]) <= 1e-5 * max(chk["f"][0], 1.0)
+    return bool(ok)
+
+
+def cpu_baseline(specs, sws, budget_s):
+    """The FP64 oracle (single thread) planning first frames of batch
+    instances until the time budget is spent."""
+    from oracle import pyorc as orc
+    t0 = time.perf_counter()
+    done, tests = 0, 0.0
+    for i in range(len(specs)):
+        s = orc.Swarm(sws[i], specs[i].width, specs[i].height)
+        r = s.plan_frame(orc.Map(specs[i]), 0)
+        done += 1
+        tests += sws[i].groups * sws[i].particles * (sws[i].waypoints + 1) * specs[i].n_edges * r["iters"]
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="plans/s", cores=1, kind="oracle",
+                sample=f"first frame of batch instances 0..{done - 1} (FP64, one thread), "
+                       f"{dt:.1f} s; {tests / dt:.3g} tests/s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--instances", type=int, default=1024)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: every box here has a single MI355X; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2308_10169_amd import inputs as I
+    from paper_2308_10169_amd import sepso
+
+    sepso.lib()
+    t_gen = time.perf_counter()
+    specs, sws = batch_workload(args.instances)
+    print(f"# generated {args.instances} instances in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    bp = sepso.BatchPlanner(specs, sws)
+    tune = bp.autotune() if not args.no_tune else None
+    tests_iter, elems_iter = bp.work()
+    print(f"# tune {tune}, tests/iteration {tests_iter:.4g}", file=sys.stderr, flush=True)
+
+    # dominant kernel: fused iteration over all instances (HIP events, library stream)
+    bp.profile_step(2)
+    kern_ms = bp.profile_step(10)
+
+    bp.plan(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = bp.plan(args.steps, want_paths=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plans = args.instances * args.steps
+    iters = res["iters"].astype(np.float64)
+    tests_run = 0.0
+    for i in range(args.instances):
+        per = sws[i].groups * sws[i].particles * (sws[i].waypoints + 1) * specs[i].n_edges
+        tests_run += per * iters[:, i].sum()
+    matched = oracle_matched(specs, sws, res, range(0, args.instances, max(1, args.instances // 8)))
+    print(f"# {plans} plans in {dt:.3f}s, mean iters {iters.mean():.1f}", file=sys.stderr, flush=True)
+
+    achieved = F_TEST * tests_iter / (kern_ms * 1e-3)
+    roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                frac=achieved / PEAK_FP32, traffic=None,
+                kernel="step_kernel (fused iteration)", ms_per_launch=kern_ms,
+                tests_per_launch=tests_iter)
+
+    # paper-shaped single instance (366 map, 30 rectangles, 8 x 170, W = 20)
+    spec2 = I.dynamic_map(0)
+    sw2 = I.dynamic_swarm(spec2.scale, seed=0)
+    pl = sepso.Planner(spec2, sw2)
+    for _ in range(3):
+        pl.plan_frame()
+    t1 = time.perf_counter()
+    its = []
+    nf = 100
+    for _ in range(nf):
+        its.append(pl.plan_frame()["iters"])
+    t2 = time.perf_counter() - t1
+    paper = dict(workload="366x366 map, 10 static + 20 moving rectangles, 8 groups x 170 "
+                          "particles, 20 waypoints, AT + PI + online HSEF, 50 iterations max",
+                 plans_per_s=nf / t2, mean_iters=float(np.mean(its)), frames=nf,
+                 paper_context_plans_per_s=67)
+    pl.close()
+
+    out = dict(metric=METRIC, value=plans / dt, unit="plans/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=1e3 * dt / args.steps, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=f"batched frame loop: {args.instances} independent dynamic "
+                                    "instances (W 8-32, 4-100 rectangles, 32-256 particles/group "
+                                    "x 8 groups, maps 128-512), AT + PI + online HSEF, <=50 "
+                                    "iterations/frame, one hipGraph per frame",
+                           instances=args.instances, tune=tune, oracle_matched=matched),
+               tests_per_s=tests_run / dt, tests_per_s_peak_frac=F_TEST * tests_run / dt / PEAK_FP32,
+               roofline=roof, paper_shaped=paper)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(specs, sws, args.cpu_budget)
+    bp.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

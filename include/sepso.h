@@ -1,0 +1,185 @@
+/*
+ * libsepso -- MI355X (gfx950) planner hot path of SEPSO: grouped particle
+ * swarm optimisation in tensor form with a path fitness of polyline length
+ * plus a crossing penalty, its application-phase frame loop, and batched
+ * planning of many independent instances.
+ *
+ * Paper: Xin, Li, Zhang, Li, "Efficient Real-time Path Planning with
+ * Self-evolving Particle Swarm Optimization in Dynamic Scenarios".
+ *
+ * Conventions (all entry points):
+ *  - Every function returns sepso_status; SEPSO_OK is 0.  sepso_last_error()
+ *    returns a thread-local message for the last failure.  No C++ exception
+ *    crosses this boundary.
+ *  - Arguments are validated before any device work: on SEPSO_E_ARG nothing
+ *    has been launched and nothing has changed.
+ *  - A HIP failure (SEPSO_E_HIP) is sticky: the handle refuses further work
+ *    (SEPSO_E_STATE) until it is destroyed.
+ *  - Host input structs and arrays are copied during the call; the caller
+ *    keeps ownership.  Host outputs go to caller-allocated buffers.
+ *  - Device memory is a caller-provided workspace (size from the matching
+ *    *_workspace_bytes call, 256-byte aligned base), which must stay valid
+ *    and untouched until the handle is destroyed.  The library allocates no
+ *    device memory of its own; it allocates a small pinned host buffer per
+ *    handle for results.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*; NULL = the default stream).  Functions documented as
+ *    "asynchronous" return before the device work completes.
+ *  - A handle is single-threaded; distinct handles are independent.
+ *
+ * Particle layout (Eq.(10)): a path of W interior waypoints is the vector
+ * [x_1..x_W, y_1..y_W]; swarm arrays are (G, N, 2W) row-major FP32.
+ */
+#ifndef SEPSO_H
+#define SEPSO_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sepso_status {
+  SEPSO_OK = 0,
+  SEPSO_E_ARG = 1,         /* invalid argument; nothing launched */
+  SEPSO_E_NOMEM = 2,       /* workspace too small or host allocation failed */
+  SEPSO_E_HIP = 3,         /* HIP runtime error (sticky) */
+  SEPSO_E_STATE = 4,       /* handle unusable (earlier HIP error) or wrong call order */
+  SEPSO_E_UNSUPPORTED = 5  /* valid request this build does not support */
+} sepso_status;
+
+const char* sepso_last_error(void);
+const char* sepso_version(void);
+
+/* Polygonal map (Sec. "Map representation"): obstacles are closed polygons
+ * given by their vertices; a path collides where one of its segments
+ * properly crosses a polygon edge.  Map = [0,width] x [0,height]. */
+typedef struct sepso_map {
+  float width, height;
+  int32_t n_polys;           /* >= 0 */
+  const int32_t* poly_ptr;   /* n_polys+1 vertex offsets, poly_ptr[0] = 0, >= 3 vertices each */
+  const float* verts;        /* poly_ptr[n_polys] vertices, (x, y) pairs */
+  float start[2], target[2]; /* path end points, inside the map */
+  const float* poly_vel;     /* n_polys (vx, vy) per frame for the device motion model, or NULL = static */
+  float endpoint_vel[4];     /* start (vx, vy), target (vx, vy) per frame */
+} sepso_map;
+
+/* One planner instance: DTPSO (Algorithm 1) over G groups of N particles
+ * with W waypoints, the fitness of Eq.(11)-(13), and the application-phase
+ * mechanisms (Priori Initialization, Auto Truncation, online HSEF). */
+typedef struct sepso_swarm {
+  int32_t groups, particles, waypoints; /* G >= 1, N >= 1, 1 <= W <= 64 */
+  int32_t max_iters;                    /* T >= 1: inertia schedule length and per-frame cap */
+  const float* hyper;                   /* G x 6: C1, C2, C3, w_init, w_end, V_limit (Table hyper8 layout) */
+  float alpha; int32_t beta;            /* penalty alpha * Q^beta, beta >= 1 (Eq.13) */
+  int32_t use_pi; float pi_gamma, pi_radius; /* Priori Initialization: fraction and half-width */
+  int32_t at_mode, at_window; float at_delta; /* Auto Truncation: 0 off, 1 std over window < delta,
+                                                 2 relative gain over window < delta */
+  int32_t hsef_every;                   /* online self-evolution period in iterations (0 = off) */
+  const float* hsef_hyper;              /* G x 6 hyper of the outer swarm (NULL = Table hyper8 rows) */
+  uint64_t seed;                        /* Philox4x32-10 key */
+  uint32_t instance;                    /* Philox counter word 2 */
+} sepso_swarm;
+
+typedef struct sepso_frame_result {
+  float cost;          /* Tbest fitness F = L + alpha Q^beta */
+  float length;        /* L of the returned path */
+  int32_t crossings;   /* Q of the returned path */
+  int32_t iters;       /* iterations run in this frame */
+  int32_t truncated;   /* Auto Truncation fired */
+  int32_t used_learned;/* reserved: 0 */
+  float device_ms;     /* device time of the frame (0 when batched) */
+} sepso_frame_result;
+
+/* Host views for state inspection / injection (any pointer may be NULL to
+ * skip that array).  Sizes: X, V, P: G*N*2W; f, L, Pf, PL: G*N floats;
+ * Q, PQ: G*N int32; gbest_n: G int32; gbest_f: G floats; hyper: G*6. */
+typedef struct sepso_state {
+  float *X, *V, *P;
+  float *f, *L, *Pf, *PL;
+  int32_t *Q, *PQ;
+  int32_t* gbest_n; float* gbest_f;
+  float* hyper;
+  int32_t tbest_g, tbest_n; float tbest_f;
+  int32_t k;           /* iterations done in the current plan */
+  uint32_t ctr;        /* global iteration counter (random-stream position) */
+  int32_t frame;       /* frames planned so far */
+} sepso_state;
+
+/* Tile configuration of the fused iteration kernel. */
+typedef struct sepso_tune {
+  int32_t seg_per_thread; /* K: path segments per thread, one of 4, 8, 12, 16, 24 */
+  int32_t block_threads;  /* 64, 128, 256 */
+} sepso_tune;
+
+typedef struct sepso_ctx sepso_ctx;
+typedef struct sepso_batch sepso_batch;
+
+/* ---- single instance ---------------------------------------------------- */
+sepso_status sepso_workspace_bytes(const sepso_map* map, const sepso_swarm* swarm, size_t* bytes);
+
+/* Validates and copies the map and swarm, carves the workspace, uploads the
+ * geometry and initialises the swarm uniformly (frame 0).  Asynchronous. */
+sepso_status sepso_create(const sepso_map* map, const sepso_swarm* swarm, void* d_workspace,
+                          size_t workspace_bytes, void* stream, sepso_ctx** out);
+sepso_status sepso_destroy(sepso_ctx* ctx);
+
+/* n iterations of Algorithm 1 (fitness -> Pbest/Gbest/Tbest -> inertia ->
+ * velocity clip -> position clip), no host synchronisation.  Asynchronous. */
+sepso_status sepso_step(sepso_ctx* ctx, int32_t n);
+
+/* One application-phase frame: next map (host copy) or, with next == NULL,
+ * one step of the device motion model for frames after the first; swarm
+ * init with Priori Initialization from the last frame's plan; iterations
+ * with online HSEF until Auto Truncation or max_iters.  Synchronises once;
+ * writes *out and the plan's 2W path values to out_path (may be NULL). */
+sepso_status sepso_plan_frame(sepso_ctx* ctx, const sepso_map* next, sepso_frame_result* out,
+                              float* out_path);
+
+/* Re-initialise the swarm for frame index `frame` (uniform; with
+ * use_prev != 0 and PI enabled, Priori Initialization from the last plan).
+ * Asynchronous. */
+sepso_status sepso_reinit(sepso_ctx* ctx, int32_t frame, int32_t use_prev);
+
+/* Copy the device state out / in.  Synchronous. */
+sepso_status sepso_get_state(sepso_ctx* ctx, sepso_state* st);
+sepso_status sepso_set_state(sepso_ctx* ctx, const sepso_state* st);
+
+/* Current obstacle vertices and endpoints (after device motion): verts gets
+ * 2*n_vert floats, endpoints 4 floats (start, target).  Synchronous. */
+sepso_status sepso_get_geometry(sepso_ctx* ctx, float* verts, float* endpoints);
+
+/* Mean device time of one fused iteration kernel over n back-to-back
+ * launches (HIP events on the handle's stream).  Advances the swarm. */
+sepso_status sepso_profile_step(sepso_ctx* ctx, int32_t n, float* avg_ms);
+
+/* ---- batch of independent instances ------------------------------------ */
+sepso_status sepso_batch_workspace_bytes(const sepso_map* maps, const sepso_swarm* swarms,
+                                         int32_t n_inst, size_t* bytes);
+/* tune may be NULL (defaults).  Asynchronous (geometry upload + init). */
+sepso_status sepso_batch_create(const sepso_map* maps, const sepso_swarm* swarms, int32_t n_inst,
+                                void* d_workspace, size_t workspace_bytes, void* stream,
+                                const sepso_tune* tune, sepso_batch** out);
+sepso_status sepso_batch_destroy(sepso_batch* b);
+/* Offsets of each instance's path in the flat out_paths array (n_inst+1). */
+sepso_status sepso_batch_path_offsets(sepso_batch* b, int64_t* offsets);
+/* n_frames frames of every instance (device motion model between frames),
+ * one captured graph per frame, one synchronisation per frame.  out holds
+ * n_inst * n_frames results (frame-major); out_paths (may be NULL) gets the
+ * last frame's paths. */
+sepso_status sepso_batch_plan(sepso_batch* b, int32_t n_frames, sepso_frame_result* out,
+                              float* out_paths);
+/* State of instance i of a batch (same views as sepso_get_state). */
+sepso_status sepso_batch_get_state(sepso_batch* b, int32_t i, sepso_state* st);
+sepso_status sepso_batch_profile_step(sepso_batch* b, int32_t n, float* avg_ms);
+/* Choose seg_per_thread / block_threads by timing candidates on this batch;
+ * the winner is applied to the batch and written to *best (may be NULL). */
+sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best);
+/* Work counters of one full iteration of every instance: segment x edge
+ * tests and swarm elements (for throughput reporting). */
+sepso_status sepso_batch_work(sepso_batch* b, double* tests_per_iter, double* elems_per_iter);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

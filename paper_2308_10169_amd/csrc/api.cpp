@@ -1,0 +1,867 @@
+// libsepso host side: argument validation, workspace carve-up, the C-ABI
+// entry points, and graph capture of whole planning frames.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sepso.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace sepso;
+
+namespace {
+
+thread_local std::string g_err;
+
+sepso_status fail(sepso_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+// Table hyper8 (DTPSO / H-SEPSO defaults): default outer-swarm hyper.
+const float kHyper8[8][6] = {
+    {2, 1, 1, 0.4f, 0.2f, 0.2f}, {1, 1, 2, 0.7f, 0.3f, 0.1f}, {2, 2, 1, 0.8f, 0.1f, 0.6f},
+    {2, 2, 1, 0.8f, 0.6f, 0.4f}, {2, 1, 2, 0.2f, 0.1f, 0.3f}, {2, 1, 2, 0.9f, 0.5f, 0.5f},
+    {1, 2, 2, 0.4f, 0.1f, 0.8f}, {1, 2, 2, 0.9f, 0.3f, 0.3f}};
+
+bool finite(float x) { return std::isfinite(x); }
+
+sepso_status check_map(const sepso_map* m, int idx) {
+  if (!m) return fail(SEPSO_E_ARG, "map[%d] is NULL", idx);
+  if (!(finite(m->width) && finite(m->height) && m->width > 0.f && m->height > 0.f))
+    return fail(SEPSO_E_ARG, "map[%d]: width/height must be finite and > 0", idx);
+  if (m->n_polys < 0 || m->n_polys > (1 << 20))
+    return fail(SEPSO_E_ARG, "map[%d]: n_polys out of range", idx);
+  for (int e = 0; e < 2; ++e) {
+    const float* p = e ? m->target : m->start;
+    if (!(finite(p[0]) && finite(p[1]) && p[0] >= 0.f && p[0] <= m->width && p[1] >= 0.f &&
+          p[1] <= m->height))
+      return fail(SEPSO_E_ARG, "map[%d]: %s outside the map", idx, e ? "target" : "start");
+  }
+  for (int j = 0; j < 4; ++j)
+    if (!finite(m->endpoint_vel[j])) return fail(SEPSO_E_ARG, "map[%d]: endpoint_vel", idx);
+  if (m->n_polys == 0) return SEPSO_OK;
+  if (!m->poly_ptr || !m->verts) return fail(SEPSO_E_ARG, "map[%d]: poly_ptr/verts NULL", idx);
+  if (m->poly_ptr[0] != 0) return fail(SEPSO_E_ARG, "map[%d]: poly_ptr[0] != 0", idx);
+  for (int q = 0; q < m->n_polys; ++q)
+    if (m->poly_ptr[q + 1] - m->poly_ptr[q] < 3)
+      return fail(SEPSO_E_ARG, "map[%d]: polygon %d has < 3 vertices", idx, q);
+  const int nv = m->poly_ptr[m->n_polys];
+  if (nv > (1 << 22)) return fail(SEPSO_E_ARG, "map[%d]: too many vertices", idx);
+  for (int j = 0; j < nv; ++j) {
+    const float x = m->verts[2 * j], y = m->verts[2 * j + 1];
+    if (!(finite(x) && finite(y) && x >= 0.f && x <= m->width && y >= 0.f && y <= m->height))
+      return fail(SEPSO_E_ARG, "map[%d]: vertex %d outside the map", idx, j);
+  }
+  if (m->poly_vel)
+    for (int q = 0; q < 2 * m->n_polys; ++q)
+      if (!finite(m->poly_vel[q])) return fail(SEPSO_E_ARG, "map[%d]: poly_vel", idx);
+  return SEPSO_OK;
+}
+
+sepso_status check_swarm(const sepso_swarm* s, int idx) {
+  if (!s) return fail(SEPSO_E_ARG, "swarm[%d] is NULL", idx);
+  if (s->groups < 1 || s->groups > kMaxG) return fail(SEPSO_E_ARG, "swarm[%d]: groups in [1,%d]", idx, kMaxG);
+  if (s->particles < 1) return fail(SEPSO_E_ARG, "swarm[%d]: particles >= 1", idx);
+  if (s->waypoints < 1 || s->waypoints > kMaxW)
+    return fail(SEPSO_E_ARG, "swarm[%d]: waypoints in [1,%d]", idx, kMaxW);
+  if (s->max_iters < 1) return fail(SEPSO_E_ARG, "swarm[%d]: max_iters >= 1", idx);
+  const double elems = (double)s->groups * s->particles * 2.0 * s->waypoints;
+  if (elems > 1.0e9) return fail(SEPSO_E_ARG, "swarm[%d]: swarm too large", idx);
+  if (!s->hyper) return fail(SEPSO_E_ARG, "swarm[%d]: hyper is NULL", idx);
+  for (int j = 0; j < 6 * s->groups; ++j)
+    if (!finite(s->hyper[j])) return fail(SEPSO_E_ARG, "swarm[%d]: hyper not finite", idx);
+  for (int g = 0; g < s->groups; ++g)
+    if (s->hyper[6 * g + 5] < 0.f) return fail(SEPSO_E_ARG, "swarm[%d]: V_limit < 0", idx);
+  if (s->hsef_hyper)
+    for (int j = 0; j < 6 * s->groups; ++j)
+      if (!finite(s->hsef_hyper[j])) return fail(SEPSO_E_ARG, "swarm[%d]: hsef_hyper", idx);
+  if (!(finite(s->alpha) && s->alpha >= 0.f)) return fail(SEPSO_E_ARG, "swarm[%d]: alpha", idx);
+  if (s->beta < 1 || s->beta > 16) return fail(SEPSO_E_ARG, "swarm[%d]: beta in [1,16]", idx);
+  if (!(finite(s->pi_gamma) && s->pi_gamma >= 0.f && s->pi_gamma <= 1.f))
+    return fail(SEPSO_E_ARG, "swarm[%d]: pi_gamma in [0,1]", idx);
+  if (!(finite(s->pi_radius) && s->pi_radius >= 0.f))
+    return fail(SEPSO_E_ARG, "swarm[%d]: pi_radius >= 0", idx);
+  if (s->at_mode < 0 || s->at_mode > 2) return fail(SEPSO_E_ARG, "swarm[%d]: at_mode", idx);
+  if (s->at_window < 1 || s->at_window >= kHist)
+    return fail(SEPSO_E_ARG, "swarm[%d]: at_window in [1,%d]", idx, kHist - 1);
+  if (!finite(s->at_delta)) return fail(SEPSO_E_ARG, "swarm[%d]: at_delta", idx);
+  if (s->hsef_every < 0) return fail(SEPSO_E_ARG, "swarm[%d]: hsef_every >= 0", idx);
+  return SEPSO_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace carve-up of a batch (byte offsets of every pool).
+struct Layout {
+  size_t desc, ctl, X, V, P, f, L, Pf, PL, Q, PQ, edges, verts, pptr, pvel, ends, endv, tiles,
+      gbn, gbf, hyper, ohyper, ov, op, opf, gpos, tpos, prev, blkt, blki, total;
+  int64_t sumPD = 0, sumP = 0, sumTilesMax = 0;
+  int64_t sumE = 0, sumPP = 0, sumPoly = 0, sumG = 0, sumGD = 0, sumD = 0, initBlocks = 0;
+};
+
+Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vector<InstDesc>* desc) {
+  Layout L{};
+  if (desc) desc->assign(n, InstDesc{});
+  for (int i = 0; i < n; ++i) {
+    const int G = sw[i].groups, N = sw[i].particles, W = sw[i].waypoints, D = 2 * W;
+    const int64_t P = (int64_t)G * N;
+    if (desc) {
+      InstDesc& d = (*desc)[i];
+      d.G = G;
+      d.N = N;
+      d.W = W;
+      d.T = sw[i].max_iters;
+      d.n_polys = maps[i].n_polys;
+      d.n_edges = maps[i].n_polys ? maps[i].poly_ptr[maps[i].n_polys] : 0;
+      d.width = maps[i].width;
+      d.height = maps[i].height;
+      d.alpha = sw[i].alpha;
+      d.beta = sw[i].beta;
+      d.use_pi = sw[i].use_pi ? 1 : 0;
+      d.n_pi = (int)std::ceil((double)sw[i].pi_gamma * (double)N);
+      d.pi_radius = sw[i].pi_radius;
+      d.at_mode = sw[i].at_mode;
+      d.at_window = sw[i].at_window;
+      d.at_delta = sw[i].at_delta;
+      d.hsef_every = sw[i].hsef_every;
+      d.T_outer = sw[i].hsef_every > 0 ? (sw[i].max_iters + sw[i].hsef_every - 1) / sw[i].hsef_every : 1;
+      d.seed_lo = (uint32_t)(sw[i].seed & 0xffffffffu);
+      d.seed_hi = (uint32_t)(sw[i].seed >> 32);
+      d.instance = sw[i].instance;
+      d.xo = L.sumPD;
+      d.po = L.sumP;
+      d.eo = (int32_t)L.sumE;
+      d.plo = (int32_t)L.sumPP;
+      d.pvo = (int32_t)L.sumPoly;
+      d.to = (int32_t)L.sumTilesMax;
+      d.go = (int32_t)L.sumG;
+      d.gpo = (int32_t)L.sumGD;
+      d.dpo = (int32_t)L.sumD;
+    }
+    L.sumPD += P * D;
+    L.sumP += P;
+    L.sumTilesMax += P;  // at most one tile per particle
+    L.sumE += maps[i].n_polys ? maps[i].poly_ptr[maps[i].n_polys] : 0;
+    L.sumPP += maps[i].n_polys + 1;
+    L.sumPoly += maps[i].n_polys;
+    L.sumG += G;
+    L.sumGD += (int64_t)G * D;
+    L.sumD += D;
+    L.initBlocks += (P * D + 255) / 256;
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + std::max<size_t>(bytes, 4));
+    return at;
+  };
+  L.desc = take(sizeof(InstDesc) * n);
+  L.ctl = take(sizeof(InstCtl) * n);
+  L.X = take(4 * L.sumPD);
+  L.V = take(4 * L.sumPD);
+  L.P = take(4 * L.sumPD);
+  L.f = take(4 * L.sumP);
+  L.L = take(4 * L.sumP);
+  L.Pf = take(4 * L.sumP);
+  L.PL = take(4 * L.sumP);
+  L.Q = take(4 * L.sumP);
+  L.PQ = take(4 * L.sumP);
+  L.edges = take(sizeof(EdgeRec) * L.sumE);
+  L.verts = take(8 * L.sumE);
+  L.pptr = take(4 * L.sumPP);
+  L.pvel = take(8 * L.sumPoly);
+  L.ends = take(16 * n);
+  L.endv = take(16 * n);
+  L.tiles = take(sizeof(TileBest) * L.sumTilesMax);
+  L.gbn = take(4 * L.sumG);
+  L.gbf = take(4 * L.sumG);
+  L.hyper = take(24 * L.sumG);
+  L.ohyper = take(24 * L.sumG);
+  L.ov = take(12 * L.sumG);
+  L.op = take(12 * L.sumG);
+  L.opf = take(4 * L.sumG);
+  L.gpos = take(4 * L.sumGD);
+  L.tpos = take(4 * L.sumD);
+  L.prev = take(4 * L.sumD);
+  L.blkt = take(8 * L.sumTilesMax);
+  L.blki = take(8 * L.initBlocks);
+  L.total = o;
+  return L;
+}
+
+int default_K(int W) {
+  // fewest threads per particle without much idle segment work
+  if (W + 1 <= 12) return 12;
+  if (W + 1 <= 16) return 16;
+  if (W + 1 <= 24) return 24;
+  return 16;
+}
+
+}  // namespace
+
+struct sepso_batch {
+  int n = 0;
+  std::vector<InstDesc> desc;
+  std::vector<int> n_vert;
+  std::vector<int32_t> h_pptr;  // polygon offsets of instance 0
+  std::vector<int64_t> path_off;
+  Layout lay{};
+  Pools pl{};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool broken = false;
+  sepso_tune tune{16, 256};
+  int tile_blocks = 0;
+  int frames_done = 0;
+  // pinned host mirrors
+  InstCtl* h_ctl = nullptr;
+  float* h_paths = nullptr;
+  float* h_stage = nullptr;  // geometry staging for host-provided maps
+  size_t stage_floats = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] no motion, [1] motion step first
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct sepso_ctx {
+  sepso_batch* b;
+};
+
+namespace {
+
+sepso_status hip_fail(sepso_batch* b, hipError_t e, const char* what) {
+  if (b) b->broken = true;
+  return fail(SEPSO_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(b, expr)                                  \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return hip_fail(b, _e, #expr); \
+  } while (0)
+
+#define LAUNCHCHK(b, what)                             \
+  do {                                                 \
+    hipError_t _e = hipGetLastError();                 \
+    if (_e != hipSuccess) return hip_fail(b, _e, what); \
+  } while (0)
+
+// Tile geometry for the current tune; fills desc tile fields and the
+// block -> (instance, tile) table.
+void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
+  const int K = b->tune.seg_per_thread, B = b->tune.block_threads;
+  blk->clear();
+  std::vector<std::pair<double, int>> order;
+  for (int i = 0; i < b->n; ++i) {
+    InstDesc& d = b->desc[i];
+    d.C = (d.W + 1 + K - 1) / K;
+    d.ppt = std::max(1, B / d.C);
+    d.tpg = (d.N + d.ppt - 1) / d.ppt;
+    d.n_tiles = d.G * d.tpg;
+    order.push_back({(double)d.n_edges * d.C, i});
+  }
+  // heavy tiles first: the dispatcher hands blocks out in order
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<double, int>& a, const std::pair<double, int>& c) { return a.first > c.first; });
+  for (auto& o : order)
+    for (int t = 0; t < b->desc[o.second].n_tiles; ++t) blk->push_back(make_int2(o.second, t));
+  b->tile_blocks = (int)blk->size();
+}
+
+sepso_status upload_tiles(sepso_batch* b) {
+  std::vector<int2> blk;
+  plan_tiles(b, &blk);
+  HIPCHK(b, hipMemcpyAsync(b->ws + b->lay.desc, b->desc.data(), sizeof(InstDesc) * b->n,
+                           hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipMemcpyAsync(b->ws + b->lay.blkt, blk.data(), sizeof(int2) * blk.size(),
+                           hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  for (int m = 0; m < 2; ++m)
+    if (b->graph[m]) {
+      hipGraphExecDestroy(b->graph[m]);
+      b->graph[m] = nullptr;
+    }
+  return SEPSO_OK;
+}
+
+void destroy_batch(sepso_batch* b) {
+  if (!b) return;
+  for (int m = 0; m < 2; ++m)
+    if (b->graph[m]) hipGraphExecDestroy(b->graph[m]);
+  if (b->ev0) hipEventDestroy(b->ev0);
+  if (b->ev1) hipEventDestroy(b->ev1);
+  if (b->h_ctl) hipHostFree(b->h_ctl);
+  if (b->h_paths) hipHostFree(b->h_paths);
+  if (b->h_stage) hipHostFree(b->h_stage);
+  if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+  delete b;
+}
+
+template <class T>
+T* at(sepso_batch* b, size_t off) {
+  return reinterpret_cast<T*>(b->ws + off);
+}
+
+sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, void* d_ws,
+                          size_t ws_bytes, void* stream, const sepso_tune* tune, sepso_batch** out) {
+  if (!out) return fail(SEPSO_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1) return fail(SEPSO_E_ARG, "n_inst must be >= 1");
+  if (!maps || !sw) return fail(SEPSO_E_ARG, "maps/swarms NULL");
+  for (int i = 0; i < n; ++i) {
+    sepso_status st = check_map(&maps[i], i);
+    if (st != SEPSO_OK) return st;
+    st = check_swarm(&sw[i], i);
+    if (st != SEPSO_OK) return st;
+  }
+  sepso_tune tn{0, 256};
+  if (tune) {
+    tn = *tune;
+    if (!step_supported(tn.seg_per_thread))
+      return fail(SEPSO_E_ARG, "seg_per_thread must be one of 4, 8, 12, 16, 24");
+    if (tn.block_threads != 64 && tn.block_threads != 128 && tn.block_threads != 256)
+      return fail(SEPSO_E_ARG, "block_threads must be 64, 128 or 256");
+  } else {
+    int wmax = 0;
+    for (int i = 0; i < n; ++i) wmax = std::max(wmax, sw[i].waypoints);
+    tn.seg_per_thread = default_K(wmax);
+  }
+  for (int i = 0; i < n; ++i) {
+    const int C = (sw[i].waypoints + tn.seg_per_thread) / tn.seg_per_thread;
+    if (C > tn.block_threads) return fail(SEPSO_E_ARG, "instance %d: path too long for the tile", i);
+  }
+  if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(SEPSO_E_ARG, "workspace not 256-byte aligned");
+  sepso_batch* b = new (std::nothrow) sepso_batch();
+  if (!b) return fail(SEPSO_E_NOMEM, "host allocation failed");
+  b->n = n;
+  b->tune = tn;
+  b->lay = plan_layout(maps, sw, n, &b->desc);
+  if (ws_bytes < b->lay.total) {
+    const size_t need = b->lay.total;
+    delete b;
+    return fail(SEPSO_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  }
+  b->ws = static_cast<char*>(d_ws);
+  if (stream) {
+    b->stream = static_cast<hipStream_t>(stream);
+  } else {
+    // graph capture needs a non-legacy stream; default priority
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete b;
+      return fail(SEPSO_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    b->own_stream = true;
+  }
+  const Layout& L = b->lay;
+  Pools& pl = b->pl;
+  pl.desc = at<InstDesc>(b, L.desc);
+  pl.ctl = at<InstCtl>(b, L.ctl);
+  pl.X = at<float>(b, L.X);
+  pl.V = at<float>(b, L.V);
+  pl.P = at<float>(b, L.P);
+  pl.f = at<float>(b, L.f);
+  pl.L = at<float>(b, L.L);
+  pl.Pf = at<float>(b, L.Pf);
+  pl.PL = at<float>(b, L.PL);
+  pl.Q = at<int32_t>(b, L.Q);
+  pl.PQ = at<int32_t>(b, L.PQ);
+  pl.edges = at<EdgeRec>(b, L.edges);
+  pl.verts = at<float2>(b, L.verts);
+  pl.poly_ptr = at<int32_t>(b, L.pptr);
+  pl.poly_vel = at<float2>(b, L.pvel);
+  pl.ends = at<float4>(b, L.ends);
+  pl.end_vel = at<float4>(b, L.endv);
+  pl.tiles = at<TileBest>(b, L.tiles);
+  pl.gbest_n = at<int32_t>(b, L.gbn);
+  pl.gbest_f = at<float>(b, L.gbf);
+  pl.hyper = at<float>(b, L.hyper);
+  pl.outer_hyper = at<float>(b, L.ohyper);
+  pl.ov = at<float>(b, L.ov);
+  pl.op = at<float>(b, L.op);
+  pl.opf = at<float>(b, L.opf);
+  pl.gbest_pos = at<float>(b, L.gpos);
+  pl.tbest_pos = at<float>(b, L.tpos);
+  pl.prev_path = at<float>(b, L.prev);
+  pl.blk_tiles = at<int2>(b, L.blkt);
+  pl.blk_init = at<int2>(b, L.blki);
+
+  // host-side images of the static pools
+  std::vector<float> verts(2 * L.sumE), pvel(2 * L.sumPoly, 0.f), ends(4 * n), endv(4 * n);
+  std::vector<float> hyper(6 * L.sumG), ohyper(6 * L.sumG);
+  std::vector<int32_t> pptr(L.sumPP);
+  std::vector<int2> blki;
+  b->n_vert.resize(n);
+  b->path_off.resize(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const InstDesc& d = b->desc[i];
+    const sepso_map& m = maps[i];
+    b->n_vert[i] = d.n_edges;
+    for (int j = 0; j < 2 * d.n_edges; ++j) verts[2 * d.eo + j] = m.verts[j];
+    for (int q = 0; q <= d.n_polys; ++q) pptr[d.plo + q] = d.n_polys ? m.poly_ptr[q] : 0;
+    if (m.poly_vel)
+      for (int q = 0; q < 2 * d.n_polys; ++q) pvel[2 * d.pvo + q] = m.poly_vel[q];
+    ends[4 * i + 0] = m.start[0];
+    ends[4 * i + 1] = m.start[1];
+    ends[4 * i + 2] = m.target[0];
+    ends[4 * i + 3] = m.target[1];
+    for (int j = 0; j < 4; ++j) endv[4 * i + j] = m.endpoint_vel[j];
+    for (int j = 0; j < 6 * d.G; ++j) {
+      hyper[6 * d.go + j] = sw[i].hyper[j];
+      ohyper[6 * d.go + j] = sw[i].hsef_hyper ? sw[i].hsef_hyper[j] : kHyper8[(j / 6) % 8][j % 6];
+    }
+    const int64_t PD = (int64_t)d.G * d.N * 2 * d.W;
+    for (int64_t e = 0; e < PD; e += 256) blki.push_back(make_int2(i, (int)e));
+    b->path_off[i + 1] = b->path_off[i] + 2 * d.W;
+  }
+  b->h_pptr.assign(pptr.begin(), pptr.begin() + b->desc[0].n_polys + 1);
+  std::vector<InstCtl> ctl(n);
+  std::memset(ctl.data(), 0, sizeof(InstCtl) * n);
+  for (int i = 0; i < n; ++i) ctl[i].tb_f = INFINITY;
+
+  auto h2d = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(b->ws + off, src, bytes, hipMemcpyHostToDevice, b->stream);
+  };
+  hipError_t e = hipSuccess;
+  const hipError_t errs[] = {
+      h2d(L.ctl, ctl.data(), sizeof(InstCtl) * n),
+      h2d(L.verts, verts.data(), 4 * verts.size()),
+      h2d(L.pptr, pptr.data(), 4 * pptr.size()),
+      h2d(L.pvel, pvel.data(), 4 * pvel.size()),
+      h2d(L.ends, ends.data(), 4 * ends.size()),
+      h2d(L.endv, endv.data(), 4 * endv.size()),
+      h2d(L.hyper, hyper.data(), 4 * hyper.size()),
+      h2d(L.ohyper, ohyper.data(), 4 * ohyper.size()),
+      h2d(L.blki, blki.data(), sizeof(int2) * blki.size())};
+  for (hipError_t x : errs)
+    if (x != hipSuccess) e = x;
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_ctl, sizeof(InstCtl) * n, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&b->h_paths, sizeof(float) * std::max<int64_t>(1, b->path_off[n]), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e != hipSuccess) {
+    sepso_status st = fail(SEPSO_E_HIP, "create: %s", hipGetErrorString(e));
+    destroy_batch(b);
+    return st;
+  }
+  sepso_status st = upload_tiles(b);
+  if (st != SEPSO_OK) {
+    destroy_batch(b);
+    return st;
+  }
+  launch_geom(pl, n, 0, b->stream);
+  launch_init(pl, (int)blki.size(), 0, 0, b->stream);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    st = fail(SEPSO_E_HIP, "create launch: %s", hipGetErrorString(e));
+    destroy_batch(b);
+    return st;
+  }
+  *out = b;
+  return SEPSO_OK;
+}
+
+sepso_status usable(sepso_batch* b) {
+  if (!b) return fail(SEPSO_E_ARG, "handle is NULL");
+  if (b->broken) return fail(SEPSO_E_STATE, "handle is unusable after an earlier HIP error");
+  return SEPSO_OK;
+}
+
+int init_blocks(sepso_batch* b) { return (int)b->lay.initBlocks; }
+
+// Enqueue one whole frame of every instance.
+void enqueue_frame(sepso_batch* b, bool move) {
+  if (move) launch_geom(b->pl, b->n, 1, b->stream);
+  launch_init(b->pl, init_blocks(b), -1, 1, b->stream);
+  int tmax = 0;
+  for (auto& d : b->desc) tmax = std::max(tmax, d.T);
+  for (int k = 0; k < tmax; ++k)
+    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
+                STEP_FIT | STEP_FRAME, b->stream);
+  hipMemcpyAsync(b->h_ctl, b->pl.ctl, sizeof(InstCtl) * b->n, hipMemcpyDeviceToHost, b->stream);
+  hipMemcpyAsync(b->h_paths, b->pl.prev_path, sizeof(float) * b->path_off[b->n],
+                 hipMemcpyDeviceToHost, b->stream);
+}
+
+sepso_status run_frame(sepso_batch* b, bool move, float* ms) {
+  const int m = move ? 1 : 0;
+  if (!b->graph[m]) {
+    hipGraph_t g = nullptr;
+    HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_frame(b, move);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->graph[m], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(b, e, "hipGraphInstantiate");
+  }
+  HIPCHK(b, hipEventRecord(b->ev0, b->stream));
+  HIPCHK(b, hipGraphLaunch(b->graph[m], b->stream));
+  HIPCHK(b, hipEventRecord(b->ev1, b->stream));
+  HIPCHK(b, hipEventSynchronize(b->ev1));
+  if (ms) HIPCHK(b, hipEventElapsedTime(ms, b->ev0, b->ev1));
+  b->frames_done += 1;
+  return SEPSO_OK;
+}
+
+void fill_result(const InstCtl& c, float ms, sepso_frame_result* r) {
+  r->cost = c.res_cost;
+  r->length = c.res_len;
+  r->crossings = c.res_q;
+  r->iters = c.res_iters;
+  r->truncated = c.res_trunc;
+  r->used_learned = 0;
+  r->device_ms = ms;
+}
+
+sepso_status get_state_inst(sepso_batch* b, int i, sepso_state* st) {
+  const InstDesc& d = b->desc[i];
+  const size_t PD = (size_t)d.G * d.N * 2 * d.W, P = (size_t)d.G * d.N;
+  auto d2h = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!dst || !bytes) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, b->stream);
+  };
+  HIPCHK(b, d2h(st->X, b->pl.X + d.xo, 4 * PD));
+  HIPCHK(b, d2h(st->V, b->pl.V + d.xo, 4 * PD));
+  HIPCHK(b, d2h(st->P, b->pl.P + d.xo, 4 * PD));
+  HIPCHK(b, d2h(st->f, b->pl.f + d.po, 4 * P));
+  HIPCHK(b, d2h(st->L, b->pl.L + d.po, 4 * P));
+  HIPCHK(b, d2h(st->Pf, b->pl.Pf + d.po, 4 * P));
+  HIPCHK(b, d2h(st->PL, b->pl.PL + d.po, 4 * P));
+  HIPCHK(b, d2h(st->Q, b->pl.Q + d.po, 4 * P));
+  HIPCHK(b, d2h(st->PQ, b->pl.PQ + d.po, 4 * P));
+  HIPCHK(b, d2h(st->gbest_n, b->pl.gbest_n + d.go, 4 * d.G));
+  HIPCHK(b, d2h(st->gbest_f, b->pl.gbest_f + d.go, 4 * d.G));
+  HIPCHK(b, d2h(st->hyper, b->pl.hyper + 6 * d.go, 24 * d.G));
+  HIPCHK(b, d2h(b->h_ctl + i, b->pl.ctl + i, sizeof(InstCtl)));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  const InstCtl& c = b->h_ctl[i];
+  st->tbest_g = c.tb_g;
+  st->tbest_n = c.tb_n;
+  st->tbest_f = c.tb_f;
+  st->k = c.k;
+  st->ctr = c.ctr;
+  st->frame = c.frame;
+  return SEPSO_OK;
+}
+
+}  // namespace
+
+// ============================== C ABI =======================================
+extern "C" {
+
+const char* sepso_last_error(void) { return g_err.c_str(); }
+const char* sepso_version(void) { return "libsepso 0.1 (gfx950)"; }
+
+sepso_status sepso_batch_workspace_bytes(const sepso_map* maps, const sepso_swarm* swarms,
+                                         int32_t n_inst, size_t* bytes) {
+  if (!bytes) return fail(SEPSO_E_ARG, "bytes is NULL");
+  if (n_inst < 1 || !maps || !swarms) return fail(SEPSO_E_ARG, "need n_inst >= 1 maps and swarms");
+  for (int i = 0; i < n_inst; ++i) {
+    sepso_status st = check_map(&maps[i], i);
+    if (st != SEPSO_OK) return st;
+    st = check_swarm(&swarms[i], i);
+    if (st != SEPSO_OK) return st;
+  }
+  *bytes = plan_layout(maps, swarms, n_inst, nullptr).total;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_workspace_bytes(const sepso_map* map, const sepso_swarm* swarm, size_t* bytes) {
+  return sepso_batch_workspace_bytes(map, swarm, 1, bytes);
+}
+
+sepso_status sepso_batch_create(const sepso_map* maps, const sepso_swarm* swarms, int32_t n_inst,
+                                void* d_ws, size_t ws_bytes, void* stream, const sepso_tune* tune,
+                                sepso_batch** out) {
+  return create_batch(maps, swarms, n_inst, d_ws, ws_bytes, stream, tune, out);
+}
+
+sepso_status sepso_create(const sepso_map* map, const sepso_swarm* swarm, void* d_ws,
+                          size_t ws_bytes, void* stream, sepso_ctx** out) {
+  if (!out) return fail(SEPSO_E_ARG, "out is NULL");
+  *out = nullptr;
+  sepso_batch* b = nullptr;
+  sepso_status st = create_batch(map, swarm, 1, d_ws, ws_bytes, stream, nullptr, &b);
+  if (st != SEPSO_OK) return st;
+  sepso_ctx* c = new (std::nothrow) sepso_ctx{b};
+  if (!c) {
+    destroy_batch(b);
+    return fail(SEPSO_E_NOMEM, "host allocation failed");
+  }
+  *out = c;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_destroy(sepso_ctx* ctx) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  destroy_batch(ctx->b);
+  delete ctx;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_batch_destroy(sepso_batch* b) {
+  if (!b) return fail(SEPSO_E_ARG, "batch is NULL");
+  destroy_batch(b);
+  return SEPSO_OK;
+}
+
+static sepso_status step_batch(sepso_batch* b, int32_t n) {
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
+  for (int k = 0; k < n; ++k)
+    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
+                b->stream);
+  if (n > 0)
+    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0, b->stream);
+  LAUNCHCHK(b, "step launch");
+  return SEPSO_OK;
+}
+
+sepso_status sepso_step(sepso_ctx* ctx, int32_t n) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  return step_batch(ctx->b, n);
+}
+
+sepso_status sepso_reinit(sepso_ctx* ctx, int32_t frame, int32_t use_prev) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (frame < 0) return fail(SEPSO_E_ARG, "frame must be >= 0");
+  launch_init(b->pl, init_blocks(b), frame, use_prev ? 1 : 0, b->stream);
+  LAUNCHCHK(b, "init launch");
+  return SEPSO_OK;
+}
+
+sepso_status sepso_plan_frame(sepso_ctx* ctx, const sepso_map* next, sepso_frame_result* out,
+                              float* out_path) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (!out) return fail(SEPSO_E_ARG, "out is NULL");
+  const InstDesc& d = b->desc[0];
+  bool move = b->frames_done > 0;
+  if (next) {
+    st = check_map(next, 0);
+    if (st != SEPSO_OK) return st;
+    if (next->n_polys != d.n_polys)
+      return fail(SEPSO_E_ARG, "next map must keep the polygon structure (n_polys)");
+    for (int q = 0; q <= d.n_polys && d.n_polys; ++q)
+      if (next->poly_ptr[q] != b->h_pptr[q]) return fail(SEPSO_E_ARG, "next map: poly_ptr differs");
+    std::vector<float> e4 = {next->start[0], next->start[1], next->target[0], next->target[1]};
+    HIPCHK(b, hipMemcpyAsync(b->pl.verts + d.eo, next->verts, 8 * (size_t)d.n_edges,
+                             hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipMemcpyAsync(b->pl.ends, e4.data(), 16, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    launch_geom(b->pl, 1, 0, b->stream);
+    LAUNCHCHK(b, "geometry launch");
+    move = false;
+  }
+  float ms = 0.f;
+  st = run_frame(b, move, &ms);
+  if (st != SEPSO_OK) return st;
+  fill_result(b->h_ctl[0], ms, out);
+  if (out_path) std::memcpy(out_path, b->h_paths, sizeof(float) * 2 * d.W);
+  return SEPSO_OK;
+}
+
+sepso_status sepso_get_state(sepso_ctx* ctx, sepso_state* st) {
+  if (!ctx || !st) return fail(SEPSO_E_ARG, "ctx/state is NULL");
+  sepso_status s = usable(ctx->b);
+  if (s != SEPSO_OK) return s;
+  return get_state_inst(ctx->b, 0, st);
+}
+
+sepso_status sepso_batch_get_state(sepso_batch* b, int32_t i, sepso_state* st) {
+  sepso_status s = usable(b);
+  if (s != SEPSO_OK) return s;
+  if (!st || i < 0 || i >= b->n) return fail(SEPSO_E_ARG, "bad instance index or state");
+  return get_state_inst(b, i, st);
+}
+
+sepso_status sepso_set_state(sepso_ctx* ctx, const sepso_state* st) {
+  if (!ctx || !st) return fail(SEPSO_E_ARG, "ctx/state is NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status s = usable(b);
+  if (s != SEPSO_OK) return s;
+  const InstDesc& d = b->desc[0];
+  const size_t PD = (size_t)d.G * d.N * 2 * d.W, P = (size_t)d.G * d.N;
+  if (st->tbest_g < 0 || st->tbest_g >= d.G || st->tbest_n < 0 || st->tbest_n >= d.N || st->k < 0)
+    return fail(SEPSO_E_ARG, "set_state: scalar fields out of range");
+  if (st->X)
+    for (size_t j = 0; j < PD; ++j) {
+      const float lim = (j % (2 * d.W)) < (size_t)d.W ? d.width : d.height;
+      if (!(st->X[j] >= 0.f && st->X[j] <= lim))
+        return fail(SEPSO_E_ARG, "set_state: X[%zu] outside the map", j);
+    }
+  if (st->hyper)
+    for (int j = 0; j < 6 * d.G; ++j)
+      if (!finite(st->hyper[j])) return fail(SEPSO_E_ARG, "set_state: hyper");
+  auto h2d = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!src || !bytes) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream);
+  };
+  HIPCHK(b, h2d(b->pl.X + d.xo, st->X, 4 * PD));
+  HIPCHK(b, h2d(b->pl.V + d.xo, st->V, 4 * PD));
+  HIPCHK(b, h2d(b->pl.P + d.xo, st->P, 4 * PD));
+  HIPCHK(b, h2d(b->pl.f + d.po, st->f, 4 * P));
+  HIPCHK(b, h2d(b->pl.L + d.po, st->L, 4 * P));
+  HIPCHK(b, h2d(b->pl.Pf + d.po, st->Pf, 4 * P));
+  HIPCHK(b, h2d(b->pl.PL + d.po, st->PL, 4 * P));
+  HIPCHK(b, h2d(b->pl.Q + d.po, st->Q, 4 * P));
+  HIPCHK(b, h2d(b->pl.PQ + d.po, st->PQ, 4 * P));
+  HIPCHK(b, h2d(b->pl.gbest_n + d.go, st->gbest_n, 4 * d.G));
+  HIPCHK(b, h2d(b->pl.gbest_f + d.go, st->gbest_f, 4 * d.G));
+  HIPCHK(b, h2d(b->pl.hyper + 6 * d.go, st->hyper, 24 * d.G));
+  HIPCHK(b, hipMemcpyAsync(b->h_ctl, b->pl.ctl, sizeof(InstCtl), hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  InstCtl c = b->h_ctl[0];
+  c.k = st->k;
+  c.ctr = st->ctr;
+  c.frame = st->frame;
+  c.tb_g = st->tbest_g;
+  c.tb_n = st->tbest_n;
+  c.tb_f = st->tbest_f;
+  c.pending = 0;
+  c.done = 0;
+  c.arrive = 0;
+  b->h_ctl[0] = c;
+  HIPCHK(b, hipMemcpyAsync(b->pl.ctl, b->h_ctl, sizeof(InstCtl), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
+sepso_status sepso_get_geometry(sepso_ctx* ctx, float* verts, float* endpoints) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status s = usable(b);
+  if (s != SEPSO_OK) return s;
+  const InstDesc& d = b->desc[0];
+  if (verts && d.n_edges)
+    HIPCHK(b, hipMemcpyAsync(verts, b->pl.verts + d.eo, 8 * (size_t)d.n_edges, hipMemcpyDeviceToHost, b->stream));
+  if (endpoints)
+    HIPCHK(b, hipMemcpyAsync(endpoints, b->pl.ends, 16, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
+static sepso_status profile_batch(sepso_batch* b, int32_t n, float* avg_ms) {
+  sepso_status s = usable(b);
+  if (s != SEPSO_OK) return s;
+  if (n < 1 || !avg_ms) return fail(SEPSO_E_ARG, "n >= 1 and avg_ms required");
+  HIPCHK(b, hipEventRecord(b->ev0, b->stream));
+  for (int k = 0; k < n; ++k)
+    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
+                b->stream);
+  HIPCHK(b, hipEventRecord(b->ev1, b->stream));
+  LAUNCHCHK(b, "step launch");
+  launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0, b->stream);
+  HIPCHK(b, hipEventSynchronize(b->ev1));
+  float ms = 0.f;
+  HIPCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  *avg_ms = ms / (float)n;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_profile_step(sepso_ctx* ctx, int32_t n, float* avg_ms) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  return profile_batch(ctx->b, n, avg_ms);
+}
+
+sepso_status sepso_batch_profile_step(sepso_batch* b, int32_t n, float* avg_ms) {
+  return profile_batch(b, n, avg_ms);
+}
+
+sepso_status sepso_batch_path_offsets(sepso_batch* b, int64_t* offsets) {
+  if (!b || !offsets) return fail(SEPSO_E_ARG, "batch/offsets NULL");
+  std::memcpy(offsets, b->path_off.data(), sizeof(int64_t) * (b->n + 1));
+  return SEPSO_OK;
+}
+
+sepso_status sepso_batch_plan(sepso_batch* b, int32_t n_frames, sepso_frame_result* out,
+                              float* out_paths) {
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (n_frames < 1 || !out) return fail(SEPSO_E_ARG, "n_frames >= 1 and out required");
+  for (int f = 0; f < n_frames; ++f) {
+    float ms = 0.f;
+    st = run_frame(b, b->frames_done > 0, &ms);
+    if (st != SEPSO_OK) return st;
+    for (int i = 0; i < b->n; ++i) fill_result(b->h_ctl[i], 0.f, &out[(size_t)f * b->n + i]);
+  }
+  if (out_paths) std::memcpy(out_paths, b->h_paths, sizeof(float) * b->path_off[b->n]);
+  return SEPSO_OK;
+}
+
+sepso_status sepso_batch_work(sepso_batch* b, double* tests, double* elems) {
+  if (!b) return fail(SEPSO_E_ARG, "batch is NULL");
+  double t = 0, e = 0;
+  for (auto& d : b->desc) {
+    t += (double)d.G * d.N * (d.W + 1) * d.n_edges;
+    e += (double)d.G * d.N * 2 * d.W;
+  }
+  if (tests) *tests = t;
+  if (elems) *elems = e;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  const int Ks[] = {8, 12, 16, 24};
+  const int Bs[] = {64, 128, 256};
+  sepso_tune win = b->tune;
+  float win_ms = INFINITY;
+  for (int K : Ks)
+    for (int B : Bs) {
+      bool ok = true;
+      for (auto& d : b->desc)
+        if ((d.W + K) / K > B) ok = false;
+      if (!ok) continue;
+      b->tune = sepso_tune{K, B};
+      st = upload_tiles(b);
+      if (st != SEPSO_OK) return st;
+      float ms = 0.f;
+      st = profile_batch(b, 1, &ms);  // warm-up
+      if (st != SEPSO_OK) return st;
+      st = profile_batch(b, 3, &ms);
+      if (st != SEPSO_OK) return st;
+      if (ms < win_ms) {
+        win_ms = ms;
+        win = b->tune;
+      }
+    }
+  b->tune = win;
+  st = upload_tiles(b);
+  if (st != SEPSO_OK) return st;
+  launch_init(b->pl, init_blocks(b), 0, 0, b->stream);
+  LAUNCHCHK(b, "init launch");
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  b->frames_done = 0;
+  if (best) *best = win;
+  return SEPSO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Shared host/device definitions of libsepso: per-instance descriptors,
+// mutable control blocks and the obstacle-edge record.  Everything lives in
+// the caller's workspace; see layout.cpp for the carve-up.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sepso {
+
+constexpr int kMaxW = 64;        // interior waypoints per path
+constexpr int kMaxG = 64;        // groups per instance
+constexpr int kHist = 64;        // Auto-Truncation history ring
+constexpr int kEdgeChunk = 512;  // obstacle edges staged in LDS per pass
+
+// Philox counter tags: which random stream a draw belongs to.
+enum Tag : uint32_t { TAG_UPDATE = 0, TAG_INIT_X = 1, TAG_INIT_V = 2, TAG_PI = 3, TAG_HSEF = 4 };
+
+// Edge flags.
+enum : int32_t { EDGE_FIRST = 1, EDGE_LAST = 2 };
+
+// One polygon edge a -> b, stored so that the fitness kernel can (i) test
+// which side of every path segment the end vertex b lies on and (ii) test
+// which side of the edge's line every path point lies on:
+//   side(p) = sign(ex * p.y - ey * p.x - (ex * a.y - ey * a.x)).
+// The first edge of a polygon also carries its start vertex a (= v0), whose
+// side is reused by the polygon's closing edge.
+struct EdgeRec {
+  float bx, by;     // end vertex
+  float ex, ney;    // b - a  (ney = -(b.y - a.y))
+  float nce;        // -(ex * a.y - ey * a.x)
+  float ax, ay;     // start vertex (meaningful on the first edge of a polygon)
+  int32_t flags;    // EDGE_FIRST / EDGE_LAST
+};
+static_assert(sizeof(EdgeRec) == 32, "EdgeRec is 32 bytes");
+
+// Read-only description of one instance (sizes, constants, pool offsets).
+struct InstDesc {
+  int32_t G, N, W, T;
+  int32_t n_edges, n_polys;
+  int32_t C;             // chunks (threads) per particle = ceil((W+1)/K)
+  int32_t ppt;           // particles per tile
+  int32_t tpg;           // tiles per group
+  int32_t n_tiles;       // G * tpg
+  float width, height;
+  float alpha; int32_t beta;
+  int32_t use_pi, n_pi;  // PI on, particles per group that get it
+  float pi_radius;
+  int32_t at_mode, at_window; float at_delta;
+  int32_t hsef_every, T_outer;
+  uint32_t seed_lo, seed_hi, instance;
+  int64_t xo;            // X, V, P pools: G*N*2W floats
+  int64_t po;            // per-particle pools: G*N
+  int32_t eo;            // edge records (n_edges) and vertices (n_edges float2)
+  int32_t plo;           // poly_ptr pool (n_polys+1)
+  int32_t pvo;           // poly_vel pool (n_polys float2)
+  int32_t to;            // tile partials (n_tiles)
+  int32_t go;            // group pools: G (gbest_n/f, outer Pbest fitness), G*6 hyper, G*3 outer
+  int32_t gpo;           // gbest positions: G*2W
+  int32_t dpo;           // per-instance path pools (Tbest, previous plan): 2W
+};
+
+// Mutable per-instance control block (device resident).
+struct InstCtl {
+  int32_t k;             // iterations with bests done in the current plan
+  int32_t pending;       // iteration k's velocity/position update not applied yet
+  int32_t done;          // the current frame has ended
+  int32_t frame;         // frames planned so far (random stream position for inits)
+  uint32_t ctr;          // counter of iteration k's update draws
+  uint32_t epoch_ctr;    // outer-swarm steps taken (random stream position)
+  int32_t tb_g, tb_n;    // total best
+  float tb_f;
+  int32_t arrive;        // blocks finished in the current launch
+  int32_t epoch_in_frame, otb;
+  int32_t truncated;
+  int32_t have_prev;     // a previous plan exists (PI allowed)
+  float res_cost, res_len;
+  int32_t res_q, res_iters, res_trunc, pad;
+  float hist[kHist];     // Tbest fitness after iterations 1..k (ring)
+};
+
+// Partial argmin of one tile (group slice).
+struct TileBest {
+  float f;
+  int32_t n;
+};
+
+}  // namespace sepso
+
+namespace sepso {
+
+// Device pointers of every pool in the workspace (passed by value).
+struct Pools {
+  const InstDesc* desc;
+  InstCtl* ctl;
+  float *X, *V, *P;
+  float *f, *L, *Pf, *PL;
+  int32_t *Q, *PQ;
+  EdgeRec* edges;
+  float2* verts;
+  int32_t* poly_ptr;
+  float2* poly_vel;
+  float4* ends;      // start.xy, target.xy per instance
+  float4* end_vel;   // per instance
+  TileBest* tiles;
+  int32_t* gbest_n;
+  float* gbest_f;
+  float* hyper;      // G*6 per instance
+  const float* outer_hyper;
+  float* ov;         // G*3
+  float* op;         // G*3
+  float* opf;        // G
+  float* gbest_pos;  // G*2W
+  float* tbest_pos;  // 2W
+  float* prev_path;  // 2W
+  const int2* blk_tiles;  // fused-iteration block -> (instance, tile)
+  const int2* blk_init;   // init block -> (instance, first element)
+};
+
+// Kernel flags of the fused iteration.
+enum : int32_t { STEP_FIT = 1, STEP_FRAME = 2 };
+
+}  // namespace sepso

@@ -1,0 +1,14 @@
+// Host-side launchers of the device kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace sepso {
+
+void launch_geom(const Pools& pl, int n_inst, int move, hipStream_t s);
+void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev, hipStream_t s);
+bool step_supported(int K);
+void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s);
+
+}  // namespace sepso

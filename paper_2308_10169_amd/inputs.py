@@ -238,13 +238,14 @@ def static_swarm(seed=0, groups=4, particles=32, waypoints=8, iters=50, variant=
 
 
 def dynamic_swarm(S, seed=0, groups=8, particles=170, waypoints=20, iters=50,
-                  at_mode=2, hsef_every=10, use_pi=1):
+                  at_mode=2, hsef_every=10, use_pi=1, instance=0):
     """Swarm of the paper-shaped dynamic run: Table hyper8path start values,
     Table params_path penalty and PI fraction, truncation when the best
     improves by < 1e-3 (relative) over 5 iterations, online self-evolution
     every 10 iterations, PI radius 5% of the map."""
     pp = PARAMS_PATH
     return SwarmSpec(groups, particles, waypoints, iters, HYPER8PATH[np.arange(groups) % 8],
-                     alpha=pp["alpha"], beta=pp["beta"], seed=seed, use_pi=use_pi,
+                     alpha=pp["alpha"], beta=pp["beta"], seed=seed, instance=instance,
+                     use_pi=use_pi,
                      pi_gamma=pp["gamma"], pi_radius=0.05 * S, at_mode=at_mode, at_window=5,
                      at_delta=1e-3, hsef_every=hsef_every)

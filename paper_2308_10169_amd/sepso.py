@@ -1,0 +1,324 @@
+"""Thin ctypes binding of libsepso (argument marshalling only).
+
+Every step of the planner runs in the library's HIP kernels.  PyTorch is used
+for the device workspace and the stream; it must own the HIP runtime in this
+process, so it is imported (and initialised) before the library is loaded.
+There is no CPU fallback: without the built library or a GPU this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsepso.so")
+
+OK, E_ARG, E_NOMEM, E_HIP, E_STATE, E_UNSUPPORTED = range(6)
+
+fp = C.POINTER(C.c_float)
+ip = C.POINTER(C.c_int32)
+
+
+class SepsoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libsepso status {status}: {msg}")
+        self.status = status
+
+
+class CMap(C.Structure):
+    _fields_ = [("width", C.c_float), ("height", C.c_float), ("n_polys", C.c_int32),
+                ("poly_ptr", ip), ("verts", fp), ("start", C.c_float * 2),
+                ("target", C.c_float * 2), ("poly_vel", fp), ("endpoint_vel", C.c_float * 4)]
+
+
+class CSwarm(C.Structure):
+    _fields_ = [("groups", C.c_int32), ("particles", C.c_int32), ("waypoints", C.c_int32),
+                ("max_iters", C.c_int32), ("hyper", fp), ("alpha", C.c_float),
+                ("beta", C.c_int32), ("use_pi", C.c_int32), ("pi_gamma", C.c_float),
+                ("pi_radius", C.c_float), ("at_mode", C.c_int32), ("at_window", C.c_int32),
+                ("at_delta", C.c_float), ("hsef_every", C.c_int32), ("hsef_hyper", fp),
+                ("seed", C.c_uint64), ("instance", C.c_uint32)]
+
+
+class CFrameResult(C.Structure):
+    _fields_ = [("cost", C.c_float), ("length", C.c_float), ("crossings", C.c_int32),
+                ("iters", C.c_int32), ("truncated", C.c_int32), ("used_learned", C.c_int32),
+                ("device_ms", C.c_float)]
+
+
+class CState(C.Structure):
+    _fields_ = [("X", fp), ("V", fp), ("P", fp), ("f", fp), ("L", fp), ("Pf", fp), ("PL", fp),
+                ("Q", ip), ("PQ", ip), ("gbest_n", ip), ("gbest_f", fp), ("hyper", fp),
+                ("tbest_g", C.c_int32), ("tbest_n", C.c_int32), ("tbest_f", C.c_float),
+                ("k", C.c_int32), ("ctr", C.c_uint32), ("frame", C.c_int32)]
+
+
+class CTune(C.Structure):
+    _fields_ = [("seg_per_thread", C.c_int32), ("block_threads", C.c_int32)]
+
+
+_lib = None
+_torch = None
+
+
+def _load():
+    global _lib, _torch
+    if _lib is not None:
+        return _lib
+    import torch  # owns the HIP runtime of this process
+    if not torch.cuda.is_available():
+        raise SepsoError(E_UNSUPPORTED, "no HIP device visible: libsepso needs an MI355X")
+    torch.cuda.init()
+    if not os.path.exists(LIB_PATH):
+        raise SepsoError(E_UNSUPPORTED, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, sz = C.c_void_p, C.c_size_t
+    L.sepso_last_error.restype = C.c_char_p
+    L.sepso_version.restype = C.c_char_p
+    L.sepso_workspace_bytes.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm), C.POINTER(sz)]
+    L.sepso_create.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm), vp, sz, vp, C.POINTER(vp)]
+    L.sepso_destroy.argtypes = [vp]
+    L.sepso_step.argtypes = [vp, C.c_int32]
+    L.sepso_reinit.argtypes = [vp, C.c_int32, C.c_int32]
+    L.sepso_plan_frame.argtypes = [vp, C.POINTER(CMap), C.POINTER(CFrameResult), fp]
+    L.sepso_get_state.argtypes = [vp, C.POINTER(CState)]
+    L.sepso_set_state.argtypes = [vp, C.POINTER(CState)]
+    L.sepso_get_geometry.argtypes = [vp, fp, fp]
+    L.sepso_profile_step.argtypes = [vp, C.c_int32, fp]
+    L.sepso_batch_workspace_bytes.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm), C.c_int32,
+                                              C.POINTER(sz)]
+    L.sepso_batch_create.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm), C.c_int32, vp, sz, vp,
+                                     C.POINTER(CTune), C.POINTER(vp)]
+    L.sepso_batch_destroy.argtypes = [vp]
+    L.sepso_batch_path_offsets.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.sepso_batch_plan.argtypes = [vp, C.c_int32, C.POINTER(CFrameResult), fp]
+    L.sepso_batch_get_state.argtypes = [vp, C.c_int32, C.POINTER(CState)]
+    L.sepso_batch_profile_step.argtypes = [vp, C.c_int32, fp]
+    L.sepso_autotune.argtypes = [vp, C.POINTER(CTune)]
+    L.sepso_batch_work.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    _lib, _torch = L, torch
+    return L
+
+
+def lib():
+    return _load()
+
+
+def _check(st):
+    if st != OK:
+        raise SepsoError(st, _lib.sepso_last_error().decode())
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64), dtype=np.float32)
+
+
+class _MapArgs:
+    """Keeps the arrays behind a CMap alive."""
+
+    def __init__(self, spec: "I.MapSpec"):
+        self.pptr = np.ascontiguousarray(spec.poly_ptr, dtype=np.int32)
+        self.verts = _f32(spec.verts).reshape(-1)
+        self.vel = _f32(spec.poly_vel).reshape(-1)
+        n_polys = len(self.pptr) - 1
+        self.c = CMap(float(spec.width), float(spec.height), n_polys,
+                      self.pptr.ctypes.data_as(ip), self.verts.ctypes.data_as(fp),
+                      (C.c_float * 2)(*spec.start), (C.c_float * 2)(*spec.target),
+                      self.vel.ctypes.data_as(fp) if n_polys else None,
+                      (C.c_float * 4)(*spec.endpoint_vel))
+
+
+class _SwarmArgs:
+    def __init__(self, sw: "I.SwarmSpec"):
+        self.hyper = _f32(sw.hyper).reshape(-1)
+        self.hsef = _f32(sw.hsef_hyper).reshape(-1)
+        self.c = CSwarm(sw.groups, sw.particles, sw.waypoints, sw.max_iters,
+                        self.hyper.ctypes.data_as(fp), float(sw.alpha), int(sw.beta),
+                        int(sw.use_pi), float(sw.pi_gamma), float(sw.pi_radius), int(sw.at_mode),
+                        int(sw.at_window), float(sw.at_delta), int(sw.hsef_every),
+                        self.hsef.ctypes.data_as(fp), int(sw.seed), int(sw.instance))
+
+
+def _result(r):
+    return dict(cost=r.cost, length=r.length, crossings=r.crossings, iters=r.iters,
+                truncated=r.truncated, used_learned=r.used_learned, device_ms=r.device_ms)
+
+
+def _state_buffers(G, N, W):
+    D = 2 * W
+    z = lambda *s: np.zeros(s, np.float32)
+    zi = lambda *s: np.zeros(s, np.int32)
+    return dict(X=z(G, N, D), V=z(G, N, D), P=z(G, N, D), f=z(G, N), L=z(G, N), Pf=z(G, N),
+                PL=z(G, N), Q=zi(G, N), PQ=zi(G, N), gbest_n=zi(G), gbest_f=z(G),
+                hyper=z(G, 6))
+
+
+def _cstate(bufs, scal=None):
+    cs = CState()
+    for k, v in bufs.items():
+        if v is not None:
+            setattr(cs, k, v.ctypes.data_as(ip if v.dtype == np.int32 else fp))
+    if scal:
+        for k, v in scal.items():
+            setattr(cs, k, v)
+    return cs
+
+
+class Planner:
+    """One planner instance (sepso_ctx)."""
+
+    def __init__(self, spec, sw, stream=None):
+        L = _load()
+        torch = _torch
+        self.spec, self.sw = spec, sw
+        self._m, self._s = _MapArgs(spec), _SwarmArgs(sw)
+        nbytes = C.c_size_t()
+        _check(L.sepso_workspace_bytes(C.byref(self._m.c), C.byref(self._s.c), C.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = C.c_void_p()
+        _check(L.sepso_create(C.byref(self._m.c), C.byref(self._s.c), C.c_void_p(self.ws.data_ptr()),
+                              nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(_lib.sepso_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(_lib.sepso_step(self.h, int(n)))
+
+    def reinit(self, frame=0, use_prev=False):
+        _check(_lib.sepso_reinit(self.h, int(frame), int(bool(use_prev))))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def plan_frame(self, next_map=None):
+        res = CFrameResult()
+        path = np.zeros(2 * self.sw.waypoints, np.float32)
+        m = _MapArgs(next_map) if next_map is not None else None
+        _check(_lib.sepso_plan_frame(self.h, C.byref(m.c) if m else None, C.byref(res),
+                                     path.ctypes.data_as(fp)))
+        out = _result(res)
+        out["path"] = path
+        return out
+
+    def get_state(self):
+        b = _state_buffers(self.sw.groups, self.sw.particles, self.sw.waypoints)
+        cs = _cstate(b)
+        _check(_lib.sepso_get_state(self.h, C.byref(cs)))
+        b.update(tbest=(cs.tbest_g, cs.tbest_n, cs.tbest_f), k=cs.k, ctr=cs.ctr, frame=cs.frame)
+        return b
+
+    def set_state(self, st):
+        keys = ("X", "V", "P", "f", "L", "Pf", "PL", "Q", "PQ", "gbest_n", "gbest_f", "hyper")
+        bufs = {}
+        for k in keys:
+            if k in st and st[k] is not None:
+                dt = np.int32 if k in ("Q", "PQ", "gbest_n") else np.float32
+                bufs[k] = np.ascontiguousarray(st[k], dtype=dt)
+        tb = st.get("tbest", (0, 0, float("inf")))
+        cs = _cstate(bufs, dict(tbest_g=int(tb[0]), tbest_n=int(tb[1]), tbest_f=float(tb[2]),
+                                k=int(st.get("k", 0)), ctr=int(st.get("ctr", 0)),
+                                frame=int(st.get("frame", 0))))
+        _check(_lib.sepso_set_state(self.h, C.byref(cs)))
+
+    def geometry(self):
+        nv = int(self.spec.poly_ptr[-1])
+        v = np.zeros(max(2 * nv, 1), np.float32)
+        e = np.zeros(4, np.float32)
+        _check(_lib.sepso_get_geometry(self.h, v.ctypes.data_as(fp), e.ctypes.data_as(fp)))
+        return v[:2 * nv].reshape(-1, 2), e
+
+    def profile_step(self, n=10):
+        ms = C.c_float()
+        _check(_lib.sepso_profile_step(self.h, int(n), C.byref(ms)))
+        return ms.value
+
+
+class BatchPlanner:
+    """Many independent planner instances in one set of launches (sepso_batch)."""
+
+    def __init__(self, specs, sws, tune=None, stream=None):
+        L = _load()
+        torch = _torch
+        n = len(specs)
+        self.specs, self.sws, self.n = specs, sws, n
+        self._m = [_MapArgs(s) for s in specs]
+        self._s = [_SwarmArgs(s) for s in sws]
+        self._cm = (CMap * n)(*[m.c for m in self._m])
+        self._cs = (CSwarm * n)(*[s.c for s in self._s])
+        nbytes = C.c_size_t()
+        _check(L.sepso_batch_workspace_bytes(self._cm, self._cs, n, C.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        t = CTune(*tune) if tune is not None else None
+        h = C.c_void_p()
+        _check(L.sepso_batch_create(self._cm, self._cs, n, C.c_void_p(self.ws.data_ptr()),
+                                    nbytes.value, C.c_void_p(self.stream.cuda_stream),
+                                    C.byref(t) if t else None, C.byref(h)))
+        self.h = h
+        off = (C.c_int64 * (n + 1))()
+        _check(L.sepso_batch_path_offsets(h, off))
+        self.path_off = np.array(off[:], dtype=np.int64)
+
+    def close(self):
+        if self.h:
+            _check(_lib.sepso_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def plan(self, n_frames=1, want_paths=False):
+        res = (CFrameResult * (self.n * n_frames))()
+        paths = np.zeros(max(int(self.path_off[-1]), 1), np.float32) if want_paths else None
+        _check(_lib.sepso_batch_plan(self.h, int(n_frames), res,
+                                     paths.ctypes.data_as(fp) if want_paths else None))
+        cost = np.array([r.cost for r in res], np.float64).reshape(n_frames, self.n)
+        iters = np.array([r.iters for r in res], np.int32).reshape(n_frames, self.n)
+        q = np.array([r.crossings for r in res], np.int32).reshape(n_frames, self.n)
+        trunc = np.array([r.truncated for r in res], np.int32).reshape(n_frames, self.n)
+        out = dict(cost=cost, iters=iters, crossings=q, truncated=trunc)
+        if want_paths:
+            out["paths"] = [paths[self.path_off[i]:self.path_off[i + 1]] for i in range(self.n)]
+        return out
+
+    def get_state(self, i):
+        sw = self.sws[i]
+        b = _state_buffers(sw.groups, sw.particles, sw.waypoints)
+        cs = _cstate(b)
+        _check(_lib.sepso_batch_get_state(self.h, int(i), C.byref(cs)))
+        b.update(tbest=(cs.tbest_g, cs.tbest_n, cs.tbest_f), k=cs.k, ctr=cs.ctr, frame=cs.frame)
+        return b
+
+    def profile_step(self, n=10):
+        ms = C.c_float()
+        _check(_lib.sepso_batch_profile_step(self.h, int(n), C.byref(ms)))
+        return ms.value
+
+    def autotune(self):
+        t = CTune()
+        _check(_lib.sepso_autotune(self.h, C.byref(t)))
+        return (t.seg_per_thread, t.block_threads)
+
+    def work(self):
+        a, b = C.c_double(), C.c_double()
+        _check(_lib.sepso_batch_work(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value

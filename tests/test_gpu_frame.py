@@ -1,0 +1,167 @@
+"""GPU frame loop (Priori Initialization, Auto Truncation, online HSEF,
+device obstacle motion) and batched planning, against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import pyorc as orc
+from paper_2308_10169_amd import inputs as I
+
+from parity import REL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sp():
+    from paper_2308_10169_amd import sepso
+    sepso.lib()
+    return sepso
+
+
+def _small_dyn(seed, **kw):
+    spec = I.dynamic_map(seed)
+    sw = I.dynamic_swarm(spec.scale, seed=seed, particles=48, waypoints=10, **kw)
+    return spec, sw
+
+
+def test_device_motion_matches_oracle_bit_exact(sp):
+    spec, sw = _small_dyn(1, iters=5)
+    pl = sp.Planner(spec, sw)
+    ref = spec.copy()
+    for f in range(12):
+        pl.plan_frame()
+        if f > 0:
+            orc.sim_step(ref)
+        v, e = pl.geometry()
+        assert np.array_equal(v, ref.verts.astype(np.float32)), f"frame {f} vertices"
+        assert np.array_equal(e, np.r_[ref.start, ref.target].astype(np.float32))
+    pl.close()
+
+
+def test_frame_result_is_consistent(sp):
+    spec, sw = _small_dyn(2)
+    pl = sp.Planner(spec, sw)
+    ref = spec.copy()
+    for f in range(6):
+        if f > 0:
+            orc.sim_step(ref)
+        r = pl.plan_frame()
+        chk = orc.fitness(orc.Map(ref), r["path"][None, :].astype(np.float64), sw.waypoints,
+                          sw.alpha, sw.beta)
+        assert chk["q_yes"][0] <= r["crossings"] <= chk["q_yes"][0] + chk["n_deg"][0]
+        if chk["n_deg"][0] == 0:
+            assert abs(chk["f"][0] - r["cost"]) <= REL * max(chk["f"][0], 1.0)
+        if r["truncated"]:
+            assert r["crossings"] == 0 and sw.at_window < r["iters"] < sw.max_iters + 1
+        else:
+            assert r["iters"] == sw.max_iters
+    pl.close()
+
+
+def test_priori_initialization(sp):
+    spec, sw = _small_dyn(3)
+    pl = sp.Planner(spec, sw)
+    r = pl.plan_frame()
+    pl.reinit(frame=1, use_prev=True)
+    st = pl.get_state()
+    o = orc.Swarm(sw, spec.width, spec.height)
+    o.init(1, prev_path=r["path"].astype(np.float64), gamma=sw.pi_gamma, radius=sw.pi_radius)
+    n_pi = int(np.ceil(sw.pi_gamma * sw.particles))
+    assert np.array_equal(st["X"][:, n_pi:], o.X[:, n_pi:].astype(np.float32))
+    assert np.all(np.abs(st["X"][:, :n_pi] - o.X[:, :n_pi]) <= REL * spec.scale)
+    d = np.abs(st["X"][:, :n_pi] - r["path"][None, None, :])
+    assert np.all(d <= sw.pi_radius * (1 + 1e-6))
+    pl.close()
+
+
+def test_first_frame_with_self_evolution_matches_oracle(sp):
+    # One frame of 11 iterations with the outer step after iteration 10: the
+    # GPU and oracle trajectories start from the same draws and stay within
+    # rounding over so few iterations, so the evolved hyper-parameters and
+    # the frame's cost agree closely.
+    spec = I.dynamic_map(4)
+    sw = I.dynamic_swarm(spec.scale, seed=4, particles=64, waypoints=12, iters=11, at_mode=0)
+    pl = sp.Planner(spec, sw)
+    r = pl.plan_frame()
+    st = pl.get_state()
+    o = orc.Swarm(sw, spec.width, spec.height)
+    ro = o.plan_frame(orc.Map(spec), 0)
+    assert r["iters"] == ro["iters"] == 11
+    assert abs(r["cost"] - ro["cost"]) <= 1e-4 * ro["cost"]
+    assert not np.allclose(o.hyper, sw.hyper)  # the outer step moved something
+    assert np.allclose(st["hyper"], o.hyper, rtol=0, atol=1e-4)
+    pl.close()
+
+
+def test_truncation_lowers_iterations(sp):
+    # Table ppresult's qualitative claim: Auto Truncation cuts iterations.
+    spec, sw_at = _small_dyn(6)
+    _, sw_no = _small_dyn(6, at_mode=0)
+    a, b = sp.Planner(spec, sw_at), sp.Planner(spec, sw_no)
+    ia = [a.plan_frame()["iters"] for _ in range(10)]
+    ib = [b.plan_frame()["iters"] for _ in range(10)]
+    assert np.mean(ia) < np.mean(ib) == sw_no.max_iters
+    a.close()
+    b.close()
+
+
+def test_frame_distribution_matches_oracle(sp):
+    # Dynamic run, several seeds x frames: median per-frame cost and mean
+    # iterations of the GPU loop against the oracle loop.
+    gc, oc, gi, oi = [], [], [], []
+    for seed in range(4):
+        spec, sw = _small_dyn(10 + seed)
+        pl = sp.Planner(spec, sw)
+        o = orc.Swarm(sw, spec.width, spec.height)
+        ref = spec.copy()
+        for f in range(8):
+            if f > 0:
+                orc.sim_step(ref)
+            r = pl.plan_frame()
+            ro = o.plan_frame(orc.Map(ref), f)
+            gc.append(r["cost"])
+            oc.append(ro["cost"])
+            gi.append(r["iters"])
+            oi.append(ro["iters"])
+        pl.close()
+    print("median cost", np.median(gc), np.median(oc), "iters", np.mean(gi), np.mean(oi))
+    assert abs(np.median(gc) - np.median(oc)) <= 0.03 * np.median(oc)
+    assert abs(np.mean(gi) - np.mean(oi)) <= 0.25 * np.mean(oi)
+
+
+def _ragged(n):
+    specs, sws = [], []
+    for i in range(n):
+        m, shape = I.batch_instance(i)
+        shape["particles"] = min(shape["particles"], 64)
+        sw = I.dynamic_swarm(m.scale, seed=77, instance=i, iters=20, **shape)
+        specs.append(m)
+        sws.append(sw)
+    return specs, sws
+
+
+def test_batch_equals_solo(sp):
+    specs, sws = _ragged(5)
+    bp = sp.BatchPlanner(specs, sws, tune=(12, 128))
+    rb = bp.plan(3, want_paths=True)
+    for i in range(5):
+        solo = sp.BatchPlanner([specs[i]], [sws[i]], tune=(12, 128))
+        rs = solo.plan(3, want_paths=True)
+        assert np.array_equal(rs["cost"][:, 0], rb["cost"][:, i])
+        assert np.array_equal(rs["iters"][:, 0], rb["iters"][:, i])
+        assert np.array_equal(rs["paths"][0], rb["paths"][i])
+        solo.close()
+    bp.close()
+
+
+def test_batch_paths_score_as_reported(sp):
+    specs, sws = _ragged(6)
+    bp = sp.BatchPlanner(specs, sws)
+    r = bp.plan(1, want_paths=True)
+    for i in range(6):
+        chk = orc.fitness(orc.Map(specs[i]), r["paths"][i][None, :].astype(np.float64),
+                          sws[i].waypoints, sws[i].alpha, sws[i].beta)
+        if chk["n_deg"][0] == 0:
+            assert chk["Q"][0] == r["crossings"][0, i]
+            assert abs(chk["f"][0] - r["cost"][0, i]) <= REL * max(chk["f"][0], 1.0)
+    bp.close()

@@ -1,0 +1,157 @@
+"""GPU parity of the fused DTPSO iteration against the FP64 oracle, by state
+injection at every step (tolerances in parity.py)."""
+import numpy as np
+import pytest
+
+from oracle import pyorc as orc
+from paper_2308_10169_amd import inputs as I
+
+from parity import check_fitness, check_step
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sp():
+    from paper_2308_10169_amd import sepso
+    sepso.lib()
+    return sepso
+
+
+def _run_injected(sp, spec, sw, steps, stats=None):
+    pl = sp.Planner(spec, sw)
+    o = orc.Swarm(sw, spec.width, spec.height)
+    m = orc.Map(spec)
+    st0 = pl.get_state()
+    for _ in range(steps):
+        pl.step(1)
+        st1 = pl.get_state()
+        check_step(o, m, st0, st1, spec.scale, stats)
+        st0 = st1
+    pl.close()
+
+
+def test_init_draws_bit_exact(sp):
+    # X0 = u * hi with u a 24-bit Philox uniform: the FP32 product is the
+    # correctly rounded exact product, so it must equal the oracle's value
+    # rounded to FP32 -- any differing random word would show.
+    spec, sw = I.static_map(0), I.static_swarm(seed=12345)
+    pl = sp.Planner(spec, sw)
+    st = pl.get_state()
+    o = orc.Swarm(sw, spec.width, spec.height)
+    o.init(0)
+    assert np.array_equal(st["X"], o.X.astype(np.float32))
+    assert np.allclose(st["V"], o.V, rtol=0, atol=1e-5 * 100)
+    assert np.all(np.isinf(st["Pf"]))
+    pl.close()
+
+
+@pytest.mark.parametrize("variant", ["hyper1", "hyper8"])
+def test_static_plan_every_step(sp, variant):
+    # Single static plan (100x100, 4 rectangles, 4x32 particles, W=8, 50
+    # iterations); variant hyper8 exercises the Tbest attractor (C3 != 0).
+    stats = {}
+    for seed in (0, 1, 2):
+        spec = I.static_map(seed)
+        sw = I.static_swarm(seed=seed, variant=variant)
+        _run_injected(sp, spec, sw, 50, stats)
+    print("parity stats", stats)
+    assert stats["paths"] == 3 * 50 * 128
+
+
+def test_dynamic_shape_steps(sp):
+    # Paper-shaped instance: 366 map, 30 rectangles, 8 x 170 particles, W = 20.
+    spec = I.dynamic_map(0)
+    sw = I.dynamic_swarm(spec.scale, seed=3)
+    stats = {}
+    _run_injected(sp, spec, sw, 12, stats)
+    print("parity stats", stats)
+
+
+@pytest.mark.parametrize("K,B", [(4, 64), (8, 128), (12, 256), (16, 256), (24, 128)])
+def test_tile_shapes_agree(sp, K, B):
+    # Every tile configuration yields the oracle's crossings and the same
+    # per-particle fitness (ragged tails: N = 37 particles, W = 13).
+    spec = I.dynamic_map(2, S=200.0, n_static=6, n_moving=6, side=(8.0, 30.0))
+    sw = I.dynamic_swarm(spec.scale, seed=9, groups=3, particles=37, waypoints=13)
+    bp = sp.BatchPlanner([spec], [sw], tune=(K, B))
+    o = orc.Swarm(sw, spec.width, spec.height)
+    o.init(0)
+    st = bp.get_state(0)
+    assert np.array_equal(st["X"], o.X.astype(np.float32))
+    bp.profile_step(1)  # one fused iteration, then the pending update
+    st1 = bp.get_state(0)
+    check_fitness(orc.Map(spec), st, st1, 13, sw.alpha, sw.beta)
+    bp.close()
+
+
+def test_adversarial_degenerate_paths(sp):
+    # Waypoints placed exactly on obstacle vertices, on edges and along edge
+    # lines: many degenerate tests; counts must stay in the oracle bracket.
+    spec = I.static_map(7)
+    sw = I.static_swarm(seed=1, groups=2, particles=64, waypoints=8)
+    pl = sp.Planner(spec, sw)
+    rng = np.random.default_rng(0)
+    V = spec.verts
+    X = np.zeros((2, 64, 16))
+    for g in range(2):
+        for n in range(64):
+            for j in range(8):
+                a, b = V[rng.integers(len(V))], V[rng.integers(len(V))]
+                t = rng.integers(0, 5) / 4.0  # vertex, edge point or beyond
+                p = a + t * (b - a)
+                X[g, n, j], X[g, n, 8 + j] = np.clip(p, 0, 100)
+    st = pl.get_state()
+    st["X"] = X.astype(np.float32)
+    st["Pf"][:] = np.inf
+    pl.set_state(st)
+    st0 = pl.get_state()
+    pl.step(1)
+    st1 = pl.get_state()
+    r = check_fitness(orc.Map(spec), st0, st1, 8, sw.alpha, sw.beta)
+    assert r["n_deg"].sum() > 100
+    pl.close()
+
+
+def test_large_stress_sampled(sp):
+    # Stress scene (512 map, 2400 edges, W = 64) at a reduced particle count;
+    # fitness of a sample of particles against the oracle.
+    spec = I.stress_map(0)
+    sw = I.SwarmSpec(8, 256, 64, 200, I.HYPER8PATH, alpha=30.0, beta=4, seed=4)
+    pl = sp.Planner(spec, sw)
+    st0 = pl.get_state()
+    pl.step(1)
+    st1 = pl.get_state()
+    idx = np.random.default_rng(1).choice(8 * 256, 96, replace=False)
+    sub = lambda st: dict(X=st["X"].reshape(-1, 128)[idx][None], Q=st["Q"].reshape(-1)[idx][None],
+                          L=st["L"].reshape(-1)[idx][None], f=st["f"].reshape(-1)[idx][None])
+    check_fitness(orc.Map(spec), sub(st0), sub(st1), 64, sw.alpha, sw.beta)
+    pl.close()
+
+
+def test_determinism(sp):
+    spec, sw = I.dynamic_map(5), I.dynamic_swarm(366.0, seed=5)
+    a, b = sp.Planner(spec, sw), sp.Planner(spec, sw)
+    a.step(20)
+    b.step(20)
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("X", "V", "P", "Pf", "Q"):
+        assert np.array_equal(sa[k], sb[k])
+    a.close()
+    b.close()
+
+
+def test_end_to_end_median_cost(sp):
+    # Static plan over 100 seeds: the median final Tbest fitness of the GPU
+    # planner is within 1% of the oracle planner's.
+    g, c = [], []
+    for seed in range(100):
+        spec, sw = I.static_map(seed), I.static_swarm(seed=seed)
+        pl = sp.Planner(spec, sw)
+        pl.step(sw.max_iters)
+        g.append(pl.get_state()["tbest"][2])
+        pl.close()
+        c.append(orc.plan_static(spec, sw)[0])
+    mg, mc = np.median(g), np.median(c)
+    print("median cost gpu", mg, "oracle", mc)
+    assert abs(mg - mc) <= 0.01 * mc
