@@ -39,14 +39,18 @@ def batch_workload(n_inst, seed_base=0):
     return specs, sws
 
 
-def oracle_matched(specs, sws, res, sample):
+def oracle_matched(specs, sws, res, sample, moves):
     """Reported cost of sampled instances equals the oracle's fitness of the
-    returned path (within 1e-5 where the oracle flags no degenerate test)."""
+    returned path on the map as moved by the oracle's own motion model
+    (within 1e-5 where the oracle flags no degenerate test)."""
     from oracle import pyorc as orc
     ok = True
     for i in sample:
+        m = specs[i].copy()
+        for _ in range(moves):
+            orc.sim_step(m)
         p = res["paths"][i][None, :].astype(np.float64)
-        chk = orc.fitness(orc.Map(specs[i]), p, sws[i].waypoints, sws[i].alpha, sws[i].beta)
+        chk = orc.fitness(orc.Map(m), p, sws[i].waypoints, sws[i].alpha, sws[i].beta)
         if chk["n_deg"][0] == 0:
             ok &= abs(chk["f"][0] - res["cost"][-1, i]) <= 1e-5 * max(chk["f"][0], 1.0)
     return bool(ok)
@@ -116,7 +120,8 @@ def main():
     for i in range(args.instances):
         per = sws[i].groups * sws[i].particles * (sws[i].waypoints + 1) * specs[i].n_edges
         tests_run += per * iters[:, i].sum()
-    matched = oracle_matched(specs, sws, res, range(0, args.instances, max(1, args.instances // 8)))
+    matched = oracle_matched(specs, sws, res, range(0, args.instances, max(1, args.instances // 8)),
+                             args.warmup + args.steps - 1)
     print(f"# {plans} plans in {dt:.3f}s, mean iters {iters.mean():.1f}", file=sys.stderr, flush=True)
 
     achieved = F_TEST * tests_iter / (kern_ms * 1e-3)

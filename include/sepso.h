@@ -178,6 +178,54 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best);
 /* Work counters of one full iteration of every instance: segment x edge
  * tests and swarm elements (for throughput reporting). */
 sepso_status sepso_batch_work(sepso_batch* b, double* tests_per_iter, double* elems_per_iter);
+/* Tbest fitness after each iteration of the last planned frame, per
+ * instance: out gets n_inst x 64 floats (entries past the frame's iteration
+ * count are stale). */
+sepso_status sepso_batch_history(sepso_batch* b, float* out);
+
+/* ---- learned initializer ------------------------------------------------
+ * An MLP (BF16 weights and activations, FP32 accumulation on MFMA) maps a
+ * 64 x 64 occupancy raster of the map (cell centre inside an obstacle) plus
+ * start and target (normalised by the map size) -- 4100 inputs -- through
+ * three ReLU layers of 512 to 320 outputs: one initial 20-waypoint path per
+ * group for 8 groups, normalised to [0,1].  When attached to a batch it runs
+ * at every frame start and takes the place of the previous plan in Priori
+ * Initialization (group g's first ceil(gamma*N) particles are drawn within
+ * +-pi_radius of proposal g); instances that are not 8 x (N, 20) or whose
+ * proposal is not finite fall back to plain Priori Initialization.
+ * Parameters (flat FP32): W1 (512 x 4100), b1, W2 (512 x 512), b2, W3, b3,
+ * W4 (320 x 512), b4 -- weights row-major (out, in).  Training: MSE against
+ * targets, Adam (0.9, 0.999, 1e-8) on FP32 master weights. */
+typedef struct sepso_lin sepso_lin;
+int64_t sepso_lin_param_count(void);
+/* max_rows (multiple of 32): rows of one forward/backward pass (batch
+ * instances or minibatch); max_samples: on-device training-set capacity. */
+sepso_status sepso_lin_workspace_bytes(int32_t max_rows, int64_t max_samples, size_t* bytes);
+/* Weights seeded uniformly in +-1/sqrt(fan_in), biases zero.  Synchronous. */
+sepso_status sepso_lin_create(int32_t max_rows, int64_t max_samples, uint64_t seed,
+                              void* d_workspace, size_t workspace_bytes, void* stream,
+                              sepso_lin** out);
+sepso_status sepso_lin_destroy(sepso_lin* lin);
+sepso_status sepso_lin_set_weights(sepso_lin* lin, const float* flat);
+sepso_status sepso_lin_get_weights(sepso_lin* lin, float* flat);
+/* Host rows x (n x 4100, rounded to BF16) -> outputs y (n x 320). */
+sepso_status sepso_lin_forward(sepso_lin* lin, const float* x, int32_t n, float* y);
+/* Loss and flat parameter gradients for n rows (n a multiple of 32). */
+sepso_status sepso_lin_grads(sepso_lin* lin, const float* x, const float* targets, int32_t n,
+                             float* loss, float* grads);
+/* Append every instance of a planned batch (8 groups x 20 waypoints each)
+ * to the training set: its features and its final group bests. */
+sepso_status sepso_lin_collect(sepso_lin* lin, sepso_batch* b);
+sepso_status sepso_lin_samples(sepso_lin* lin, int64_t* n);
+/* steps Adam steps over consecutive minibatches of the training set;
+ * loss_out (may be NULL) gets the loss of each step. */
+sepso_status sepso_lin_train(sepso_lin* lin, int32_t steps, int32_t batch, float lr,
+                             float* loss_out);
+/* Network input features of the batch's current maps (n_inst x 4100). */
+sepso_status sepso_lin_features(sepso_lin* lin, sepso_batch* b, float* out);
+/* Use lin's proposals at every frame start of b (NULL detaches). */
+sepso_status sepso_lin_attach(sepso_batch* b, sepso_lin* lin);
+sepso_status sepso_lin_attach_ctx(sepso_ctx* ctx, sepso_lin* lin);
 
 #ifdef __cplusplus
 }

@@ -283,3 +283,55 @@ def plan_static(spec, sw, iters=None):
     s.init(0)
     s.step(m, iters if iters is not None else sw.max_iters)
     return s.s.tbest_f, s
+
+
+# ---------------------------------------------------------------------------
+# learned initializer (MLP) oracle
+def bf16(x):
+    """Round-to-nearest-even BF16 of each value (FP64 in, FP64 out)."""
+    L = lib()
+    L.orc_bf16.argtypes = [C.c_double]
+    L.orc_bf16.restype = C.c_double
+    a = np.asarray(x, dtype=np.float64)
+    return np.vectorize(L.orc_bf16, otypes=[np.float64])(a) if a.ndim else L.orc_bf16(float(a))
+
+
+def mlp(sizes, W, b, x, target=None, round=True, grads=True):
+    """FP64 MLP forward (+ backward when target given and grads).  W[l]:
+    (sizes[l+1], sizes[l]); returns dict(y, loss, gW, gb)."""
+    L = lib()
+    nl = len(sizes) - 1
+    sz = np.ascontiguousarray(sizes, dtype=np.int32)
+    Wc = [np.ascontiguousarray(w, dtype=np.float64) for w in W]
+    bc = [np.ascontiguousarray(v, dtype=np.float64) for v in b]
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    B = x.shape[0]
+    y = np.zeros((B, sizes[-1]))
+    loss = C.c_double(0.0)
+    Wp = (dp * nl)(*[_p(w) for w in Wc])
+    bp = (dp * nl)(*[_p(v) for v in bc])
+    tg = None
+    if target is not None:
+        tg = np.ascontiguousarray(target, dtype=np.float64)
+    gW = [np.zeros_like(w) for w in Wc]
+    gb = [np.zeros_like(v) for v in bc]
+    do_g = grads and target is not None
+    gWp = (dp * nl)(*[_p(w) for w in gW]) if do_g else None
+    gbp = (dp * nl)(*[_p(v) for v in gb]) if do_g else None
+    L.orc_mlp.argtypes = [C.c_int32, ip, C.POINTER(dp), C.POINTER(dp), C.c_int32, dp, dp,
+                          C.c_int32, dp, C.POINTER(C.c_double), C.POINTER(dp), C.POINTER(dp)]
+    L.orc_mlp(nl, _p(sz, ip), Wp, bp, B, _p(x), _p(tg) if tg is not None else None,
+              int(bool(round)), _p(y), C.byref(loss), gWp, gbp)
+    return dict(y=y, loss=loss.value if target is not None else None,
+                gW=gW if do_g else None, gb=gb if do_g else None)
+
+
+def raster(spec, n=64):
+    L = lib()
+    ptr = np.ascontiguousarray(spec.poly_ptr, dtype=np.int32)
+    verts = np.ascontiguousarray(spec.verts, dtype=np.float64)
+    out = np.zeros((n, n))
+    L.orc_raster.argtypes = [C.c_double, C.c_double, C.c_int32, ip, dp, C.c_int32, dp]
+    L.orc_raster(float(spec.width), float(spec.height), len(ptr) - 1, _p(ptr, ip), _p(verts),
+                 int(n), _p(out))
+    return out

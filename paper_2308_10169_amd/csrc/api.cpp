@@ -12,23 +12,12 @@
 
 #include "../../include/sepso.h"
 #include "common.h"
+#include "internal.h"
 #include "kernels.h"
 
 using namespace sepso;
 
 namespace {
-
-thread_local std::string g_err;
-
-sepso_status fail(sepso_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return st;
-}
 
 // Table hyper8 (DTPSO / H-SEPSO defaults): default outer-swarm hyper.
 const float kHyper8[8][6] = {
@@ -103,14 +92,6 @@ sepso_status check_swarm(const sepso_swarm* s, int idx) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// Workspace carve-up of a batch (byte offsets of every pool).
-struct Layout {
-  size_t desc, ctl, X, V, P, f, L, Pf, PL, Q, PQ, edges, verts, pptr, pvel, ends, endv, tiles,
-      gbn, gbf, hyper, ohyper, ov, op, opf, gpos, tpos, prev, blkt, blki, total;
-  int64_t sumPD = 0, sumP = 0, sumTilesMax = 0;
-  int64_t sumE = 0, sumPP = 0, sumPoly = 0, sumG = 0, sumGD = 0, sumD = 0, initBlocks = 0;
-};
 
 Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vector<InstDesc>* desc) {
   Layout L{};
@@ -196,6 +177,7 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   L.gpos = take(4 * L.sumGD);
   L.tpos = take(4 * L.sumD);
   L.prev = take(4 * L.sumD);
+  L.prop = take(4 * L.sumGD);
   L.blkt = take(8 * L.sumTilesMax);
   L.blki = take(8 * L.initBlocks);
   L.total = o;
@@ -211,34 +193,6 @@ int default_K(int W) {
 }
 
 }  // namespace
-
-struct sepso_batch {
-  int n = 0;
-  std::vector<InstDesc> desc;
-  std::vector<int> n_vert;
-  std::vector<int32_t> h_pptr;  // polygon offsets of instance 0
-  std::vector<int64_t> path_off;
-  Layout lay{};
-  Pools pl{};
-  char* ws = nullptr;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  bool broken = false;
-  sepso_tune tune{16, 256};
-  int tile_blocks = 0;
-  int frames_done = 0;
-  // pinned host mirrors
-  InstCtl* h_ctl = nullptr;
-  float* h_paths = nullptr;
-  float* h_stage = nullptr;  // geometry staging for host-provided maps
-  size_t stage_floats = 0;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] no motion, [1] motion step first
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-};
-
-struct sepso_ctx {
-  sepso_batch* b;
-};
 
 namespace {
 
@@ -305,7 +259,6 @@ void destroy_batch(sepso_batch* b) {
   if (b->ev1) hipEventDestroy(b->ev1);
   if (b->h_ctl) hipHostFree(b->h_ctl);
   if (b->h_paths) hipHostFree(b->h_paths);
-  if (b->h_stage) hipHostFree(b->h_stage);
   if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
   delete b;
 }
@@ -397,6 +350,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
   pl.gbest_pos = at<float>(b, L.gpos);
   pl.tbest_pos = at<float>(b, L.tpos);
   pl.prev_path = at<float>(b, L.prev);
+  pl.proposal = at<float>(b, L.prop);
   pl.blk_tiles = at<int2>(b, L.blkt);
   pl.blk_init = at<int2>(b, L.blki);
 
@@ -490,6 +444,7 @@ int init_blocks(sepso_batch* b) { return (int)b->lay.initBlocks; }
 // Enqueue one whole frame of every instance.
 void enqueue_frame(sepso_batch* b, bool move) {
   if (move) launch_geom(b->pl, b->n, 1, b->stream);
+  if (b->lin) lin_enqueue_proposals(b->lin, b);
   launch_init(b->pl, init_blocks(b), -1, 1, b->stream);
   int tmax = 0;
   for (auto& d : b->desc) tmax = std::max(tmax, d.T);
@@ -528,7 +483,7 @@ void fill_result(const InstCtl& c, float ms, sepso_frame_result* r) {
   r->crossings = c.res_q;
   r->iters = c.res_iters;
   r->truncated = c.res_trunc;
-  r->used_learned = 0;
+  r->used_learned = c.use_learned;
   r->device_ms = ms;
 }
 
@@ -812,6 +767,12 @@ sepso_status sepso_batch_plan(sepso_batch* b, int32_t n_frames, sepso_frame_resu
     for (int i = 0; i < b->n; ++i) fill_result(b->h_ctl[i], 0.f, &out[(size_t)f * b->n + i]);
   }
   if (out_paths) std::memcpy(out_paths, b->h_paths, sizeof(float) * b->path_off[b->n]);
+  return SEPSO_OK;
+}
+
+sepso_status sepso_batch_history(sepso_batch* b, float* out) {
+  if (!b || !out) return fail(SEPSO_E_ARG, "batch/out NULL");
+  for (int i = 0; i < b->n; ++i) std::memcpy(out + (size_t)i * kHist, b->h_ctl[i].hist, 4 * kHist);
   return SEPSO_OK;
 }
 

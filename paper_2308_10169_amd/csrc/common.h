@@ -12,6 +12,15 @@ constexpr int kMaxG = 64;        // groups per instance
 constexpr int kHist = 64;        // Auto-Truncation history ring
 constexpr int kEdgeChunk = 512;  // obstacle edges staged in LDS per pass
 
+// Learned initializer: 64 x 64 occupancy raster + start/target (4 values)
+// -> 3 x 512 hidden -> 8 groups x 20 waypoints x 2 coordinates.
+constexpr int kRaster = 64;
+constexpr int kLinIn = kRaster * kRaster + 4;   // 4100
+constexpr int kLinInPad = 4128;                 // multiple of 32
+constexpr int kLinHidden = 512;
+constexpr int kLinGroups = 8, kLinW = 20;
+constexpr int kLinOut = kLinGroups * 2 * kLinW; // 320
+
 // Philox counter tags: which random stream a draw belongs to.
 enum Tag : uint32_t { TAG_UPDATE = 0, TAG_INIT_X = 1, TAG_INIT_V = 2, TAG_PI = 3, TAG_HSEF = 4 };
 
@@ -74,7 +83,7 @@ struct InstCtl {
   int32_t truncated;
   int32_t have_prev;     // a previous plan exists (PI allowed)
   float res_cost, res_len;
-  int32_t res_q, res_iters, res_trunc, pad;
+  int32_t res_q, res_iters, res_trunc, use_learned;
   float hist[kHist];     // Tbest fitness after iterations 1..k (ring)
 };
 
@@ -112,6 +121,7 @@ struct Pools {
   float* gbest_pos;  // G*2W
   float* tbest_pos;  // 2W
   float* prev_path;  // 2W
+  float* proposal;   // G*2W learned initial path per group (layout of gbest_pos)
   const int2* blk_tiles;  // fused-iteration block -> (instance, tile)
   const int2* blk_init;   // init block -> (instance, first element)
 };

@@ -1,0 +1,103 @@
+// Host-side internals shared by the C-ABI translation units: error state,
+// workspace layout, and the batch / context / learned-initializer handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/sepso.h"
+#include "common.h"
+
+namespace sepso {
+
+inline thread_local std::string g_err;
+
+inline sepso_status fail(sepso_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+// Workspace carve-up of a batch (byte offsets of every pool).
+struct Layout {
+  size_t desc, ctl, X, V, P, f, L, Pf, PL, Q, PQ, edges, verts, pptr, pvel, ends, endv, tiles,
+      gbn, gbf, hyper, ohyper, ov, op, opf, gpos, tpos, prev, prop, blkt, blki, total;
+  int64_t sumPD = 0, sumP = 0, sumTilesMax = 0;
+  int64_t sumE = 0, sumPP = 0, sumPoly = 0, sumG = 0, sumGD = 0, sumD = 0, initBlocks = 0;
+};
+
+}  // namespace sepso
+
+struct sepso_lin;
+
+struct sepso_batch {
+  int n = 0;
+  std::vector<sepso::InstDesc> desc;
+  std::vector<int> n_vert;
+  std::vector<int32_t> h_pptr;  // polygon offsets of instance 0
+  std::vector<int64_t> path_off;
+  sepso::Layout lay{};
+  sepso::Pools pl{};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool broken = false;
+  sepso_tune tune{16, 256};
+  int tile_blocks = 0;
+  int frames_done = 0;
+  // pinned host mirrors
+  sepso::InstCtl* h_ctl = nullptr;
+  float* h_paths = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] no motion, [1] motion step first
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  sepso_lin* lin = nullptr;  // attached learned initializer (not owned)
+};
+
+struct sepso_ctx {
+  sepso_batch* b;
+};
+
+// Learned initializer: BF16 MLP 4100 -> 512 -> 512 -> 512 -> 320 with FP32
+// master weights and Adam state, activations for up to max_rows rows, and an
+// on-device training set of up to max_samples (input, target) rows.
+struct sepso_lin {
+  int max_rows = 0;
+  int64_t max_samples = 0, n_samples = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool broken = false;
+  int adam_t = 0;
+  float* W32[4];
+  float* b32[4];
+  uint16_t* W16[4];
+  float *mW[4], *vW[4], *mb[4], *vb[4];
+  float* gW[4];
+  float* gb[4];
+  uint16_t* X16;     // max_rows x kLinInPad
+  uint16_t* A16[3];  // max_rows x 512
+  float* Y;          // max_rows x 320
+  float* T;          // max_rows x 320
+  float* dY;
+  uint16_t* dY16;
+  float* dZ[3];
+  uint16_t* dZ16[3];
+  float* rowsq;
+  float* dloss;       // loss per training step
+  int32_t* eligible;  // max_rows
+  uint16_t* DX;       // max_samples x kLinInPad
+  float* DT;          // max_samples x 320
+  float* h_loss = nullptr;  // pinned, max_rows
+};
+
+namespace sepso {
+// Learned-initializer hooks used by the frame loop (lin.cpp).
+void lin_enqueue_proposals(sepso_lin* lin, sepso_batch* b);
+}  // namespace sepso

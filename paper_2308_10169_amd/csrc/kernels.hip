@@ -146,7 +146,8 @@ __global__ __launch_bounds__(256) void init_kernel(Pools pl, int frame_override,
   const int64_t PD = (int64_t)d.G * d.N * D;
   const int64_t e = (int64_t)bi.y + threadIdx.x;
   const int frame = frame_override >= 0 ? frame_override : ctl->frame;
-  const bool pi = use_prev && d.use_pi && ctl->have_prev;
+  const bool learned = use_prev && ctl->use_learned;
+  const bool pi = !learned && use_prev && d.use_pi && ctl->have_prev;
   if (e < PD) {
     const int i = (int)(e / D), dd = (int)(e - (int64_t)i * D);
     const int g = i / d.N, n = i - g * d.N;
@@ -157,10 +158,13 @@ __global__ __launch_bounds__(256) void init_kernel(Pools pl, int frame_override,
     const U4 rx = philox(c0, (uint32_t)frame, d.instance, TAG_INIT_X, d.seed_lo, d.seed_hi);
     const U4 rv = philox(c0, (uint32_t)frame, d.instance, TAG_INIT_V, d.seed_lo, d.seed_hi);
     float x = u01(rx.v[dd & 3]) * hi;
-    if (pi && n < d.n_pi) {
+    if ((pi || learned) && n < d.n_pi) {
+      // Priori Initialization around the previous plan, or around this
+      // group's learned proposal when the network supplied one
       const U4 rp = philox(c0, (uint32_t)frame, d.instance, TAG_PI, d.seed_lo, d.seed_hi);
       const float r = d.pi_radius;
-      x = clampf(pl.prev_path[d.dpo + dd] + (-r + u01(rp.v[dd & 3]) * (2.f * r)), 0.f, hi);
+      const float c = learned ? pl.proposal[d.gpo + g * D + dd] : pl.prev_path[d.dpo + dd];
+      x = clampf(c + (-r + u01(rp.v[dd & 3]) * (2.f * r)), 0.f, hi);
     }
     const float v = -vmax + u01(rv.v[dd & 3]) * (2.f * vmax);
     const int64_t o = d.xo + e;
@@ -395,8 +399,8 @@ __device__ void finish_iteration(const Pools& pl, const InstDesc& d, InstCtl* ct
 // particle; thread chunk c handles path segments [cK, cK+K) between points
 // cK .. cK+K (point 0 = start, W+1 = target, points past W+1 repeat the
 // target so that their segments have zero length and cross nothing).
-template <int K>
-__global__ __launch_bounds__(256) void step_kernel(Pools pl, int flags) {
+template <int K, bool FIT>
+__device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   __shared__ EdgeRec s_edge[kEdgeChunk];
   __shared__ int s_q[256];
   __shared__ float s_l[256];
@@ -486,12 +490,12 @@ __global__ __launch_bounds__(256) void step_kernel(Pools pl, int flags) {
       }
     }
   }
-  if (!(flags & STEP_FIT)) {
+  if (!FIT) {
     __threadfence();
     __syncthreads();
     if (t == 0) s_last = atomicAdd(&ctl->arrive, 1) == d.n_tiles - 1;
     __syncthreads();
-    if (s_last) finish_iteration(pl, d, ctl, k, pending, ctr, flags);
+    if (s_last) finish_iteration(pl, d, ctl, k, pending, ctr, flags & ~STEP_FIT);
     return;
   }
 
@@ -521,8 +525,10 @@ __global__ __launch_bounds__(256) void step_kernel(Pools pl, int flags) {
     }
     __syncthreads();
     if (active) {
+      EdgeRec nx = s_edge[0];
       for (int e = 0; e < ne; ++e) {
-        const EdgeRec r = s_edge[e];
+        const EdgeRec r = nx;
+        if (e + 1 < ne) nx = s_edge[e + 1];  // next record in flight while this one is used
         const int fl = __builtin_amdgcn_readfirstlane(r.flags);
         if (fl & EDGE_FIRST) {
           w0 = pack_seg_sides<K>(r.ax, r.ay, dx, ndy, nc);
@@ -635,25 +641,33 @@ void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev
 
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
 
+// One fused iteration (fitness path) and the update-only flush, as separate
+// kernels so that profiles separate them.
+template <int K>
+__global__ __launch_bounds__(256) void iter_kernel(Pools pl, int flags) {
+  iteration<K, true>(pl, flags);
+}
+template <int K>
+__global__ __launch_bounds__(256) void update_kernel(Pools pl, int flags) {
+  iteration<K, false>(pl, flags);
+}
+
+template <int K>
+static void launch_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s) {
+  if (flags & STEP_FIT)
+    hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
+  else
+    hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
+}
+
 void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s) {
   switch (K) {
-    case 4:
-      hipLaunchKernelGGL(step_kernel<4>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
-      break;
-    case 8:
-      hipLaunchKernelGGL(step_kernel<8>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
-      break;
-    case 12:
-      hipLaunchKernelGGL(step_kernel<12>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
-      break;
-    case 16:
-      hipLaunchKernelGGL(step_kernel<16>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
-      break;
-    case 24:
-      hipLaunchKernelGGL(step_kernel<24>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
-      break;
-    default:
-      break;
+    case 4: launch_k<4>(pl, n_blocks, threads, flags, s); break;
+    case 8: launch_k<8>(pl, n_blocks, threads, flags, s); break;
+    case 12: launch_k<12>(pl, n_blocks, threads, flags, s); break;
+    case 16: launch_k<16>(pl, n_blocks, threads, flags, s); break;
+    case 24: launch_k<24>(pl, n_blocks, threads, flags, s); break;
+    default: break;
   }
 }
 

@@ -1,0 +1,312 @@
+// Learned initializer (device code): occupancy raster of each instance's
+// map, a BF16 MLP (FP32 accumulation on gfx950 MFMA) that proposes one
+// initial path per group, its MSE backward pass and Adam with FP32 master
+// weights.  GEMMs run on v_mfma_f32_16x16x32_bf16.
+#include "common.h"
+#include "mlp.h"
+
+namespace sepso {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// Input features of instance i (row i of X): 64 x 64 occupancy (cell centre
+// inside any obstacle polygon, even-odd rule) followed by start and target
+// normalised by the map size; zero padding up to kLinInPad.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void raster_kernel(Pools pl, uint16_t* X, int ldx,
+                                                     int32_t* eligible) {
+  const int inst = blockIdx.x;
+  const InstDesc& d = pl.desc[inst];
+  const float2* verts = pl.verts + d.eo;
+  const int32_t* pp = pl.poly_ptr + d.plo;
+  uint16_t* row = X + (int64_t)inst * ldx;
+  for (int cell = threadIdx.x; cell < kRaster * kRaster; cell += blockDim.x) {
+    const int r = cell / kRaster, c = cell - r * kRaster;
+    const float px = (c + 0.5f) * d.width / kRaster, py = (r + 0.5f) * d.height / kRaster;
+    int inside = 0;
+    for (int q = 0; q < d.n_polys && !inside; ++q) {
+      const int v0 = pp[q], m = pp[q + 1] - v0;
+      int odd = 0;
+      for (int j = 0; j < m; ++j) {
+        const float2 a = verts[v0 + j], b = verts[v0 + (j + 1 == m ? 0 : j + 1)];
+        if ((a.y > py) != (b.y > py)) {
+          const float xc = a.x + (py - a.y) * (b.x - a.x) / (b.y - a.y);
+          if (px < xc) odd ^= 1;
+        }
+      }
+      inside = odd;
+    }
+    row[cell] = inside ? 0x3F80 : 0;  // 1.0 or 0.0
+  }
+  if (threadIdx.x < kLinInPad - kRaster * kRaster) {
+    const int j = threadIdx.x;
+    const float4 e = pl.ends[inst];
+    float v = 0.f;
+    if (j == 0) v = e.x / d.width;
+    if (j == 1) v = e.y / d.height;
+    if (j == 2) v = e.z / d.width;
+    if (j == 3) v = e.w / d.height;
+    row[kRaster * kRaster + j] = to_bf16(v);
+  }
+  if (threadIdx.x == 0) eligible[inst] = (d.G == kLinGroups && d.W == kLinW) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// C[M x N] = op(A)[M x K] * op(B)[K x N], BF16 in, FP32 accumulate.
+//   A_KM = false: A(m, k) = A[m*lda + k]   A_KM = true: A(m, k) = A[k*lda + m]
+//   B_KN = false: B(k, n) = B[n*ldb + k]   B_KN = true: B(k, n) = B[k*ldb + n]
+// Block tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA 16x16x32 tiles).
+// Requires K % 32 == 0; M % 8 == 0 when A_KM; N % 8 == 0 when B_KN.
+// ---------------------------------------------------------------------------
+template <bool A_KM, bool B_KN>
+__global__ __launch_bounds__(256) void gemm_kernel(const uint16_t* __restrict__ A, int lda,
+                                                   const uint16_t* __restrict__ B, int ldb, int M,
+                                                   int N, int K, Epi ep) {
+  constexpr int LDS = 40;  // padded row (k) length
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * LDS];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * LDS];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    if (!A_KM) {
+      const int row = t >> 2, kc = (t & 3) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (m0 + row < M) v = *reinterpret_cast<const uint4*>(A + (int64_t)(m0 + row) * lda + k0 + kc);
+      *reinterpret_cast<uint4*>(&As[row * LDS + kc]) = v;
+    } else {
+      const int kr = t >> 3, mc = (t & 7) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (m0 + mc < M) v = *reinterpret_cast<const uint4*>(A + (int64_t)(k0 + kr) * lda + m0 + mc);
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+      for (int i = 0; i < 8; ++i) As[(mc + i) * LDS + kr] = h[i];
+    }
+    if (!B_KN) {
+      const int row = t >> 2, kc = (t & 3) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (n0 + row < N) v = *reinterpret_cast<const uint4*>(B + (int64_t)(n0 + row) * ldb + k0 + kc);
+      *reinterpret_cast<uint4*>(&Bs[row * LDS + kc]) = v;
+    } else {
+      const int kr = t >> 3, nc = (t & 7) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (n0 + nc < N) v = *reinterpret_cast<const uint4*>(B + (int64_t)(k0 + kr) * ldb + n0 + nc);
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+      for (int i = 0; i < 8; ++i) Bs[(nc + i) * LDS + kr] = h[i];
+    }
+    __syncthreads();
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    bf16x8 a[2], b[2];
+    for (int i = 0; i < 2; ++i) {
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm + i * 16 + r16) * LDS + kq]);
+      b[i] = *reinterpret_cast<const bf16x8*>(&Bs[(wn + i * 16 + r16) * LDS + kq]);
+    }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // D layout: lane holds column (lane % 16), rows 4*(lane/16) .. +3
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row >= M || col >= N) continue;
+        float v = acc[i][j][r];
+        const int64_t o = (int64_t)row * ep.ldo + col;
+        switch (ep.mode) {
+          case EPI_BIAS_RELU_BF16:
+            v += ep.bias[col];
+            ep.out_bf16[o] = to_bf16(v > 0.f ? v : 0.f);
+            break;
+          case EPI_BIAS_F32:
+            ep.out_f32[o] = v + ep.bias[col];
+            break;
+          case EPI_F32:
+            ep.out_f32[o] = v;
+            break;
+          case EPI_MASK: {
+            const float dz = from_bf16(ep.mask[o]) > 0.f ? v : 0.f;
+            ep.out_f32[o] = dz;
+            ep.out_bf16[o] = to_bf16(dz);
+            break;
+          }
+        }
+      }
+}
+
+// dy = 2 (y - target) / (B * n) (FP32 and BF16) and per-row squared-error sums.
+__global__ __launch_bounds__(256) void loss_kernel(const float* y, const float* target, int B,
+                                                   int n, float* dy, uint16_t* dy16,
+                                                   float* row_sq) {
+  const int r = blockIdx.x;
+  __shared__ float s[256];
+  float acc = 0.f;
+  const float scale = 2.f / ((float)B * (float)n);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const int64_t o = (int64_t)r * n + j;
+    const float e = y[o] - target[o];
+    acc += e * e;
+    dy[o] = scale * e;
+    dy16[o] = to_bf16(scale * e);
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+    if (threadIdx.x < m) s[threadIdx.x] += s[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) row_sq[r] = s[0];
+}
+
+// Mean of the per-row squared errors (one block, fixed order).
+__global__ __launch_bounds__(256) void loss_sum_kernel(const float* row_sq, int B, float scale,
+                                                       float* out) {
+  __shared__ float s[256];
+  float acc = 0.f;
+  for (int r = threadIdx.x; r < B; r += blockDim.x) acc += row_sq[r];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+    if (threadIdx.x < m) s[threadIdx.x] += s[threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0] * scale;
+}
+
+// Training targets of instance i: its final group bests, normalised by the
+// map size (row i of T, Eq.(10) layout per group).
+__global__ __launch_bounds__(256) void targets_kernel(Pools pl, float* T, int ldt) {
+  const int inst = blockIdx.x;
+  const InstDesc& d = pl.desc[inst];
+  const int D = 2 * d.W;
+  for (int j = threadIdx.x; j < d.G * D && j < ldt; j += blockDim.x) {
+    const int dd = j % D;
+    T[(int64_t)inst * ldt + j] = pl.gbest_pos[d.gpo + j] / (dd < d.W ? d.width : d.height);
+  }
+}
+
+// Column sums of a B x n FP32 matrix (bias gradients), fixed order.
+__global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int n, float* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.f;
+  for (int r = 0; r < B; ++r) s += dz[(int64_t)r * n + j];
+  out[j] = s;
+}
+
+// Adam on FP32 master weights (rows x cols with `cols` real columns stored
+// at stride `ld`), refreshing the BF16 copy used by the GEMMs.
+__global__ __launch_bounds__(256) void adam_kernel(float* p, const float* g, float* m, float* v,
+                                                   uint16_t* p16, int64_t count, float lr,
+                                                   float b1, float b2, float eps, float c1,
+                                                   float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  if (p16) p16[i] = to_bf16(pi);
+}
+
+__global__ __launch_bounds__(256) void cvt_bf16_kernel(const float* p, uint16_t* p16, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p16[i] = to_bf16(p[i]);
+}
+
+// Accept the network's proposals: eligible instances with a finite output
+// get per-group initial paths (clamped to the map); others fall back.
+__global__ __launch_bounds__(256) void proposal_kernel(Pools pl, const float* Y, int ldy,
+                                                       const int32_t* eligible) {
+  const int inst = blockIdx.x;
+  const InstDesc& d = pl.desc[inst];
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) s_ok = eligible[inst];
+  __syncthreads();
+  const int D = 2 * d.W;
+  if (s_ok) {
+    for (int j = threadIdx.x; j < kLinOut; j += blockDim.x)
+      if (!isfinite(Y[(int64_t)inst * ldy + j])) atomicAnd(&s_ok, 0);
+  }
+  __syncthreads();
+  if (s_ok) {
+    for (int j = threadIdx.x; j < d.G * D; j += blockDim.x) {
+      const int dd = j % D;
+      const float hi = dd < d.W ? d.width : d.height;
+      float u = Y[(int64_t)inst * ldy + j];
+      u = u < 0.f ? 0.f : (u > 1.f ? 1.f : u);
+      pl.proposal[d.gpo + j] = u * hi;
+    }
+  }
+  if (threadIdx.x == 0) pl.ctl[inst].use_learned = s_ok;
+}
+
+// ---------------------------------------------------------------------------
+void launch_raster(const Pools& pl, int n_inst, uint16_t* X, int ldx, int32_t* eligible,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(raster_kernel, dim3(n_inst), dim3(256), 0, s, pl, X, ldx, eligible);
+}
+
+void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                 int M, int N, int K, const Epi& ep, hipStream_t s) {
+  const dim3 grid((N + 63) / 64, (M + 63) / 64);
+  if (!a_km && !b_kn)
+    hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+  else if (!a_km && b_kn)
+    hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+  else if (a_km && b_kn)
+    hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+  else
+    hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+}
+
+void launch_loss(const float* y, const float* target, int B, int n, float* dy, uint16_t* dy16,
+                 float* row_sq, hipStream_t s) {
+  hipLaunchKernelGGL(loss_kernel, dim3(B), dim3(256), 0, s, y, target, B, n, dy, dy16, row_sq);
+}
+
+void launch_loss_sum(const float* row_sq, int B, float scale, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, row_sq, B, scale, out);
+}
+
+void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t s) {
+  hipLaunchKernelGGL(targets_kernel, dim3(n_inst), dim3(256), 0, s, pl, T, ldt);
+}
+
+void launch_colsum(const float* dz, int B, int n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dz, B, n, out);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, uint16_t* p16, int64_t count,
+                 float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, g, m, v,
+                     p16, count, lr, b1, b2, eps, c1, c2);
+}
+
+void launch_cvt_bf16(const float* p, uint16_t* p16, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(cvt_bf16_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, p16, count);
+}
+
+void launch_proposal(const Pools& pl, int n_inst, const float* Y, int ldy, const int32_t* eligible,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(proposal_kernel, dim3(n_inst), dim3(256), 0, s, pl, Y, ldy, eligible);
+}
+
+}  // namespace sepso

@@ -182,6 +182,42 @@ def static_map(seed, S=100.0, n_rects=4, side=(5.0, 20.0), start=(5.0, 5.0),
     return make_map(S, S, rects, s, t)
 
 
+def random_static_maps(n, seed, S=100.0, n_rects=4, side=(5.0, 20.0), margin=1.0):
+    """n static maps of the single-plan shape with random start and target
+    (learned-initializer training and held-out sets), drawn vectorised:
+    start/target uniform in [2, S-2]^2, rectangles as in static_map, any
+    rectangle containing an endpoint (with margin) redrawn."""
+    rng = np.random.default_rng(seed)
+    st = snap(rng.uniform(2.0, S - 2.0, size=(n, 2, 2)))
+    wh = snap(rng.uniform(*side, size=(n, n_rects, 2)))
+    xy = snap(rng.uniform(0.0, 1.0, size=(n, n_rects, 2)) * (S - wh))
+    for _ in range(1000):
+        bad = np.zeros((n, n_rects), bool)
+        for e in range(2):
+            p = st[:, e, None, :]
+            bad |= np.all((xy - margin <= p) & (p <= xy + wh + margin), axis=2)
+        if not bad.any():
+            break
+        k = int(bad.sum())
+        wh[bad] = snap(rng.uniform(*side, size=(k, 2)))
+        xy[bad] = snap(rng.uniform(0.0, 1.0, size=(k, 2)) * (S - wh[bad]))
+    maps = []
+    for i in range(n):
+        rects = [[[x, y], [x + w, y], [x + w, y + h], [x, y + h]]
+                 for (x, y), (w, h) in zip(xy[i], wh[i])]
+        maps.append(make_map(S, S, rects, st[i, 0], st[i, 1]))
+    return maps
+
+
+def learned_swarm(seed=0, instance=0, iters=50):
+    """Planner shape the learned initializer serves: 8 groups x 32
+    particles x 20 waypoints with the Table hyper8 rows, 1e3 per crossing,
+    no truncation; proposals are perturbed by +-5% of the map."""
+    hyper = HYPER8[np.arange(8)]
+    return SwarmSpec(8, 32, 20, iters, hyper, alpha=1e3, beta=1, seed=seed, instance=instance,
+                     pi_gamma=0.25, pi_radius=5.0)
+
+
 def dynamic_map(seed, S=366.0, n_static=10, n_moving=20, side=(10.0, 40.0), vmax=2.0):
     """Paper-shaped dynamic scene: S x S map, static and moving rectangles
     (velocities uniform in +-vmax cells/frame per axis, bouncing off the

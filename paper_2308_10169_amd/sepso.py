@@ -101,6 +101,21 @@ def _load():
     L.sepso_batch_profile_step.argtypes = [vp, C.c_int32, fp]
     L.sepso_autotune.argtypes = [vp, C.POINTER(CTune)]
     L.sepso_batch_work.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.sepso_batch_history.argtypes = [vp, fp]
+    L.sepso_lin_param_count.restype = C.c_int64
+    L.sepso_lin_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.POINTER(sz)]
+    L.sepso_lin_create.argtypes = [C.c_int32, C.c_int64, C.c_uint64, vp, sz, vp, C.POINTER(vp)]
+    L.sepso_lin_destroy.argtypes = [vp]
+    L.sepso_lin_set_weights.argtypes = [vp, fp]
+    L.sepso_lin_get_weights.argtypes = [vp, fp]
+    L.sepso_lin_forward.argtypes = [vp, fp, C.c_int32, fp]
+    L.sepso_lin_grads.argtypes = [vp, fp, fp, C.c_int32, fp, fp]
+    L.sepso_lin_collect.argtypes = [vp, vp]
+    L.sepso_lin_samples.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.sepso_lin_train.argtypes = [vp, C.c_int32, C.c_int32, C.c_float, fp]
+    L.sepso_lin_features.argtypes = [vp, vp, fp]
+    L.sepso_lin_attach.argtypes = [vp, vp]
+    L.sepso_lin_attach_ctx.argtypes = [vp, vp]
     _lib, _torch = L, torch
     return L
 
@@ -322,3 +337,102 @@ class BatchPlanner:
         a, b = C.c_double(), C.c_double()
         _check(_lib.sepso_batch_work(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def history(self):
+        """Tbest fitness after each iteration of the last frame (n, 64)."""
+        out = np.zeros((self.n, 64), np.float32)
+        _check(_lib.sepso_batch_history(self.h, out.ctypes.data_as(fp)))
+        return out
+
+    def attach(self, lin):
+        _check(_lib.sepso_lin_attach(self.h, lin.h if lin is not None else None))
+
+
+LIN_IN, LIN_OUT, LIN_HIDDEN = 4100, 320, 512
+
+
+class LearnedInit:
+    """Learned initializer (sepso_lin): BF16 MLP trained and run by the
+    library's MFMA kernels."""
+
+    def __init__(self, max_rows=1024, max_samples=0, seed=0, stream=None):
+        L = _load()
+        torch = _torch
+        nbytes = C.c_size_t()
+        _check(L.sepso_lin_workspace_bytes(int(max_rows), int(max_samples), C.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = C.c_void_p()
+        _check(L.sepso_lin_create(int(max_rows), int(max_samples), int(seed),
+                                  C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.max_rows = max_rows
+        self.n_params = int(L.sepso_lin_param_count())
+
+    def close(self):
+        if self.h:
+            _check(_lib.sepso_lin_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self):
+        w = np.zeros(self.n_params, np.float32)
+        _check(_lib.sepso_lin_get_weights(self.h, w.ctypes.data_as(fp)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(_lib.sepso_lin_set_weights(self.h, w.ctypes.data_as(fp)))
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, LIN_IN)
+        y = np.zeros((len(x), LIN_OUT), np.float32)
+        _check(_lib.sepso_lin_forward(self.h, x.ctypes.data_as(fp), len(x), y.ctypes.data_as(fp)))
+        return y
+
+    def grads(self, x, t):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, LIN_IN)
+        t = np.ascontiguousarray(t, dtype=np.float32).reshape(-1, LIN_OUT)
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_float()
+        _check(_lib.sepso_lin_grads(self.h, x.ctypes.data_as(fp), t.ctypes.data_as(fp), len(x),
+                                    C.byref(loss), g.ctypes.data_as(fp)))
+        return loss.value, g
+
+    def collect(self, batch):
+        _check(_lib.sepso_lin_collect(self.h, batch.h))
+
+    def samples(self):
+        n = C.c_int64()
+        _check(_lib.sepso_lin_samples(self.h, C.byref(n)))
+        return n.value
+
+    def train(self, steps, batch=256, lr=1e-3):
+        loss = np.zeros(steps, np.float32)
+        _check(_lib.sepso_lin_train(self.h, int(steps), int(batch), float(lr),
+                                    loss.ctypes.data_as(fp)))
+        return loss
+
+    def features(self, batch):
+        out = np.zeros((batch.n, LIN_IN), np.float32)
+        _check(_lib.sepso_lin_features(self.h, batch.h, out.ctypes.data_as(fp)))
+        return out
+
+
+def split_params(flat):
+    """Flat parameter vector -> ([W1..W4], [b1..b4]) views (out, in)."""
+    sizes = [LIN_IN, LIN_HIDDEN, LIN_HIDDEN, LIN_HIDDEN, LIN_OUT]
+    W, b, o = [], [], 0
+    for l in range(4):
+        n_in, n_out = sizes[l], sizes[l + 1]
+        W.append(flat[o:o + n_in * n_out].reshape(n_out, n_in))
+        o += n_in * n_out
+        b.append(flat[o:o + n_out])
+        o += n_out
+    return W, b

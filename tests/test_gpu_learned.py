@@ -1,0 +1,104 @@
+"""Learned initializer on the GPU: BF16 MFMA forward and backward against the
+FP64 oracle (which rounds to BF16 at the same storage points), the raster
+features, and the gain over the plain planner on held-out maps.
+
+Tolerances: outputs and per-tensor gradients rel-L2 <= 1e-2 and cosine
+>= 0.999 (BF16 storage, FP32 vs FP64 accumulation order)."""
+import numpy as np
+import pytest
+
+from oracle import pyorc as orc
+from paper_2308_10169_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [4100, 512, 512, 512, 320]
+
+
+@pytest.fixture(scope="module")
+def sp():
+    from paper_2308_10169_amd import sepso
+    sepso.lib()
+    return sepso
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 4100), np.float32)
+    x[:, :4096] = rng.random((n, 4096)) < 0.15
+    x[:, 4096:] = rng.uniform(0, 1, (n, 4))
+    t = rng.uniform(0, 1, (n, 320)).astype(np.float32)
+    return x, t
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _cos(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def test_forward_matches_oracle(sp):
+    lin = sp.LearnedInit(max_rows=64, seed=3)
+    w = lin.get_weights()
+    W, b = sp.split_params(w.astype(np.float64))
+    rng = np.random.default_rng(0)
+    b = [rng.normal(0, 0.05, v.shape) for v in b]  # non-zero biases
+    flat = np.concatenate([np.concatenate([W[l].ravel(), b[l]]) for l in range(4)])
+    lin.set_weights(flat.astype(np.float32))
+    W, b = sp.split_params(lin.get_weights().astype(np.float64))
+    x, _ = _inputs(40, 1)  # ragged row count (not a multiple of 32)
+    y = lin.forward(x)
+    ref = orc.mlp(SIZES, W, b, x.astype(np.float64), round=True, grads=False)["y"]
+    assert _rel(y, ref) <= 1e-2 and _cos(y, ref) >= 0.999
+    lin.close()
+
+
+def test_gradients_match_oracle(sp):
+    lin = sp.LearnedInit(max_rows=64, seed=5)
+    W, b = sp.split_params(lin.get_weights().astype(np.float64))
+    x, t = _inputs(64, 2)
+    loss, g = lin.grads(x, t)
+    ref = orc.mlp(SIZES, W, b, x.astype(np.float64), target=t.astype(np.float64), round=True)
+    assert abs(loss - ref["loss"]) <= 1e-2 * ref["loss"]
+    gW, gb = sp.split_params(g.astype(np.float64))
+    for l in range(4):
+        for got, want in ((gW[l], ref["gW"][l]), (gb[l], ref["gb"][l])):
+            assert _rel(got, want) <= 1e-2, (l, _rel(got, want))
+            assert _cos(got, want) >= 0.999, (l, _cos(got, want))
+    lin.close()
+
+
+def test_raster_features_match_oracle(sp):
+    maps = I.random_static_maps(24, seed=11)
+    sws = [I.learned_swarm(seed=1, instance=i) for i in range(24)]
+    bp = sp.BatchPlanner(maps, sws)
+    lin = sp.LearnedInit(max_rows=32, seed=0)
+    feats = lin.features(bp)
+    for i, m in enumerate(maps):
+        r = orc.raster(m, 64).ravel()
+        assert np.array_equal(feats[i, :4096], r.astype(np.float32))
+        e = np.array([m.start[0] / m.width, m.start[1] / m.height,
+                      m.target[0] / m.width, m.target[1] / m.height])
+        # BF16 of the FP32 quotient vs of the exact one: equal up to one BF16 step
+        assert np.all(np.abs(feats[i, 4096:] - orc.bf16(e)) <= 2.0 ** -8 * np.abs(e))
+    lin.close()
+    bp.close()
+
+
+def test_learned_start_beats_plain_planner(sp):
+    # The planner generates its own training set, the network is trained on
+    # the GPU, and on held-out maps the learned start reaches the plain
+    # planner's final cost in fewer iterations.
+    from paper_2308_10169_amd import learned
+    lin = sp.LearnedInit(max_rows=4096, max_samples=8192, seed=0)
+    n = learned.generate(lin, 8192, seed=7)
+    assert n == 8192
+    loss = lin.train(600, batch=256, lr=1e-3)
+    assert loss[-20:].mean() < 0.5 * loss[:20].mean()
+    ev = learned.evaluate(lin, n_maps=256, seed=3_000_000)
+    print("learned vs plain", ev)
+    assert ev["median_iters_learned"] < ev["median_iters_plain"]
+    assert ev["first_iter_cost_learned"] < ev["first_iter_cost_plain"]
+    lin.close()

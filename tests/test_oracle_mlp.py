@@ -1,0 +1,90 @@
+"""Pins of the learned-initializer oracle (FP64 MLP and occupancy raster)
+against library routines, finite differences and closed forms -- CPU only."""
+import numpy as np
+import torch
+
+from paper_2308_10169_amd import inputs as I
+
+
+def _net(sizes, seed=0, scale=0.5):
+    rng = np.random.default_rng(seed)
+    W = [rng.normal(0, scale / np.sqrt(sizes[l]), (sizes[l + 1], sizes[l])) for l in range(len(sizes) - 1)]
+    b = [rng.normal(0, 0.1, sizes[l + 1]) for l in range(len(sizes) - 1)]
+    return W, b
+
+
+def test_bf16_round_matches_torch(orc):
+    rng = np.random.default_rng(0)
+    v = np.concatenate([rng.normal(0, 1, 4000), rng.normal(0, 1e-3, 1000),
+                        rng.uniform(-300, 300, 1000)]).astype(np.float32)
+    # exact ties: 1 + odd multiples of 2^-8 (halfway between BF16 neighbours)
+    v = np.concatenate([v, (1.0 + (2 * np.arange(50) + 1) * 2.0 ** -8).astype(np.float32)])
+    want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    got = orc.bf16(v.astype(np.float64))
+    assert np.array_equal(got, want)
+
+
+def test_forward_matches_numpy_without_rounding(orc):
+    sizes = [9, 7, 6, 4]
+    W, b = _net(sizes)
+    x = np.random.default_rng(1).normal(0, 1, (5, 9))
+    r = orc.mlp(sizes, W, b, x, round=False, grads=False)
+    h = x
+    for l in range(3):
+        h = h @ W[l].T + b[l]
+        if l < 2:
+            h = np.maximum(h, 0.0)
+    assert np.allclose(r["y"], h, rtol=1e-13, atol=1e-13)
+
+
+def test_backward_matches_finite_differences(orc):
+    sizes = [6, 5, 4, 3]
+    W, b = _net(sizes, seed=2, scale=1.5)
+    rng = np.random.default_rng(3)
+    x = rng.normal(0, 1, (4, 6))
+    t = rng.normal(0, 1, (4, 3))
+    r = orc.mlp(sizes, W, b, x, target=t, round=False)
+    h = 1e-6
+    for l in range(3):
+        for arr, g in ((W[l], r["gW"][l]), (b[l], r["gb"][l])):
+            it = np.nditer(arr, flags=["multi_index"])
+            for _ in it:
+                idx = it.multi_index
+                old = arr[idx]
+                arr[idx] = old + h
+                lp = orc.mlp(sizes, W, b, x, target=t, round=False, grads=False)["loss"]
+                arr[idx] = old - h
+                lm = orc.mlp(sizes, W, b, x, target=t, round=False, grads=False)["loss"]
+                arr[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - g[idx]) <= 1e-6 * max(1.0, abs(fd)), (l, idx, fd, g[idx])
+
+
+def test_rounding_changes_little(orc):
+    sizes = [32, 16, 16, 8]
+    W, b = _net(sizes, seed=4)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 1, (8, 32))
+    t = rng.uniform(0, 1, (8, 8))
+    a = orc.mlp(sizes, W, b, x, target=t, round=False)
+    c = orc.mlp(sizes, W, b, x, target=t, round=True)
+    assert abs(a["loss"] - c["loss"]) <= 2e-2 * a["loss"]
+    for l in range(3):
+        rel = np.linalg.norm(a["gW"][l] - c["gW"][l]) / np.linalg.norm(a["gW"][l])
+        assert rel < 3e-2
+
+
+def test_raster_of_rectangle_and_u_shape(orc):
+    box = [[20.0, 30.0], [60.0, 30.0], [60.0, 50.0], [20.0, 50.0]]
+    spec = I.make_map(100.0, 100.0, [box], (1, 1), (99, 99))
+    r = orc.raster(spec, 64)
+    cx = (np.arange(64) + 0.5) * 100.0 / 64
+    want = ((cx[None, :] > 20) & (cx[None, :] < 60) & (cx[:, None] > 30) & (cx[:, None] < 50))
+    assert np.array_equal(r.astype(bool), want)
+    U = [[20, 20], [80, 20], [80, 80], [60, 80], [60, 40], [40, 40], [40, 80], [20, 80]]
+    spec = I.make_map(100.0, 100.0, [U], (1, 1), (99, 99))
+    r = orc.raster(spec, 50)  # cell centres at 1, 3, ..., 99
+    c = np.arange(50) * 2 + 1.0
+    inside = lambda x, y: (20 < x < 80 and 20 < y < 80) and not (40 < x < 60 and y > 40)
+    want = np.array([[inside(x, y) for x in c] for y in c])
+    assert np.array_equal(r.astype(bool), want)
