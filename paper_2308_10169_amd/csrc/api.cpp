@@ -127,7 +127,6 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
       d.eo = (int32_t)L.sumE;
       d.plo = (int32_t)L.sumPP;
       d.pvo = (int32_t)L.sumPoly;
-      d.to = (int32_t)L.sumTilesMax;
       d.go = (int32_t)L.sumG;
       d.gpo = (int32_t)L.sumGD;
       d.dpo = (int32_t)L.sumD;
@@ -166,7 +165,6 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   L.pvel = take(8 * L.sumPoly);
   L.ends = take(16 * n);
   L.endv = take(16 * n);
-  L.tiles = take(sizeof(TileBest) * L.sumTilesMax);
   L.gbn = take(4 * L.sumG);
   L.gbf = take(4 * L.sumG);
   L.hyper = take(24 * L.sumG);
@@ -184,12 +182,18 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   return L;
 }
 
-int default_K(int W) {
-  // fewest threads per particle without much idle segment work
-  if (W + 1 <= 12) return 12;
-  if (W + 1 <= 16) return 16;
-  if (W + 1 <= 24) return 24;
-  return 16;
+// A tile shape suits a batch when a thread's K segments touch at most three
+// particles (K <= 2(W+2) for the shortest path) and the block's positions
+// fit the LDS buffer (B*K <= 4096 slots).
+bool tune_ok(int K, int B, int w_min) {
+  return step_supported(K) && (B == 64 || B == 128 || B == 256) && K <= 2 * (w_min + 2) &&
+         B * K <= 4096;
+}
+
+sepso_tune default_tune(int w_min) {
+  for (int K : {16, 12, 8, 4})
+    if (tune_ok(K, 128, w_min)) return sepso_tune{K, 128};
+  return sepso_tune{4, 128};
 }
 
 }  // namespace
@@ -213,25 +217,32 @@ sepso_status hip_fail(sepso_batch* b, hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(b, _e, what); \
   } while (0)
 
-// Tile geometry for the current tune; fills desc tile fields and the
-// block -> (instance, tile) table.
+// Block geometry for the current tune: each block of the fused iteration
+// takes ppb = floor(B*K / (W+2)) consecutive particles (their W+2 stream
+// slots fill the block's B*K); fills the desc fields, the LDS sizing and the
+// block -> (instance, first particle) table, heaviest blocks first (the
+// dispatcher hands blocks out in order).
 void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
   const int K = b->tune.seg_per_thread, B = b->tune.block_threads;
   blk->clear();
   std::vector<std::pair<double, int>> order;
+  int buf = 8 * 256, ppb_max = 1;
   for (int i = 0; i < b->n; ++i) {
     InstDesc& d = b->desc[i];
-    d.C = (d.W + 1 + K - 1) / K;
-    d.ppt = std::max(1, B / d.C);
-    d.tpg = (d.N + d.ppt - 1) / d.ppt;
-    d.n_tiles = d.G * d.tpg;
-    order.push_back({(double)d.n_edges * d.C, i});
+    d.ppb = std::max(1, (B * K) / (d.W + 2));
+    d.n_blocks = (d.G * d.N + d.ppb - 1) / d.ppb;
+    buf = std::max(buf, d.ppb * 2 * d.W);
+    ppb_max = std::max(ppb_max, d.ppb);
+    order.push_back({(double)d.n_edges * d.ppb * (d.W + 2), i});
   }
-  // heavy tiles first: the dispatcher hands blocks out in order
+  b->pl.buf_floats = (buf + 7) & ~7;
+  b->pl.ppb_max = ppb_max;
   std::stable_sort(order.begin(), order.end(),
                    [](const std::pair<double, int>& a, const std::pair<double, int>& c) { return a.first > c.first; });
-  for (auto& o : order)
-    for (int t = 0; t < b->desc[o.second].n_tiles; ++t) blk->push_back(make_int2(o.second, t));
+  for (auto& o : order) {
+    const InstDesc& d = b->desc[o.second];
+    for (int t = 0; t < d.n_blocks; ++t) blk->push_back(make_int2(o.second, t * d.ppb));
+  }
   b->tile_blocks = (int)blk->size();
 }
 
@@ -280,21 +291,15 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
     st = check_swarm(&sw[i], i);
     if (st != SEPSO_OK) return st;
   }
-  sepso_tune tn{0, 256};
+  int w_min = kMaxW;
+  for (int i = 0; i < n; ++i) w_min = std::min(w_min, sw[i].waypoints);
+  sepso_tune tn = default_tune(w_min);
   if (tune) {
     tn = *tune;
-    if (!step_supported(tn.seg_per_thread))
-      return fail(SEPSO_E_ARG, "seg_per_thread must be one of 4, 8, 12, 16, 24");
-    if (tn.block_threads != 64 && tn.block_threads != 128 && tn.block_threads != 256)
-      return fail(SEPSO_E_ARG, "block_threads must be 64, 128 or 256");
-  } else {
-    int wmax = 0;
-    for (int i = 0; i < n; ++i) wmax = std::max(wmax, sw[i].waypoints);
-    tn.seg_per_thread = default_K(wmax);
-  }
-  for (int i = 0; i < n; ++i) {
-    const int C = (sw[i].waypoints + tn.seg_per_thread) / tn.seg_per_thread;
-    if (C > tn.block_threads) return fail(SEPSO_E_ARG, "instance %d: path too long for the tile", i);
+    if (!tune_ok(tn.seg_per_thread, tn.block_threads, w_min))
+      return fail(SEPSO_E_ARG,
+                  "tune: seg_per_thread in {4,8,12,16,24} and <= 2*(waypoints+2), block_threads in "
+                  "{64,128,256}, product <= 4096");
   }
   if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(SEPSO_E_ARG, "workspace not 256-byte aligned");
@@ -322,6 +327,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
   }
   const Layout& L = b->lay;
   Pools& pl = b->pl;
+  pl.n_inst = n;
   pl.desc = at<InstDesc>(b, L.desc);
   pl.ctl = at<InstCtl>(b, L.ctl);
   pl.X = at<float>(b, L.X);
@@ -339,7 +345,6 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
   pl.poly_vel = at<float2>(b, L.pvel);
   pl.ends = at<float4>(b, L.ends);
   pl.end_vel = at<float4>(b, L.endv);
-  pl.tiles = at<TileBest>(b, L.tiles);
   pl.gbest_n = at<int32_t>(b, L.gbn);
   pl.gbest_f = at<float>(b, L.gbf);
   pl.hyper = at<float>(b, L.hyper);
@@ -791,16 +796,15 @@ sepso_status sepso_batch_work(sepso_batch* b, double* tests, double* elems) {
 sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
   sepso_status st = usable(b);
   if (st != SEPSO_OK) return st;
-  const int Ks[] = {8, 12, 16, 24};
+  const int Ks[] = {4, 8, 12, 16, 24};
   const int Bs[] = {64, 128, 256};
   sepso_tune win = b->tune;
   float win_ms = INFINITY;
   for (int K : Ks)
     for (int B : Bs) {
-      bool ok = true;
-      for (auto& d : b->desc)
-        if ((d.W + K) / K > B) ok = false;
-      if (!ok) continue;
+      int w_min = kMaxW;
+      for (auto& d : b->desc) w_min = std::min(w_min, d.W);
+      if (!tune_ok(K, B, w_min)) continue;
       b->tune = sepso_tune{K, B};
       st = upload_tiles(b);
       if (st != SEPSO_OK) return st;

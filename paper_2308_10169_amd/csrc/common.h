@@ -46,10 +46,8 @@ static_assert(sizeof(EdgeRec) == 32, "EdgeRec is 32 bytes");
 struct InstDesc {
   int32_t G, N, W, T;
   int32_t n_edges, n_polys;
-  int32_t C;             // chunks (threads) per particle = ceil((W+1)/K)
-  int32_t ppt;           // particles per tile
-  int32_t tpg;           // tiles per group
-  int32_t n_tiles;       // G * tpg
+  int32_t ppb;           // particles per block of the fused iteration
+  int32_t n_blocks;      // ceil(G*N / ppb)
   float width, height;
   float alpha; int32_t beta;
   int32_t use_pi, n_pi;  // PI on, particles per group that get it
@@ -62,7 +60,6 @@ struct InstDesc {
   int32_t eo;            // edge records (n_edges) and vertices (n_edges float2)
   int32_t plo;           // poly_ptr pool (n_polys+1)
   int32_t pvo;           // poly_vel pool (n_polys float2)
-  int32_t to;            // tile partials (n_tiles)
   int32_t go;            // group pools: G (gbest_n/f, outer Pbest fitness), G*6 hyper, G*3 outer
   int32_t gpo;           // gbest positions: G*2W
   int32_t dpo;           // per-instance path pools (Tbest, previous plan): 2W
@@ -87,11 +84,6 @@ struct InstCtl {
   float hist[kHist];     // Tbest fitness after iterations 1..k (ring)
 };
 
-// Partial argmin of one tile (group slice).
-struct TileBest {
-  float f;
-  int32_t n;
-};
 
 }  // namespace sepso
 
@@ -99,6 +91,9 @@ namespace sepso {
 
 // Device pointers of every pool in the workspace (passed by value).
 struct Pools {
+  int32_t n_inst;
+  int32_t buf_floats;  // fused-iteration LDS buffer (positions / edge chunk), floats
+  int32_t ppb_max;     // largest particles-per-block over the instances
   const InstDesc* desc;
   InstCtl* ctl;
   float *X, *V, *P;
@@ -110,7 +105,6 @@ struct Pools {
   float2* poly_vel;
   float4* ends;      // start.xy, target.xy per instance
   float4* end_vel;   // per instance
-  TileBest* tiles;
   int32_t* gbest_n;
   float* gbest_f;
   float* hyper;      // G*6 per instance
@@ -122,7 +116,7 @@ struct Pools {
   float* tbest_pos;  // 2W
   float* prev_path;  // 2W
   float* proposal;   // G*2W learned initial path per group (layout of gbest_pos)
-  const int2* blk_tiles;  // fused-iteration block -> (instance, tile)
+  const int2* blk_tiles;  // fused-iteration block -> (instance, first particle)
   const int2* blk_init;   // init block -> (instance, first element)
 };
 

@@ -27,8 +27,7 @@ inline sepso_status fail(sepso_status st, const char* fmt, ...) {
 
 // Workspace carve-up of a batch (byte offsets of every pool).
 struct Layout {
-  size_t desc, ctl, X, V, P, f, L, Pf, PL, Q, PQ, edges, verts, pptr, pvel, ends, endv, tiles,
-      gbn, gbf, hyper, ohyper, ov, op, opf, gpos, tpos, prev, prop, blkt, blki, total;
+  size_t desc, ctl, X, V, P, f, L, Pf, PL, Q, PQ, edges, verts, pptr, pvel, ends, endv, gbn, gbf, hyper, ohyper, ov, op, opf, gpos, tpos, prev, prop, blkt, blki, total;
   int64_t sumPD = 0, sumP = 0, sumTilesMax = 0;
   int64_t sumE = 0, sumPP = 0, sumPoly = 0, sumG = 0, sumGD = 0, sumD = 0, initBlocks = 0;
 };

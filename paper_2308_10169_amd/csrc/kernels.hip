@@ -306,35 +306,63 @@ __device__ void hsef_step(const Pools& pl, const InstDesc& d, InstCtl* ctl, cons
   if (t == 0) ctl->epoch_ctr += 1;
 }
 
-// Work of the last block of an instance to finish a launch.
-__device__ void finish_iteration(const Pools& pl, const InstDesc& d, InstCtl* ctl, int k,
-                                 int pending, uint32_t ctr, int flags) {
+
+// Bests of one instance after an iteration (Algorithm 1, "update P, G, T"):
+// Gbest_g = argmin of the Pbest fitness over group g (lowest index on ties),
+// Tbest = argmin over groups; then Auto Truncation, the online outer step
+// and the control-block advance.  One block per instance, after the tile
+// kernels have finished (kernel boundary = visibility, no fences in tiles).
+__global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   __shared__ float s_gf[kMaxG];
   __shared__ int s_gn[kMaxG];
+  __shared__ float s_rf[256];
+  __shared__ int s_rn[256];
   __shared__ int s_tg, s_stop, s_at, s_q;
+  const int inst = blockIdx.x;
+  const InstDesc& d = pl.desc[inst];
+  InstCtl* ctl = pl.ctl + inst;
+  if ((flags & STEP_FRAME) && ctl->done) return;
+  const int k = ctl->k, pending = ctl->pending;
+  const uint32_t ctr = ctl->ctr;
   const int t = threadIdx.x, G = d.G, N = d.N, D = 2 * d.W;
-  if (!(flags & STEP_FIT)) {  // update-only launch
+  __syncthreads();  // every thread has read the control block before it advances
+  if (!(flags & STEP_FIT)) {  // after an update-only launch
     if (t == 0) {
       ctl->ctr = ctr + (pending ? 1u : 0u);
       ctl->pending = 0;
-      ctl->arrive = 0;
     }
     return;
   }
-  const TileBest* tb = pl.tiles + d.to;
-  for (int g = t; g < G; g += blockDim.x) {
-    TileBest b = tb[g * d.tpg];
-    for (int j = 1; j < d.tpg; ++j) {
-      const TileBest c = tb[g * d.tpg + j];
-      if (better(c.f, c.n, b.f, b.n)) b = c;
+  const float* Pf = pl.Pf + d.po;
+  for (int g = 0; g < G; ++g) {
+    float bf = INFINITY;
+    int bn = 0x7fffffff;
+    for (int n = t; n < N; n += blockDim.x) {
+      const float f = Pf[g * N + n];
+      if (better(f, n, bf, bn)) {
+        bf = f;
+        bn = n;
+      }
     }
-    if (b.n >= N) b.n = 0;
-    pl.gbest_n[d.go + g] = b.n;
-    pl.gbest_f[d.go + g] = b.f;
-    s_gn[g] = b.n;
-    s_gf[g] = b.f;
+    s_rf[t] = bf;
+    s_rn[t] = bn;
+    __syncthreads();
+    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+      if (t < m && better(s_rf[t + m], s_rn[t + m], s_rf[t], s_rn[t])) {
+        s_rf[t] = s_rf[t + m];
+        s_rn[t] = s_rn[t + m];
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      const int n = s_rn[0] < N ? s_rn[0] : 0;
+      s_gn[g] = n;
+      s_gf[g] = s_rf[0];
+      pl.gbest_n[d.go + g] = n;
+      pl.gbest_f[d.go + g] = s_rf[0];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (t == 0) {
     int tg = 0;
     for (int g = 1; g < G; ++g)
@@ -391,144 +419,163 @@ __device__ void finish_iteration(const Pools& pl, const InstDesc& d, InstCtl* ct
       ctl->pending = 1;
       ctl->ctr = ctr_new;
     }
-    ctl->arrive = 0;
   }
 }
 
-// Thread layout: block = tile of `ppt` particles of one group, C threads per
-// particle; thread chunk c handles path segments [cK, cK+K) between points
-// cK .. cK+K (point 0 = start, W+1 = target, points past W+1 repeat the
-// target so that their segments have zero length and cross nothing).
+// ---------------------------------------------------------------------------
+// Fused iteration over one block = ppb consecutive particles of an instance
+// (flat index g*N + n, possibly spanning groups).
+//
+//  A. previous iteration's update, elementwise and coalesced over the
+//     block's contiguous (particle, coordinate) range; new positions also
+//     go to LDS;
+//  B. the block's paths are laid end to end as a stream of points (start,
+//     W waypoints, target per particle); thread t takes the K segments
+//     starting at stream slot tK.  A slot joining one particle's target to
+//     the next one's start is not a path segment and is masked out; a
+//     thread's K segments belong to at most three particles ("pieces");
+//  C. crossings of the K segments with every obstacle edge (edges staged in
+//     LDS, reusing the position buffer): per edge, one packed side word of
+//     the edge's end vertex against the K segment lines and one of the K+1
+//     points against the edge line; crossing bits = both straddle;
+//  D. per-particle Q and L summed in thread order (deterministic), fitness
+//     and Pbest; improved particles' positions go to P.
+// ---------------------------------------------------------------------------
 template <int K, bool FIT>
 __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
-  __shared__ EdgeRec s_edge[kEdgeChunk];
-  __shared__ int s_q[256];
-  __shared__ float s_l[256];
-  __shared__ float s_pf[256];
-  __shared__ int s_imp[256];
-  __shared__ int s_last;
+  // dynamic LDS: positions / edge chunk | r1..r3 per particle | Pbest flags |
+  // per-thread piece counts and lengths
+  extern __shared__ __attribute__((aligned(16))) float s_dyn[];
+  float* s_buf = s_dyn;
+  float* s_r = s_buf + pl.buf_floats;
+  int* s_imp = reinterpret_cast<int*>(s_r + 3 * pl.ppb_max);
+  int* s_q = s_imp + pl.ppb_max;
+  float* s_l = reinterpret_cast<float*>(s_q + 3 * blockDim.x);
 
   const int2 bt = pl.blk_tiles[blockIdx.x];
-  const int inst = bt.x, tile = bt.y;
+  const int inst = bt.x, p0 = bt.y;
   const InstDesc& d = pl.desc[inst];
   InstCtl* ctl = pl.ctl + inst;
   if ((flags & STEP_FRAME) && ctl->done) return;
   const int k = ctl->k, pending = ctl->pending;
   const uint32_t ctr = ctl->ctr;
-  const int N = d.N, W = d.W, D = 2 * W, C = d.C;
-  const int g = tile / d.tpg;
-  const int n0 = (tile - g * d.tpg) * d.ppt;
-  const int t = threadIdx.x;
-  const int slot = t / C, c = t - slot * C;
-  const int n = n0 + slot;
-  const bool active = slot < d.ppt && n < N;
-  const int i = g * N + n;
-  float* X = pl.X + d.xo + (int64_t)i * D;
-  float* V = pl.V + d.xo + (int64_t)i * D;
+  const int N = d.N, W = d.W, D = 2 * W, S = W + 2;
+  const int np = min(d.ppb, d.G * N - p0);  // particles in this block
+  const int t = threadIdx.x, B = blockDim.x;
 
-  // ---- 1. path points of this chunk, with the pending update applied ------
-  float px[K + 1], py[K + 1], vx[K + 1], vy[K + 1];
-  if (active) {
-    const float4 ends = pl.ends[inst];
-    float w = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, vmx = 0.f, vmy = 0.f;
-    const float* Pp = pl.P + d.xo + (int64_t)i * D;
-    const float* Gb = pl.gbest_pos + d.gpo + g * D;
+  // ---- A. update (coalesced) ----------------------------------------------
+  if (pending) {
+    for (int j = t; j < np; j += B) {
+      const U4 r = philox((uint32_t)(p0 + j), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
+      s_r[3 * j + 0] = u01(r.v[0]);
+      s_r[3 * j + 1] = u01(r.v[1]);
+      s_r[3 * j + 2] = u01(r.v[2]);
+    }
+    __syncthreads();
+  }
+  {
+    float* X = pl.X + d.xo + (int64_t)p0 * D;
+    float* V = pl.V + d.xo + (int64_t)p0 * D;
+    const float* Pp = pl.P + d.xo + (int64_t)p0 * D;
+    const float* Gb = pl.gbest_pos + d.gpo;
     const float* Tb = pl.tbest_pos + d.dpo;
-    if (pending) {
-      const float* h = pl.hyper + d.go * 6 + g * 6;
-      const int kk = k < d.T ? k : d.T;
-      w = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
-      const U4 r = philox((uint32_t)i, ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
-      a1 = h[0] * u01(r.v[0]);
-      a2 = h[1] * u01(r.v[1]);
-      a3 = h[2] * u01(r.v[2]);
-      vmx = h[5] * d.width * 0.5f;
-      vmy = h[5] * d.height * 0.5f;
-    }
-#pragma unroll
-    for (int s = 0; s <= K; ++s) {
-      int j = c * K + s;
-      j = j > W + 1 ? W + 1 : j;
-      float x, y, u = 0.f, v = 0.f;
-      if (j == 0) {
-        x = ends.x;
-        y = ends.y;
-      } else if (j == W + 1) {
-        x = ends.z;
-        y = ends.w;
-      } else {
-        const int q = j - 1;
-        x = X[q];
-        y = X[W + q];
-        if (pending) {
-          u = V[q];
-          v = V[W + q];
-          u = w * u + a1 * (Pp[q] - x) + a2 * (Gb[q] - x) + a3 * (Tb[q] - x);
-          v = w * v + a1 * (Pp[W + q] - y) + a2 * (Gb[W + q] - y) + a3 * (Tb[W + q] - y);
-          u = clampf(u, -vmx, vmx);
-          v = clampf(v, -vmy, vmy);
-          x = clampf(x + u, 0.f, d.width);
-          y = clampf(y + v, 0.f, d.height);
-        }
+    const float* hy = pl.hyper + d.go * 6;
+    const int kk = k < d.T ? k : d.T;
+    const int nel = np * D;
+    for (int e = t; e < nel; e += B) {
+      float x = X[e];
+      if (pending) {
+        const int j = e / D, dd = e - j * D, g = (p0 + j) / N;
+        const float* h = hy + g * 6;
+        const float w = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
+        const float hi = dd < W ? d.width : d.height;
+        const float vmax = h[5] * hi * 0.5f;
+        const float a1 = h[0] * s_r[3 * j], a2 = h[1] * s_r[3 * j + 1], a3 = h[2] * s_r[3 * j + 2];
+        float v = V[e];
+        v = w * v + a1 * (Pp[e] - x) + a2 * (Gb[g * D + dd] - x) + a3 * (Tb[dd] - x);
+        v = clampf(v, -vmax, vmax);
+        x = clampf(x + v, 0.f, hi);
+        X[e] = x;
+        V[e] = v;
       }
-      px[s] = x;
-      py[s] = y;
-      vx[s] = u;
-      vy[s] = v;
+      if (FIT) s_buf[e] = x;
     }
   }
-  __syncthreads();  // every thread has read the old positions of its points
-  if (active && pending) {
-#pragma unroll
-    for (int s = 1; s <= K; ++s) {
-      const int j = c * K + s;
-      if (j <= W) {
-        X[j - 1] = px[s];
-        X[W + j - 1] = py[s];
-        V[j - 1] = vx[s];
-        V[W + j - 1] = vy[s];
-      }
-    }
-  }
-  if (!FIT) {
-    __threadfence();
-    __syncthreads();
-    if (t == 0) s_last = atomicAdd(&ctl->arrive, 1) == d.n_tiles - 1;
-    __syncthreads();
-    if (s_last) finish_iteration(pl, d, ctl, k, pending, ctr, flags & ~STEP_FIT);
-    return;
-  }
+  if (!FIT) return;
+  __syncthreads();
 
-  // ---- 2. segment lines and lengths ----------------------------------------
+  // ---- B. this thread's K segments of the point stream ---------------------
+  const int n_pts = np * S;               // stream points
+  const bool active = t * K < n_pts - 1;  // owns at least one slot
+  const int jf = (t * K) / S;             // first particle touched
+  const float4 ends = pl.ends[inst];
+  float px[K + 1], py[K + 1];
+#pragma unroll
+  for (int s = 0; s <= K; ++s) {
+    int q = t * K + s;
+    q = q < n_pts ? q : n_pts - 1;
+    const int j = q / S, idx = q - j * S;
+    float x, y;
+    if (idx == 0) {
+      x = ends.x;
+      y = ends.y;
+    } else if (idx == S - 1) {
+      x = ends.z;
+      y = ends.w;
+    } else {
+      x = s_buf[j * D + idx - 1];
+      y = s_buf[j * D + W + idx - 1];
+    }
+    px[s] = x;
+    py[s] = y;
+  }
   float dx[K], ndy[K], nc[K];
-  float len = 0.f;
+  uint32_t mk0 = 0, mk1 = 0, mk2 = 0;
+  float l0 = 0.f, l1 = 0.f, l2 = 0.f;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
     const float ddx = px[s + 1] - px[s], ddy = py[s + 1] - py[s];
     dx[s] = ddx;
     ndy[s] = -ddy;
     nc[s] = fmaf(ddy, px[s], -(ddx * py[s]));
-    if (c * K + s <= W) len += sqrtf(ddx * ddx + ddy * ddy);
+    const int m = t * K + s;  // slot between points m and m+1
+    const int jm = m / S;
+    if (m < n_pts - 1 && m - jm * S != S - 1) {
+      const float len = sqrtf(ddx * ddx + ddy * ddy);
+      const uint32_t bit = 1u << (K - 1 - s);
+      const int pc = jm - jf;
+      if (pc == 0) {
+        mk0 |= bit;
+        l0 += len;
+      } else if (pc == 1) {
+        mk1 |= bit;
+        l1 += len;
+      } else {
+        mk2 |= bit;
+        l2 += len;
+      }
+    }
   }
+  __syncthreads();  // positions consumed: s_buf now stages edges
 
-  // ---- 3. crossings: segments x obstacle edges (edges staged in LDS) --------
-  int cnt = 0;
+  // ---- C. crossings ----------------------------------------------------------
+  int c0 = 0, c1 = 0, c2 = 0;
   uint32_t w0 = 0, wp = 0;
   const EdgeRec* er = pl.edges + d.eo;
-  for (int e0 = 0; e0 < d.n_edges; e0 += kEdgeChunk) {
-    const int ne = d.n_edges - e0 < kEdgeChunk ? d.n_edges - e0 : kEdgeChunk;
-    __syncthreads();
+  EdgeRec* s_edge = reinterpret_cast<EdgeRec*>(s_buf);
+  const int chunk = pl.buf_floats / 8;  // edge records per LDS pass
+  for (int e0 = 0; e0 < d.n_edges; e0 += chunk) {
+    const int ne = d.n_edges - e0 < chunk ? d.n_edges - e0 : chunk;
+    if (e0 > 0) __syncthreads();
     {
       const float4* src = reinterpret_cast<const float4*>(er + e0);
-      float4* dst = reinterpret_cast<float4*>(s_edge);
-      for (int q = t; q < ne * 2; q += blockDim.x) dst[q] = src[q];
+      float4* dst = reinterpret_cast<float4*>(s_buf);
+      for (int q = t; q < ne * 2; q += B) dst[q] = src[q];
     }
     __syncthreads();
     if (active) {
-      EdgeRec nx = s_edge[0];
       for (int e = 0; e < ne; ++e) {
-        const EdgeRec r = nx;
-        if (e + 1 < ne) nx = s_edge[e + 1];  // next record in flight while this one is used
+        const EdgeRec r = s_edge[e];
         const int fl = __builtin_amdgcn_readfirstlane(r.flags);
         if (fl & EDGE_FIRST) {
           w0 = pack_seg_sides<K>(r.ax, r.ay, dx, ndy, nc);
@@ -548,98 +595,65 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
         }
         // segment s straddles the edge's line iff points s and s+1 differ;
         // the edge straddles segment s's line iff its two vertices differ.
-        cnt += __popc((wp ^ wn) & (ew ^ (ew >> 1)));
+        const uint32_t x = (wp ^ wn) & (ew ^ (ew >> 1));
+        c0 += __popc(x & mk0);
+        c1 += __popc(x & mk1);
+        c2 += __popc(x & mk2);
         wp = wn;
       }
     }
   }
 
-  // ---- 4. per-particle fitness and Pbest ------------------------------------
-  s_q[t] = cnt;
-  s_l[t] = len;
+  // ---- D. per-particle fitness and Pbest -------------------------------------
+  s_q[3 * t + 0] = c0;
+  s_q[3 * t + 1] = c1;
+  s_q[3 * t + 2] = c2;
+  s_l[3 * t + 0] = l0;
+  s_l[3 * t + 1] = l1;
+  s_l[3 * t + 2] = l2;
   __syncthreads();
-  if (active && c == 0) {
+  for (int j = t; j < np; j += B) {
+    const int t_lo = (j * S) / K, t_hi = (j * S + W) / K;  // threads holding its W+1 slots
     int q = 0;
     float L = 0.f;
-    for (int cc = 0; cc < C; ++cc) {
-      q += s_q[t + cc];
-      L += s_l[t + cc];
+    for (int tt = t_lo; tt <= t_hi; ++tt) {
+      const int pc = j - (tt * K) / S;
+      q += s_q[3 * tt + pc];
+      L += s_l[3 * tt + pc];
     }
     const float qf = (float)q;
     float pw = 1.f;
     for (int b = 0; b < d.beta; ++b) pw *= qf;
     const float fv = L + d.alpha * pw;
-    const int64_t po = d.po + i;
+    const int64_t po = d.po + p0 + j;
     pl.f[po] = fv;
     pl.L[po] = L;
     pl.Q[po] = q;
-    float pf = pl.Pf[po];
     const float fc = isfinite(fv) ? fv : INFINITY;
-    const int imp = fc < pf;
+    const int imp = fc < pl.Pf[po];
     if (imp) {
       pl.Pf[po] = fc;
       pl.PL[po] = L;
       pl.PQ[po] = q;
-      pf = fc;
     }
-    s_imp[slot] = imp;
-    s_pf[slot] = pf;
+    s_imp[j] = imp;
   }
   __syncthreads();
-  if (active && s_imp[slot]) {
-    float* Pw = pl.P + d.xo + (int64_t)i * D;
+  if (active) {
+    float* Pw = pl.P + d.xo + (int64_t)p0 * D;
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
-      const int j = c * K + s;
-      if (j <= W) {
-        Pw[j - 1] = px[s];
-        Pw[W + j - 1] = py[s];
+      const int q = t * K + s;  // points owned by this thread
+      if (q < n_pts) {
+        const int j = q / S, idx = q - j * S;
+        if (idx >= 1 && idx <= W && s_imp[j]) {
+          Pw[j * D + idx - 1] = px[s];
+          Pw[j * D + W + idx - 1] = py[s];
+        }
       }
     }
   }
-
-  // ---- 5. tile argmin (lowest index on ties) --------------------------------
-  if (t < 64) {
-    float bf = INFINITY;
-    int bn = 0x7fffffff;
-    for (int sl = t; sl < d.ppt; sl += 64) {
-      if (n0 + sl < N && better(s_pf[sl], n0 + sl, bf, bn)) {
-        bf = s_pf[sl];
-        bn = n0 + sl;
-      }
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      const float of = __shfl_xor(bf, m);
-      const int on = __shfl_xor(bn, m);
-      if (better(of, on, bf, bn)) {
-        bf = of;
-        bn = on;
-      }
-    }
-    if (t == 0) pl.tiles[d.to + tile] = TileBest{bf, bn};
-  }
-
-  // ---- 6. the last block of this instance reduces the bests -----------------
-  __threadfence();
-  __syncthreads();
-  if (t == 0) s_last = atomicAdd(&ctl->arrive, 1) == d.n_tiles - 1;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  finish_iteration(pl, d, ctl, k, pending, ctr, flags);
 }
-
-// ---------------------------------------------------------------------------
-void launch_geom(const Pools& pl, int n_inst, int move, hipStream_t s) {
-  hipLaunchKernelGGL(geom_kernel, dim3(n_inst), dim3(256), 0, s, pl, move);
-}
-
-void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev, hipStream_t s) {
-  hipLaunchKernelGGL(init_kernel, dim3(n_blocks), dim3(256), 0, s, pl, frame_override, use_prev);
-}
-
-bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
 
 // One fused iteration (fitness path) and the update-only flush, as separate
 // kernels so that profiles separate them.
@@ -652,12 +666,30 @@ __global__ __launch_bounds__(256) void update_kernel(Pools pl, int flags) {
   iteration<K, false>(pl, flags);
 }
 
+// ---------------------------------------------------------------------------
+void launch_geom(const Pools& pl, int n_inst, int move, hipStream_t s) {
+  hipLaunchKernelGGL(geom_kernel, dim3(n_inst), dim3(256), 0, s, pl, move);
+}
+
+void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev, hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel, dim3(n_blocks), dim3(256), 0, s, pl, frame_override, use_prev);
+}
+
+size_t iter_lds_bytes(const Pools& pl, int threads) {
+  return 4 * ((size_t)pl.buf_floats + 4 * (size_t)pl.ppb_max + 6 * (size_t)threads);
+}
+
+bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
+
 template <int K>
 static void launch_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s) {
   if (flags & STEP_FIT)
-    hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
+    hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads), s,
+                       pl, flags);
   else
-    hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), 0, s, pl, flags);
+    hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads),
+                       s, pl, flags);
+  hipLaunchKernelGGL(reduce_kernel, dim3(pl.n_inst), dim3(256), 0, s, pl, flags);
 }
 
 void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s) {
