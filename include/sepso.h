@@ -153,6 +153,11 @@ sepso_status sepso_get_geometry(sepso_ctx* ctx, float* verts, float* endpoints);
  * launches (HIP events on the handle's stream).  Advances the swarm. */
 sepso_status sepso_profile_step(sepso_ctx* ctx, int32_t n, float* avg_ms);
 
+/* Tile shape of the fused iteration: set explicitly, or chosen by timing
+ * candidates (the swarm is re-initialised for frame 0 afterwards). */
+sepso_status sepso_set_tune(sepso_ctx* ctx, const sepso_tune* tune);
+sepso_status sepso_autotune_ctx(sepso_ctx* ctx, sepso_tune* best);
+
 /* ---- batch of independent instances ------------------------------------ */
 sepso_status sepso_batch_workspace_bytes(const sepso_map* maps, const sepso_swarm* swarms,
                                          int32_t n_inst, size_t* bytes);

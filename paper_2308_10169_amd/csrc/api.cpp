@@ -829,4 +829,21 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
   return SEPSO_OK;
 }
 
+sepso_status sepso_set_tune(sepso_ctx* ctx, const sepso_tune* tune) {
+  if (!ctx || !tune) return fail(SEPSO_E_ARG, "ctx/tune NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (!tune_ok(tune->seg_per_thread, tune->block_threads, b->desc[0].W))
+    return fail(SEPSO_E_ARG, "tune: seg_per_thread in {4,8,12,16,24} and <= 2*(waypoints+2), "
+                             "block_threads in {64,128,256}, product <= 4096");
+  b->tune = *tune;
+  return upload_tiles(b);
+}
+
+sepso_status sepso_autotune_ctx(sepso_ctx* ctx, sepso_tune* best) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  return sepso_autotune(ctx->b, best);
+}
+
 }  // extern "C"

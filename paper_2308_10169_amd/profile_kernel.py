@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--instances", type=int, default=1024)
     ap.add_argument("--tune", default="16,64", help="K,block_threads or 'auto'")
     ap.add_argument("--launches", type=int, default=20)
+    ap.add_argument("--warmup-launches", type=int, default=20)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a plain device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
     from paper_2308_10169_amd import sepso
     specs, sws = workload(args.workload, args.instances)
@@ -52,7 +55,7 @@ def main():
     if tune is None:
         tune = bp.autotune()
     tests, elems = bp.work()
-    bp.profile_step(2)
+    bp.profile_step(args.warmup_launches)  # clocks settle before the measured launches
     ms = bp.profile_step(args.launches)
     rate = tests / (ms * 1e-3)
     print(json.dumps(dict(workload=args.workload, instances=len(specs), tune=tune,
@@ -61,6 +64,15 @@ def main():
                           tflops_alg=F_TEST * rate / 1e12, frac_peak=F_TEST * rate / PEAK_FP32)),
           flush=True)
     bp.close()
+    if args.copy_mb > 0:
+        import torch
+        n = args.copy_mb << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=n, copies=3)), flush=True)
 
 
 if __name__ == "__main__":

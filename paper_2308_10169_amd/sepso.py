@@ -90,6 +90,8 @@ def _load():
     L.sepso_set_state.argtypes = [vp, C.POINTER(CState)]
     L.sepso_get_geometry.argtypes = [vp, fp, fp]
     L.sepso_profile_step.argtypes = [vp, C.c_int32, fp]
+    L.sepso_set_tune.argtypes = [vp, C.POINTER(CTune)]
+    L.sepso_autotune_ctx.argtypes = [vp, C.POINTER(CTune)]
     L.sepso_batch_workspace_bytes.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm), C.c_int32,
                                               C.POINTER(sz)]
     L.sepso_batch_create.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm), C.c_int32, vp, sz, vp,
@@ -262,6 +264,14 @@ class Planner:
         ms = C.c_float()
         _check(_lib.sepso_profile_step(self.h, int(n), C.byref(ms)))
         return ms.value
+
+    def set_tune(self, K, B):
+        _check(_lib.sepso_set_tune(self.h, C.byref(CTune(int(K), int(B)))))
+
+    def autotune(self):
+        t = CTune()
+        _check(_lib.sepso_autotune_ctx(self.h, C.byref(t)))
+        return (t.seg_per_thread, t.block_threads)
 
 
 class BatchPlanner:
