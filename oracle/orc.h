@@ -23,7 +23,8 @@ extern "C" {
 
 /* Philox counter tags (which stream a draw belongs to). */
 enum { ORC_TAG_UPDATE = 0, ORC_TAG_INIT_X = 1, ORC_TAG_INIT_V = 2, ORC_TAG_PI = 3,
-       ORC_TAG_HSEF = 4, ORC_TAG_LEARNED = 5 };
+       ORC_TAG_HSEF = 4, ORC_TAG_LEARNED = 5, ORC_TAG_EVOLVE = 6, ORC_TAG_EVOLVE_X = 7,
+       ORC_TAG_EVOLVE_V = 8 };
 
 /* Philox4x32 with 10 rounds, written from Salmon et al. (SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -101,8 +102,9 @@ void orc_hsef_step(orc_swarm* s, orc_hsef* h);
 
 /* Auto Truncation decision after iteration k (1-based); hist[i] = Tbest
  * fitness after iteration i+1. mode 1: population std over the last `window`
- * values < delta; mode 2: hist[k-window] - hist[k] < delta*max(1,|hist[k]|).
- * Both require the current best path to be collision-free. */
+ * values < delta; mode 2: hist[k-window] - hist[k] < delta*max(1,|hist[k]|);
+ * mode 3: as mode 1 over the last min(k, window) values once k >= 2.
+ * All require the current best path to be collision-free. */
 int32_t orc_at_check(const double* hist, int32_t k, int32_t mode, int32_t window,
                      double delta, int32_t q_tbest);
 
@@ -130,6 +132,33 @@ typedef struct orc_frame_result {
 void orc_plan_frame(orc_swarm* s, orc_hsef* h, const orc_map* m, const orc_frame_cfg* c,
                     int32_t frame, const double* prev_path, double* out_path, double* hist,
                     orc_frame_result* res);
+
+/* Evolution phase, Sec. "Hierarchical Self-evolving Framework" / Eq.(9):
+ * the higher-level swarm H-SEPSO (Gh groups of Nh particles, hyper-parameters
+ * h_hyper, Table hyper8) moves over whole lower-level hyper matrices (Dh =
+ * 6*G_L values, row-major (G_L, 6)); column c of a row is boxed to
+ * [lo[c], hi[c]].  Its fitness is the lower level's lowest fitness value
+ * after a full run, supplied by the caller.  Random streams: counter
+ * (c0, c1, 0, tag) with tags EVOLVE_X / EVOLVE_V (init, c1 = 0) and EVOLVE
+ * (move, c0 = H particle, c1 = ctr).  All arrays owned by the caller. */
+typedef struct orc_evolve {
+  int32_t Gh, Nh, Dh, E;     /* E: evolutions of the inertia schedule, Eq.(6) */
+  const double* h_hyper;     /* Gh*6 */
+  const double* lo;          /* 6: per-column lower bound */
+  const double* hi;          /* 6: per-column upper bound */
+  uint64_t seed;
+  double *X, *V, *P;         /* Gh*Nh*Dh */
+  double* Pf;                /* Gh*Nh */
+  int32_t* gbest_n;          /* Gh */
+  double* gbest_f;           /* Gh */
+  int32_t tb_g, tb_n;
+  double tb_f;
+  int32_t k;                 /* evolutions done */
+  uint32_t ctr;              /* random stream position of the move */
+} orc_evolve;
+void orc_evolve_init(orc_evolve* h);
+/* bests from lfv (Gh*Nh values) then the move of Eq.(6)-(8) */
+void orc_evolve_step(orc_evolve* h, const double* lfv);
 
 #ifdef __cplusplus
 }

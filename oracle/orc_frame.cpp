@@ -97,14 +97,21 @@ void orc_hsef_step(orc_swarm* s, orc_hsef* h) {
 int32_t orc_at_check(const double* hist, int32_t k, int32_t mode, int32_t window, double delta,
                      int32_t q_tbest) {
   if (mode == 0 || q_tbest != 0 || window < 1) return 0;
-  if (mode == 1) {
-    if (k < window) return 0;
+  if (mode == 1 || mode == 3) {
+    // mode 1: the full window must have elapsed; mode 3: the window is
+    // whatever has elapsed (at least two values), capped at `window`
+    int32_t w = window;
+    if (mode == 1 && k < window) return 0;
+    if (mode == 3) {
+      if (k < 2) return 0;
+      w = k < window ? k : window;
+    }
     double mean = 0.0;
-    for (int32_t i = k - window; i < k; ++i) mean += hist[i];
-    mean /= (double)window;
+    for (int32_t i = k - w; i < k; ++i) mean += hist[i];
+    mean /= (double)w;
     double var = 0.0;
-    for (int32_t i = k - window; i < k; ++i) var += (hist[i] - mean) * (hist[i] - mean);
-    var /= (double)window;
+    for (int32_t i = k - w; i < k; ++i) var += (hist[i] - mean) * (hist[i] - mean);
+    var /= (double)w;
     return std::sqrt(var) < delta ? 1 : 0;
   }
   if (mode == 2) {

@@ -12,9 +12,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
-SOURCES = ["orc_core.cpp", "orc_frame.cpp", "orc_mlp.cpp"]
+SOURCES = ["orc_core.cpp", "orc_frame.cpp", "orc_mlp.cpp", "orc_evolve.cpp"]
 
-TAG_UPDATE, TAG_INIT_X, TAG_INIT_V, TAG_PI, TAG_HSEF, TAG_LEARNED = range(6)
+(TAG_UPDATE, TAG_INIT_X, TAG_INIT_V, TAG_PI, TAG_HSEF, TAG_LEARNED, TAG_EVOLVE, TAG_EVOLVE_X,
+ TAG_EVOLVE_V) = range(9)
 
 
 def build(force: bool = True) -> str:
@@ -69,6 +70,14 @@ class OrcFrameResult(C.Structure):
                 ("iters", C.c_int32), ("truncated", C.c_int32)]
 
 
+class OrcEvolve(C.Structure):
+    _fields_ = [("Gh", C.c_int32), ("Nh", C.c_int32), ("Dh", C.c_int32), ("E", C.c_int32),
+                ("h_hyper", dp), ("lo", dp), ("hi", dp), ("seed", C.c_uint64),
+                ("X", dp), ("V", dp), ("P", dp), ("Pf", dp), ("gbest_n", ip), ("gbest_f", dp),
+                ("tb_g", C.c_int32), ("tb_n", C.c_int32), ("tb_f", C.c_double),
+                ("k", C.c_int32), ("ctr", C.c_uint32)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -98,6 +107,8 @@ def lib():
         L.orc_plan_frame.argtypes = [C.POINTER(OrcSwarm), C.POINTER(OrcHsef), C.POINTER(OrcMap),
                                      C.POINTER(OrcFrameCfg), C.c_int32, dp, dp, dp,
                                      C.POINTER(OrcFrameResult)]
+        L.orc_evolve_init.argtypes = [C.POINTER(OrcEvolve)]
+        L.orc_evolve_step.argtypes = [C.POINTER(OrcEvolve), dp]
         _lib = L
     return _lib
 
@@ -335,3 +346,76 @@ def raster(spec, n=64):
     L.orc_raster(float(spec.width), float(spec.height), len(ptr) - 1, _p(ptr, ip), _p(verts),
                  int(n), _p(out))
     return out
+
+
+# Default per-column box of the evolved hyper-parameters (C1, C2, C3, w_init,
+# w_end, V_limit); the paper does not state one.
+EVOLVE_LO = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+EVOLVE_HI = np.array([3.0, 3.0, 3.0, 1.0, 1.0, 1.0])
+
+
+class Evolve:
+    """Evolution phase (Sec. "Hierarchical Self-evolving Framework", Eq.(9)).
+
+    The higher level (H-SEPSO) lives in liborc; each H particle's fitness is
+    the lowest fitness value of a full lower-level run (one oracle frame with
+    truncation, priori initialisation and online evolution switched off) of
+    its own persistent lower-level swarm, instance i, with the particle's
+    values as the lower level's (G_L, 6) hyper matrix."""
+
+    def __init__(self, spec, lsw, h_groups=8, h_particles=4, evolutions=500, seed=0,
+                 h_hyper=None, lo=None, hi=None):
+        import dataclasses
+        from paper_2308_10169_amd import inputs as I
+        Gl = lsw.groups
+        self.Gh, self.Nh, self.Dh = h_groups, h_particles, 6 * Gl
+        n = h_groups * h_particles
+        hh = I.HYPER8[np.arange(h_groups) % 8] if h_hyper is None else h_hyper
+        self.h_hyper = np.ascontiguousarray(hh, dtype=np.float64).reshape(h_groups, 6).copy()
+        self.lo = np.ascontiguousarray(EVOLVE_LO if lo is None else lo, dtype=np.float64).copy()
+        self.hi = np.ascontiguousarray(EVOLVE_HI if hi is None else hi, dtype=np.float64).copy()
+        z = lambda *sh: np.zeros(sh, np.float64)
+        self.X, self.V, self.P = z(n, self.Dh), z(n, self.Dh), z(n, self.Dh)
+        self.Pf = np.full(n, np.inf)
+        self.gbest_n = np.zeros(h_groups, np.int32)
+        self.gbest_f = np.full(h_groups, np.inf)
+        self.h = OrcEvolve(h_groups, h_particles, self.Dh, evolutions, _p(self.h_hyper),
+                           _p(self.lo), _p(self.hi), int(seed), _p(self.X), _p(self.V), _p(self.P),
+                           _p(self.Pf), _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0,
+                           float("inf"), 0, 0)
+        lib().orc_evolve_init(C.byref(self.h))
+        self.map = Map(spec)
+        self.lower = []
+        for i in range(n):
+            sw = dataclasses.replace(lsw, instance=i, use_pi=0, at_mode=0, hsef_every=0)
+            self.lower.append(Swarm(sw, spec.width, spec.height))
+        self.evolution = 0
+
+    k = property(lambda self: self.h.k)
+    ctr = property(lambda self: self.h.ctr)
+    tbest = property(lambda self: (self.h.tb_g, self.h.tb_n, self.h.tb_f))
+
+    def lfv(self, hyper_rows=None):
+        """Lowest fitness value of every H particle's lower-level run at the
+        current evolution (hyper_rows overrides the H positions)."""
+        src = self.X if hyper_rows is None else hyper_rows
+        out = np.empty(len(self.lower))
+        for i, sw in enumerate(self.lower):
+            sw.hyper[:] = src[i].reshape(sw.G, 6)
+            out[i] = sw.plan_frame(self.map, self.evolution)["cost"]
+        return out
+
+    def step(self, lfv):
+        v = np.ascontiguousarray(lfv, dtype=np.float64)
+        lib().orc_evolve_step(C.byref(self.h), _p(v))
+
+    def evolve(self, n=1, hyper_cast=None):
+        """n evolutions; hyper_cast maps the positions handed to the lower
+        level (e.g. to FP32).  Returns the per-evolution total-best LFV."""
+        curve = []
+        for _ in range(n):
+            rows = self.X if hyper_cast is None else hyper_cast(self.X)
+            self.step(self.lfv(rows))
+            self.evolution += 1
+            curve.append(self.h.tb_f)
+        return np.array(curve)

@@ -27,6 +27,20 @@ def test_at_mode2_relative_improvement(orc):
     assert orc.at_check(flat, 5, 2, 5, 1e-3, 0) == 0  # needs k > window
 
 
+def test_at_mode3_growing_window(orc):
+    # std over the last min(k, TW) values once two exist
+    hist = np.array([430.0, 424.0, 421.0, 420.5, 420.4] + [420.4] * 30)
+    # k = 2: std(430, 424) = 3 < 10 -> stop;  k = 1: never
+    assert orc.at_check(hist, 1, 3, 20, 10.0, 0) == 0
+    assert orc.at_check(hist, 2, 3, 20, 10.0, 0) == 1
+    assert orc.at_check(hist, 2, 3, 20, 2.9, 0) == 0
+    assert orc.at_check(hist, 2, 3, 20, 10.0, 1) == 0  # collision -> keep going
+    # beyond TW values the window is capped: k = 30 sees only the flat tail
+    assert orc.at_check(hist, 30, 3, 20, 1e-9, 0) == 1
+    wide = np.r_[np.full(10, 400.0), np.full(10, 440.0)]  # std 20 over 20 values
+    assert orc.at_check(wide, 20, 3, 20, 20.5, 0) == 1 and orc.at_check(wide, 20, 3, 20, 19.5, 0) == 0
+
+
 def _dyn_swarm(orc, spec, **kw):
     sw = I.dynamic_swarm(spec.scale, seed=2, particles=24, waypoints=6, **kw)
     return orc.Swarm(sw, spec.width, spec.height)
