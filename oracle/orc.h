@@ -24,7 +24,8 @@ extern "C" {
 /* Philox counter tags (which stream a draw belongs to). */
 enum { ORC_TAG_UPDATE = 0, ORC_TAG_INIT_X = 1, ORC_TAG_INIT_V = 2, ORC_TAG_PI = 3,
        ORC_TAG_HSEF = 4, ORC_TAG_LEARNED = 5, ORC_TAG_EVOLVE = 6, ORC_TAG_EVOLVE_X = 7,
-       ORC_TAG_EVOLVE_V = 8 };
+       ORC_TAG_EVOLVE_V = 8, ORC_TAG_BF_UPDATE = 9, ORC_TAG_BF_INIT_X = 10,
+       ORC_TAG_BF_INIT_V = 11 };
 
 /* Philox4x32 with 10 rounds, written from Salmon et al. (SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -159,6 +160,29 @@ typedef struct orc_evolve {
 void orc_evolve_init(orc_evolve* h);
 /* bests from lfv (Gh*Nh values) then the move of Eq.(6)-(8) */
 void orc_evolve_step(orc_evolve* h, const double* lfv);
+
+/* Benchmark-function workload (Table BFs): DTPSO over [lo, hi]^D on one of
+ * the four functions.  Random streams: counter (c0, c1, 0, tag), tags
+ * BF_INIT_X / BF_INIT_V (c0 = 4-value block of the flat index, c1 = 0) and
+ * BF_UPDATE (c0 = particle, c1 = ctr). */
+enum { ORC_BF_SPHERE = 1, ORC_BF_ROSENBROCK = 2, ORC_BF_RASTRIGIN = 3, ORC_BF_GRIEWANK = 4 };
+double orc_bf_value(int32_t func, int32_t D, const double* x);
+typedef struct orc_bf {
+  int32_t func, G, N, D, T;
+  double lo, hi;
+  const double* hyper;       /* G*6 (Table hyper8 rows) */
+  uint64_t seed;
+  double *X, *V, *P;         /* G*N*D */
+  double *f, *Pf;            /* G*N */
+  int32_t* gbest_n;          /* G */
+  double* gbest_f;           /* G */
+  int32_t tb_g, tb_n;
+  double tb_f;
+  int32_t k;
+  uint32_t ctr;
+} orc_bf;
+void orc_bf_init(orc_bf* s);
+void orc_bf_step(orc_bf* s);  /* evaluate, bests, move (Algorithm 1) */
 
 #ifdef __cplusplus
 }

@@ -12,10 +12,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
-SOURCES = ["orc_core.cpp", "orc_frame.cpp", "orc_mlp.cpp", "orc_evolve.cpp"]
+SOURCES = ["orc_core.cpp", "orc_frame.cpp", "orc_mlp.cpp", "orc_evolve.cpp", "orc_bf.cpp"]
 
 (TAG_UPDATE, TAG_INIT_X, TAG_INIT_V, TAG_PI, TAG_HSEF, TAG_LEARNED, TAG_EVOLVE, TAG_EVOLVE_X,
- TAG_EVOLVE_V) = range(9)
+ TAG_EVOLVE_V, TAG_BF_UPDATE, TAG_BF_INIT_X, TAG_BF_INIT_V) = range(12)
+BF_SPHERE, BF_ROSENBROCK, BF_RASTRIGIN, BF_GRIEWANK = 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -78,6 +79,14 @@ class OrcEvolve(C.Structure):
                 ("k", C.c_int32), ("ctr", C.c_uint32)]
 
 
+class OrcBF(C.Structure):
+    _fields_ = [("func", C.c_int32), ("G", C.c_int32), ("N", C.c_int32), ("D", C.c_int32),
+                ("T", C.c_int32), ("lo", C.c_double), ("hi", C.c_double), ("hyper", dp),
+                ("seed", C.c_uint64), ("X", dp), ("V", dp), ("P", dp), ("f", dp), ("Pf", dp),
+                ("gbest_n", ip), ("gbest_f", dp), ("tb_g", C.c_int32), ("tb_n", C.c_int32),
+                ("tb_f", C.c_double), ("k", C.c_int32), ("ctr", C.c_uint32)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -107,6 +116,10 @@ def lib():
         L.orc_plan_frame.argtypes = [C.POINTER(OrcSwarm), C.POINTER(OrcHsef), C.POINTER(OrcMap),
                                      C.POINTER(OrcFrameCfg), C.c_int32, dp, dp, dp,
                                      C.POINTER(OrcFrameResult)]
+        L.orc_bf_value.argtypes = [C.c_int32, C.c_int32, dp]
+        L.orc_bf_value.restype = C.c_double
+        L.orc_bf_init.argtypes = [C.POINTER(OrcBF)]
+        L.orc_bf_step.argtypes = [C.POINTER(OrcBF)]
         L.orc_evolve_init.argtypes = [C.POINTER(OrcEvolve)]
         L.orc_evolve_step.argtypes = [C.POINTER(OrcEvolve), dp]
         _lib = L
@@ -419,3 +432,43 @@ class Evolve:
             self.evolution += 1
             curve.append(self.h.tb_f)
         return np.array(curve)
+
+
+def bf_value(func, x):
+    """Benchmark function `func` (1..4, Table BFs) of one point x (D,)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().orc_bf_value(int(func), len(x), _p(x))
+
+
+class BFSwarm:
+    """DTPSO on a benchmark function (Table BFs) with numpy-owned state."""
+
+    def __init__(self, func, groups, particles, dims, iters, hyper, lo=-600.0, hi=600.0, seed=0):
+        G, N, D = groups, particles, dims
+        self.G, self.N, self.D = G, N, D
+        self.hyper = np.ascontiguousarray(hyper, dtype=np.float64).reshape(G, 6).copy()
+        z = lambda *sh: np.zeros(sh, np.float64)
+        self.X, self.V, self.P = z(G, N, D), z(G, N, D), z(G, N, D)
+        self.f, self.Pf = z(G, N), z(G, N)
+        self.gbest_n = np.zeros(G, np.int32)
+        self.gbest_f = z(G)
+        self.s = OrcBF(int(func), G, N, D, int(iters), float(lo), float(hi), _p(self.hyper),
+                       int(seed), _p(self.X), _p(self.V), _p(self.P), _p(self.f), _p(self.Pf),
+                       _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0, float("inf"), 0, 0)
+        lib().orc_bf_init(C.byref(self.s))
+
+    k = property(lambda self: self.s.k)
+    ctr = property(lambda self: self.s.ctr)
+    tbest = property(lambda self: (self.s.tb_g, self.s.tb_n, self.s.tb_f))
+
+    def step(self, n=1):
+        for _ in range(n):
+            lib().orc_bf_step(C.byref(self.s))
+
+    def set_scalars(self, k=None, ctr=None, tbest=None):
+        if k is not None:
+            self.s.k = int(k)
+        if ctr is not None:
+            self.s.ctr = int(ctr)
+        if tbest is not None:
+            self.s.tb_g, self.s.tb_n, self.s.tb_f = int(tbest[0]), int(tbest[1]), float(tbest[2])
