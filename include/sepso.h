@@ -73,8 +73,11 @@ typedef struct sepso_swarm {
   const float* hyper;                   /* G x 6: C1, C2, C3, w_init, w_end, V_limit (Table hyper8 layout) */
   float alpha; int32_t beta;            /* penalty alpha * Q^beta, beta >= 1 (Eq.13) */
   int32_t use_pi; float pi_gamma, pi_radius; /* Priori Initialization: fraction and half-width */
-  int32_t at_mode, at_window; float at_delta; /* Auto Truncation: 0 off, 1 std over window < delta,
-                                                 2 relative gain over window < delta */
+  int32_t at_mode, at_window; float at_delta; /* Auto Truncation (needs a collision-free best):
+                                                 0 off; 1 population std of the last `window`
+                                                 Tbest values < delta (full window); 2 relative
+                                                 gain over `window` iterations < delta; 3 as 1
+                                                 over the last min(k, window) values, k >= 2 */
   int32_t hsef_every;                   /* online self-evolution period in iterations (0 = off) */
   const float* hsef_hyper;              /* G x 6 hyper of the outer swarm (NULL = Table hyper8 rows) */
   uint64_t seed;                        /* Philox4x32-10 key */
@@ -180,6 +183,9 @@ sepso_status sepso_batch_profile_step(sepso_batch* b, int32_t n, float* avg_ms);
 /* Choose seg_per_thread / block_threads by timing candidates on this batch;
  * the winner is applied to the batch and written to *best (may be NULL). */
 sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best);
+/* Apply a tile configuration to every instance (same bounds as sepso_set_tune,
+ * with the smallest waypoint count of the batch). */
+sepso_status sepso_batch_set_tune(sepso_batch* b, const sepso_tune* tune);
 /* Work counters of one full iteration of every instance: segment x edge
  * tests and swarm elements (for throughput reporting). */
 sepso_status sepso_batch_work(sepso_batch* b, double* tests_per_iter, double* elems_per_iter);
@@ -231,6 +237,121 @@ sepso_status sepso_lin_features(sepso_lin* lin, sepso_batch* b, float* out);
 /* Use lin's proposals at every frame start of b (NULL detaches). */
 sepso_status sepso_lin_attach(sepso_batch* b, sepso_lin* lin);
 sepso_status sepso_lin_attach_ctx(sepso_ctx* ctx, sepso_lin* lin);
+
+/* ---- benchmark-function workload ----------------------------------------
+ * Table BFs with the Sec. "Standard / Large-scale benchmark functions" setup:
+ * DTPSO (Algorithm 1, Eq.(6)-(8)) minimising func = 1 Sphere, 2 Rosenbrock,
+ * 3 Rastrigin, 4 Griewank (textbook definitions, minimum 0) over [lo, hi]^D
+ * with G groups of N particles and per-group hyper-parameters (Table hyper8
+ * layout).  FP32 state; particle rows padded to a multiple of 4 floats in
+ * the workspace.  Random streams: Philox4x32-10, key = seed, counter (c0, c1,
+ * 0, tag): tags 10 / 11 draw the initial positions / velocities (c0 = 4-value
+ * block of the flat (particle, dim) index, c1 = 0), tag 9 the move (c0 =
+ * particle, c1 = ctr, words 0..2 = r1, r2, r3). */
+typedef struct sepso_bf_cfg {
+  int32_t func;                  /* 1..4 */
+  int32_t groups, particles, dims; /* G in [1, 64], N >= 1, D >= 1 */
+  int32_t max_iters;             /* T >= 1: inertia schedule length (Eq.6) */
+  const float* hyper;            /* G x 6 (C1, C2, C3, w_init, w_end, V_limit >= 0) */
+  float lo, hi;                  /* search box, lo < hi; V clipped to V_limit (hi - lo) / 2 */
+  uint64_t seed;
+} sepso_bf_cfg;
+
+/* Host views (any pointer may be NULL): X, V, P: G*N*D row-major; f, Pf:
+ * G*N; gbest_n, gbest_f: G.  tb_* is derived from gbest_f (lowest group,
+ * lowest index on ties).  pending = a move is owed before the next
+ * evaluation (0 after every sepso_bf_step call). */
+typedef struct sepso_bf_state {
+  float *X, *V, *P;
+  float *f, *Pf;
+  int32_t* gbest_n; float* gbest_f;
+  int32_t tb_g, tb_n; float tb_f;
+  int32_t k;           /* iterations evaluated */
+  uint32_t ctr;        /* random-stream position of the move */
+  int32_t pending;
+} sepso_bf_state;
+
+typedef struct sepso_bf sepso_bf;
+sepso_status sepso_bf_workspace_bytes(const sepso_bf_cfg* cfg, size_t* bytes);
+/* Validates, initialises the swarm (synchronous); workspace caller-owned,
+ * 256-byte aligned; stream NULL = an internal non-blocking stream. */
+sepso_status sepso_bf_create(const sepso_bf_cfg* cfg, void* d_workspace, size_t workspace_bytes,
+                             void* stream, sepso_bf** out);
+sepso_status sepso_bf_destroy(sepso_bf* bf);
+/* n iterations of Algorithm 1 (evaluate, bests, move), asynchronous. */
+sepso_status sepso_bf_step(sepso_bf* bf, int32_t n);
+/* As sepso_bf_step, timed with events on the handle's stream: device
+ * milliseconds per iteration (synchronous). */
+sepso_status sepso_bf_profile(sepso_bf* bf, int32_t n, float* ms_per_iter);
+sepso_status sepso_bf_get_state(sepso_bf* bf, sepso_bf_state* st);
+/* Injects state (NULL arrays are left as they are); the Gbest rows are
+ * rebuilt from P and gbest_n when both are given.  Synchronous. */
+sepso_status sepso_bf_set_state(sepso_bf* bf, const sepso_bf_state* st);
+
+/* ---- evolution phase ------------------------------------------------------
+ * Sec. "Hierarchical Self-evolving Framework", Eq.(9), and the path-planning
+ * evolution that produced Table hyper8path.  The higher-level swarm H-SEPSO
+ * (h_groups x h_particles particles, hyper-parameters h_hyper, Table hyper8 by
+ * default) moves, with the DTPSO update of Eq.(6)-(8), over whole lower-level
+ * hyper matrices: particle i holds G_L rows of (C1, C2, C3, w_init, w_end,
+ * V_limit), row-major, column c boxed to [lo[c], hi[c]].  Its fitness is the
+ * lowest fitness value (Tbest fitness after max_iters iterations) of a full
+ * lower-level run on `map` with those values: instance i of an internal batch
+ * runs one frame per evolution from a fresh random swarm (Philox frame
+ * counter = evolution index), with no obstacle motion, Priori Initialization,
+ * Auto Truncation or online self-evolution (the template's use_pi, at_mode,
+ * hsef_every and instance are overridden; its hyper may be NULL).
+ * Random streams of the higher level: Philox4x32-10 with key cfg->seed and
+ * counter (c0, c1, 0, tag): tag 7 / 8 draw the initial positions / velocities
+ * (c0 = 4-value block of the flat (particle, dim) index, c1 = 0), tag 6 the
+ * move (c0 = particle, c1 = evolution counter, words 0..2 = r1, r2, r3). */
+typedef struct sepso_evolve_cfg {
+  int32_t h_groups;      /* 1..64 */
+  int32_t h_particles;   /* per group; h_groups * h_particles <= 1024 */
+  int32_t evolutions;    /* E >= 1: inertia schedule length (Eq.6) and curve capacity */
+  const float* h_hyper;  /* h_groups x 6, V_limit >= 0; NULL = Table hyper8 rows */
+  const float* lo;       /* 6 per-column lower bounds; NULL = 0 for every column */
+  const float* hi;       /* 6 per-column upper bounds (> lo); NULL = (3, 3, 3, 1, 1, 1) */
+  uint64_t seed;
+} sepso_evolve_cfg;
+
+/* Host views of the higher level (any pointer may be NULL).  n = h_groups *
+ * h_particles, Dh = 6 * G_L: X, V, P: n x Dh; Pf, lfv: n (lfv = fitness of
+ * the last evolution); gbest_n / gbest_f: h_groups. */
+typedef struct sepso_evolve_state {
+  float *X, *V, *P;
+  float *Pf, *lfv;
+  int32_t* gbest_n; float* gbest_f;
+  int32_t tb_g, tb_n; float tb_f;
+  int32_t k;             /* evolutions done */
+  uint32_t ctr;          /* random-stream position of the move */
+} sepso_evolve_state;
+
+typedef struct sepso_evolve sepso_evolve;
+/* Device workspace (caller-owned, 256-byte aligned) for the lower-level batch
+ * of n instances plus the higher level's state. */
+sepso_status sepso_evolve_workspace_bytes(const sepso_map* map, const sepso_swarm* lower,
+                                          const sepso_evolve_cfg* cfg, size_t* bytes);
+/* Validates, uploads, and initialises the higher level (synchronous). */
+sepso_status sepso_evolve_create(const sepso_map* map, const sepso_swarm* lower,
+                                 const sepso_evolve_cfg* cfg, void* d_workspace,
+                                 size_t workspace_bytes, void* stream, sepso_evolve** out);
+sepso_status sepso_evolve_destroy(sepso_evolve* ev);
+/* n evolutions (one captured graph each: lower-level frame of every H
+ * particle, then the H bests and move), one synchronisation at the end.
+ * curve (n floats, n <= evolutions; may be NULL) receives the total-best LFV
+ * after each. */
+sepso_status sepso_evolve_run(sepso_evolve* ev, int32_t n, float* curve);
+/* One higher-level step with the given fitness values (n floats; non-finite
+ * counts as +inf) in place of lower-level runs: a seam for checking the
+ * higher level on its own.  Synchronous. */
+sepso_status sepso_evolve_inject(sepso_evolve* ev, const float* lfv);
+sepso_status sepso_evolve_get_state(sepso_evolve* ev, sepso_evolve_state* st);
+/* Best hyper matrix found so far (Dh floats, the total-best H Pbest) and its
+ * LFV; SEPSO_E_STATE before the first evolution. */
+sepso_status sepso_evolve_best(sepso_evolve* ev, float* hyper, float* lfv);
+/* The lower-level batch (owned by ev): for sepso_batch_get_state and tuning. */
+sepso_status sepso_evolve_lower(sepso_evolve* ev, sepso_batch** b);
 
 #ifdef __cplusplus
 }

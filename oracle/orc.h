@@ -182,7 +182,9 @@ typedef struct orc_bf {
   uint32_t ctr;
 } orc_bf;
 void orc_bf_init(orc_bf* s);
-void orc_bf_step(orc_bf* s);  /* evaluate, bests, move (Algorithm 1) */
+void orc_bf_eval(orc_bf* s);     /* f = function value of X */
+void orc_bf_advance(orc_bf* s);  /* bests from f, then the move with index k; ctr += 1 */
+void orc_bf_step(orc_bf* s);     /* k += 1, eval, advance (Algorithm 1) */
 
 #ifdef __cplusplus
 }

@@ -80,14 +80,21 @@ void orc_bf_init(orc_bf* s) {
   s->ctr = 0;
 }
 
-// One Algorithm-1 iteration: evaluate, bests, then the move.
-void orc_bf_step(orc_bf* s) {
+// Fitness of every particle's current position.
+void orc_bf_eval(orc_bf* s) {
+  for (int32_t i = 0; i < s->G * s->N; ++i) {
+    const double fi = orc_bf_value(s->func, s->D, s->X + (size_t)i * s->D);
+    s->f[i] = std::isfinite(fi) ? fi : kInf;
+  }
+}
+
+// Bests from the fitness in f (Pbest on strict improvement, Gbest the
+// group's lowest Pbest, lowest index on ties, Tbest the lowest Gbest), then
+// the move of Eq.(6)-(8) with iteration index k.
+void orc_bf_advance(orc_bf* s) {
   const int32_t G = s->G, N = s->N, D = s->D;
-  s->k += 1;
   for (int32_t i = 0; i < G * N; ++i) {
-    double fi = orc_bf_value(s->func, D, s->X + (size_t)i * D);
-    if (!std::isfinite(fi)) fi = kInf;
-    s->f[i] = fi;
+    const double fi = std::isfinite(s->f[i]) ? s->f[i] : kInf;
     if (fi < s->Pf[i]) {
       s->Pf[i] = fi;
       std::memcpy(s->P + (size_t)i * D, s->X + (size_t)i * D, sizeof(double) * D);
@@ -135,4 +142,11 @@ void orc_bf_step(orc_bf* s) {
     }
   }
   s->ctr += 1;
+}
+
+// One Algorithm-1 iteration: evaluate, bests, then the move.
+void orc_bf_step(orc_bf* s) {
+  s->k += 1;
+  orc_bf_eval(s);
+  orc_bf_advance(s);
 }

@@ -120,6 +120,8 @@ def lib():
         L.orc_bf_value.restype = C.c_double
         L.orc_bf_init.argtypes = [C.POINTER(OrcBF)]
         L.orc_bf_step.argtypes = [C.POINTER(OrcBF)]
+        L.orc_bf_eval.argtypes = [C.POINTER(OrcBF)]
+        L.orc_bf_advance.argtypes = [C.POINTER(OrcBF)]
         L.orc_evolve_init.argtypes = [C.POINTER(OrcEvolve)]
         L.orc_evolve_step.argtypes = [C.POINTER(OrcEvolve), dp]
         _lib = L
@@ -464,6 +466,12 @@ class BFSwarm:
     def step(self, n=1):
         for _ in range(n):
             lib().orc_bf_step(C.byref(self.s))
+
+    def eval(self):
+        lib().orc_bf_eval(C.byref(self.s))
+
+    def advance(self):
+        lib().orc_bf_advance(C.byref(self.s))
 
     def set_scalars(self, k=None, ctr=None, tbest=None):
         if k is not None:

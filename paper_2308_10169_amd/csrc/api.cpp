@@ -83,7 +83,7 @@ sepso_status check_swarm(const sepso_swarm* s, int idx) {
     return fail(SEPSO_E_ARG, "swarm[%d]: pi_gamma in [0,1]", idx);
   if (!(finite(s->pi_radius) && s->pi_radius >= 0.f))
     return fail(SEPSO_E_ARG, "swarm[%d]: pi_radius >= 0", idx);
-  if (s->at_mode < 0 || s->at_mode > 2) return fail(SEPSO_E_ARG, "swarm[%d]: at_mode", idx);
+  if (s->at_mode < 0 || s->at_mode > 3) return fail(SEPSO_E_ARG, "swarm[%d]: at_mode", idx);
   if (s->at_window < 1 || s->at_window >= kHist)
     return fail(SEPSO_E_ARG, "swarm[%d]: at_window in [1,%d]", idx, kHist - 1);
   if (!finite(s->at_delta)) return fail(SEPSO_E_ARG, "swarm[%d]: at_delta", idx);
@@ -93,12 +93,58 @@ sepso_status check_swarm(const sepso_swarm* s, int idx) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// An axis-aligned rectangle: four vertices whose consecutive edges are
+// alternately horizontal and vertical (either orientation).
+bool is_axis_rect(const float* v, int m) {
+  if (m != 4) return false;
+  bool prev_h = false;
+  for (int j = 0; j < 4; ++j) {
+    const float ax = v[2 * j], ay = v[2 * j + 1];
+    const float bx = v[2 * ((j + 1) % 4)], by = v[2 * ((j + 1) % 4) + 1];
+    const bool h = ay == by && ax != bx, vt = ax == bx && ay != by;
+    if (!h && !vt) return false;
+    if (j > 0 && h == prev_h) return false;
+    prev_h = h;
+  }
+  return true;
+}
+
+// Per polygon of a map: (1, slot among rectangles) or (0, first slot among
+// the other polygons' edges).
+void classify_polys(const sepso_map& m, std::vector<int2>* kind, int* n_rects, int* n_gedges) {
+  kind->assign(m.n_polys, make_int2(0, 0));
+  int nr = 0, ne = 0;
+  for (int q = 0; q < m.n_polys; ++q) {
+    const int v0 = m.poly_ptr[q], cnt = m.poly_ptr[q + 1] - v0;
+    if (is_axis_rect(m.verts + 2 * v0, cnt)) {
+      (*kind)[q] = make_int2(1, nr++);
+    } else {
+      (*kind)[q] = make_int2(0, ne);
+      ne += cnt;
+    }
+  }
+  *n_rects = nr;
+  *n_gedges = ne;
+}
+
 Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vector<InstDesc>* desc) {
   Layout L{};
   if (desc) desc->assign(n, InstDesc{});
+  std::vector<int2> kind;
   for (int i = 0; i < n; ++i) {
     const int G = sw[i].groups, N = sw[i].particles, W = sw[i].waypoints, D = 2 * W;
     const int64_t P = (int64_t)G * N;
+    int n_rects = 0, n_gedges = 0;
+    classify_polys(maps[i], &kind, &n_rects, &n_gedges);
+    if (desc) {
+      InstDesc& d = (*desc)[i];
+      d.n_rects = n_rects;
+      d.n_gedges = n_gedges;
+      d.ro = (int32_t)L.sumR;
+      d.geo = (int32_t)L.sumGE;
+    }
+    L.sumR += n_rects;
+    L.sumGE += n_gedges;
     if (desc) {
       InstDesc& d = (*desc)[i];
       d.G = G;
@@ -159,7 +205,9 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   L.PL = take(4 * L.sumP);
   L.Q = take(4 * L.sumP);
   L.PQ = take(4 * L.sumP);
-  L.edges = take(sizeof(EdgeRec) * L.sumE);
+  L.edges = take(sizeof(EdgeRec) * L.sumGE);
+  L.rects = take(16 * L.sumR);
+  L.pkind = take(8 * L.sumPoly);
   L.verts = take(8 * L.sumE);
   L.pptr = take(4 * L.sumPP);
   L.pvel = take(8 * L.sumPoly);
@@ -254,6 +302,7 @@ sepso_status upload_tiles(sepso_batch* b) {
   HIPCHK(b, hipMemcpyAsync(b->ws + b->lay.blkt, blk.data(), sizeof(int2) * blk.size(),
                            hipMemcpyHostToDevice, b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
+  b->tune_gen += 1;
   for (int m = 0; m < 2; ++m)
     if (b->graph[m]) {
       hipGraphExecDestroy(b->graph[m]);
@@ -340,6 +389,8 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
   pl.Q = at<int32_t>(b, L.Q);
   pl.PQ = at<int32_t>(b, L.PQ);
   pl.edges = at<EdgeRec>(b, L.edges);
+  pl.rects = at<float4>(b, L.rects);
+  pl.pkind = at<int2>(b, L.pkind);
   pl.verts = at<float2>(b, L.verts);
   pl.poly_ptr = at<int32_t>(b, L.pptr);
   pl.poly_vel = at<float2>(b, L.pvel);
@@ -363,11 +414,18 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
   std::vector<float> verts(2 * L.sumE), pvel(2 * L.sumPoly, 0.f), ends(4 * n), endv(4 * n);
   std::vector<float> hyper(6 * L.sumG), ohyper(6 * L.sumG);
   std::vector<int32_t> pptr(L.sumPP);
-  std::vector<int2> blki;
+  std::vector<int2> blki, pkind(std::max<int64_t>(1, L.sumPoly));
   b->n_vert.resize(n);
   b->path_off.resize(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     const InstDesc& d = b->desc[i];
+    {
+      std::vector<int2> kind;
+      int nr = 0, ne = 0;
+      classify_polys(maps[i], &kind, &nr, &ne);
+      for (int q = 0; q < d.n_polys; ++q) pkind[d.pvo + q] = kind[q];
+      if (i == 0) b->h_kind = kind;
+    }
     const sepso_map& m = maps[i];
     b->n_vert[i] = d.n_edges;
     for (int j = 0; j < 2 * d.n_edges; ++j) verts[2 * d.eo + j] = m.verts[j];
@@ -401,6 +459,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
       h2d(L.ctl, ctl.data(), sizeof(InstCtl) * n),
       h2d(L.verts, verts.data(), 4 * verts.size()),
       h2d(L.pptr, pptr.data(), 4 * pptr.size()),
+      h2d(L.pkind, pkind.data(), 8 * L.sumPoly),
       h2d(L.pvel, pvel.data(), 4 * pvel.size()),
       h2d(L.ends, ends.data(), 4 * ends.size()),
       h2d(L.endv, endv.data(), 4 * endv.size()),
@@ -629,6 +688,14 @@ sepso_status sepso_plan_frame(sepso_ctx* ctx, const sepso_map* next, sepso_frame
       return fail(SEPSO_E_ARG, "next map must keep the polygon structure (n_polys)");
     for (int q = 0; q <= d.n_polys && d.n_polys; ++q)
       if (next->poly_ptr[q] != b->h_pptr[q]) return fail(SEPSO_E_ARG, "next map: poly_ptr differs");
+    {
+      std::vector<int2> kind;
+      int nr = 0, ne = 0;
+      classify_polys(*next, &kind, &nr, &ne);
+      for (int q = 0; q < d.n_polys; ++q)
+        if (kind[q].x != b->h_kind[q].x)
+          return fail(SEPSO_E_ARG, "next map: polygon %d changed between rectangle and general", q);
+    }
     std::vector<float> e4 = {next->start[0], next->start[1], next->target[0], next->target[1]};
     HIPCHK(b, hipMemcpyAsync(b->pl.verts + d.eo, next->verts, 8 * (size_t)d.n_edges,
                              hipMemcpyHostToDevice, b->stream));
@@ -829,21 +896,304 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
   return SEPSO_OK;
 }
 
-sepso_status sepso_set_tune(sepso_ctx* ctx, const sepso_tune* tune) {
-  if (!ctx || !tune) return fail(SEPSO_E_ARG, "ctx/tune NULL");
-  sepso_batch* b = ctx->b;
+sepso_status sepso_batch_set_tune(sepso_batch* b, const sepso_tune* tune) {
+  if (!b || !tune) return fail(SEPSO_E_ARG, "batch/tune NULL");
   sepso_status st = usable(b);
   if (st != SEPSO_OK) return st;
-  if (!tune_ok(tune->seg_per_thread, tune->block_threads, b->desc[0].W))
+  int w_min = kMaxW;
+  for (const InstDesc& d : b->desc) w_min = std::min(w_min, d.W);
+  if (!tune_ok(tune->seg_per_thread, tune->block_threads, w_min))
     return fail(SEPSO_E_ARG, "tune: seg_per_thread in {4,8,12,16,24} and <= 2*(waypoints+2), "
                              "block_threads in {64,128,256}, product <= 4096");
   b->tune = *tune;
   return upload_tiles(b);
 }
 
+sepso_status sepso_set_tune(sepso_ctx* ctx, const sepso_tune* tune) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  return sepso_batch_set_tune(ctx->b, tune);
+}
+
 sepso_status sepso_autotune_ctx(sepso_ctx* ctx, sepso_tune* best) {
   if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
   return sepso_autotune(ctx->b, best);
+}
+
+}  // extern "C"
+
+// ============================ evolution phase ===============================
+
+struct sepso_evolve {
+  sepso_batch* b = nullptr;   // lower level: instance i = H particle i
+  sepso::EvolveDev dev{};
+  size_t batch_bytes = 0;
+  hipGraphExec_t graph = nullptr;  // one lower-level frame + the H step
+  int graph_gen = -1;              // tile plan the graph was captured with
+};
+
+namespace {
+
+const float kEvolveLo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+const float kEvolveHi[6] = {3.f, 3.f, 3.f, 1.f, 1.f, 1.f};
+
+struct EvolveInputs {
+  std::vector<sepso_map> maps;
+  std::vector<sepso_swarm> swarms;
+  std::vector<float> placeholder;  // lower-level hyper until the H init writes it
+  size_t batch_bytes = 0, h_bytes = 0;
+};
+
+sepso_status evolve_inputs(const sepso_map* map, const sepso_swarm* lower,
+                           const sepso_evolve_cfg* cfg, EvolveInputs* in) {
+  if (!map || !lower || !cfg) return fail(SEPSO_E_ARG, "map/lower/cfg is NULL");
+  if (cfg->h_groups < 1 || cfg->h_groups > kMaxG)
+    return fail(SEPSO_E_ARG, "evolve: h_groups in [1,%d]", kMaxG);
+  if (cfg->h_particles < 1 || (int64_t)cfg->h_groups * cfg->h_particles > kEvolveMaxH)
+    return fail(SEPSO_E_ARG, "evolve: h_particles >= 1 and h_groups*h_particles <= %d", kEvolveMaxH);
+  if (cfg->evolutions < 1) return fail(SEPSO_E_ARG, "evolve: evolutions >= 1");
+  const float* lo = cfg->lo ? cfg->lo : kEvolveLo;
+  const float* hi = cfg->hi ? cfg->hi : kEvolveHi;
+  for (int c = 0; c < 6; ++c)
+    if (!(finite(lo[c]) && finite(hi[c]) && lo[c] < hi[c]))
+      return fail(SEPSO_E_ARG, "evolve: lo[%d] < hi[%d] finite", c, c);
+  if (lo[5] < 0.f) return fail(SEPSO_E_ARG, "evolve: V_limit lower bound < 0");
+  if (cfg->h_hyper)
+    for (int j = 0; j < 6 * cfg->h_groups; ++j)
+      if (!finite(cfg->h_hyper[j]) || (j % 6 == 5 && cfg->h_hyper[j] < 0.f))
+        return fail(SEPSO_E_ARG, "evolve: h_hyper");
+  const int n = cfg->h_groups * cfg->h_particles;
+  sepso_swarm t = *lower;
+  if (t.groups < 1 || t.groups > kMaxG) return fail(SEPSO_E_ARG, "lower: groups in [1,%d]", kMaxG);
+  in->placeholder.resize(6 * t.groups);
+  for (int j = 0; j < 6 * t.groups; ++j) in->placeholder[j] = kHyper8[(j / 6) % 8][j % 6];
+  if (!t.hyper) t.hyper = in->placeholder.data();
+  t.use_pi = 0;
+  t.at_mode = 0;
+  t.hsef_every = 0;
+  in->maps.assign(n, *map);
+  in->swarms.assign(n, t);
+  for (int i = 0; i < n; ++i) in->swarms[i].instance = (uint32_t)i;
+  sepso_status st = sepso_batch_workspace_bytes(in->maps.data(), in->swarms.data(), n, &in->batch_bytes);
+  if (st != SEPSO_OK) return st;
+  in->batch_bytes = align256(in->batch_bytes);
+  const size_t Dh = 6 * (size_t)t.groups;
+  in->h_bytes = align256(sizeof(EvolveCtl)) + align256(4 * 3 * n * Dh) + align256(4 * 2 * (size_t)n) +
+                align256(8 * (size_t)cfg->h_groups) + align256(4 * (6 * (size_t)cfg->h_groups + 12)) +
+                align256(4 * (size_t)n) + align256(4 * (size_t)cfg->evolutions);
+  return SEPSO_OK;
+}
+
+sepso_status evolve_usable(sepso_evolve* ev) {
+  if (!ev) return fail(SEPSO_E_ARG, "evolve handle is NULL");
+  return usable(ev->b);
+}
+
+}  // namespace
+
+extern "C" {
+
+sepso_status sepso_evolve_workspace_bytes(const sepso_map* map, const sepso_swarm* lower,
+                                          const sepso_evolve_cfg* cfg, size_t* bytes) {
+  if (!bytes) return fail(SEPSO_E_ARG, "bytes is NULL");
+  EvolveInputs in;
+  sepso_status st = evolve_inputs(map, lower, cfg, &in);
+  if (st != SEPSO_OK) return st;
+  *bytes = in.batch_bytes + in.h_bytes;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_evolve_create(const sepso_map* map, const sepso_swarm* lower,
+                                 const sepso_evolve_cfg* cfg, void* d_ws, size_t ws_bytes,
+                                 void* stream, sepso_evolve** out) {
+  if (!out) return fail(SEPSO_E_ARG, "out is NULL");
+  *out = nullptr;
+  EvolveInputs in;
+  sepso_status st = evolve_inputs(map, lower, cfg, &in);
+  if (st != SEPSO_OK) return st;
+  if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
+  if (ws_bytes < in.batch_bytes + in.h_bytes)
+    return fail(SEPSO_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes,
+                in.batch_bytes + in.h_bytes);
+  const int n = cfg->h_groups * cfg->h_particles;
+  sepso_evolve* ev = new (std::nothrow) sepso_evolve();
+  if (!ev) return fail(SEPSO_E_NOMEM, "host allocation failed");
+  st = create_batch(in.maps.data(), in.swarms.data(), n, d_ws, in.batch_bytes, stream, nullptr, &ev->b);
+  if (st != SEPSO_OK) {
+    delete ev;
+    return st;
+  }
+  ev->batch_bytes = in.batch_bytes;
+  char* base = static_cast<char*>(d_ws) + in.batch_bytes;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += align256(bytes);
+    return p;
+  };
+  EvolveDev& d = ev->dev;
+  d.Gh = cfg->h_groups;
+  d.Nh = cfg->h_particles;
+  d.Dh = 6 * lower->groups;
+  d.E = cfg->evolutions;
+  d.seed_lo = (uint32_t)(cfg->seed & 0xffffffffu);
+  d.seed_hi = (uint32_t)(cfg->seed >> 32);
+  const size_t nD = (size_t)n * d.Dh;
+  d.ctl = reinterpret_cast<EvolveCtl*>(take(sizeof(EvolveCtl)));
+  float* xvp = reinterpret_cast<float*>(take(4 * 3 * nD));
+  d.X = xvp;
+  d.V = xvp + nD;
+  d.P = xvp + 2 * nD;
+  float* pl2 = reinterpret_cast<float*>(take(4 * 2 * (size_t)n));
+  d.Pf = pl2;
+  d.lfv = pl2 + n;
+  char* gb = take(8 * (size_t)d.Gh);
+  d.gbest_n = reinterpret_cast<int32_t*>(gb);
+  d.gbest_f = reinterpret_cast<float*>(gb + 4 * d.Gh);
+  float* consts = reinterpret_cast<float*>(take(4 * (6 * (size_t)d.Gh + 12)));
+  d.h_hyper = consts;
+  d.lo = consts + 6 * d.Gh;
+  d.hi = consts + 6 * d.Gh + 6;
+  float* lin = reinterpret_cast<float*>(take(4 * (size_t)n));
+  d.lfv_in = lin;
+  d.curve = reinterpret_cast<float*>(take(4 * (size_t)d.E));
+  std::vector<float> hc(6 * d.Gh + 12);
+  for (int j = 0; j < 6 * d.Gh; ++j)
+    hc[j] = cfg->h_hyper ? cfg->h_hyper[j] : kHyper8[(j / 6) % 8][j % 6];
+  for (int c = 0; c < 6; ++c) {
+    hc[6 * d.Gh + c] = cfg->lo ? cfg->lo[c] : kEvolveLo[c];
+    hc[6 * d.Gh + 6 + c] = cfg->hi ? cfg->hi[c] : kEvolveHi[c];
+  }
+  sepso_batch* b = ev->b;
+  hipError_t e = hipMemcpyAsync(consts, hc.data(), 4 * hc.size(), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) {
+    launch_evolve_init(d, b->pl, b->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    st = fail(SEPSO_E_HIP, "evolve create: %s", hipGetErrorString(e));
+    destroy_batch(b);
+    delete ev;
+    return st;
+  }
+  *out = ev;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_evolve_destroy(sepso_evolve* ev) {
+  if (!ev) return fail(SEPSO_E_ARG, "evolve handle is NULL");
+  if (ev->graph) hipGraphExecDestroy(ev->graph);
+  destroy_batch(ev->b);
+  delete ev;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_evolve_run(sepso_evolve* ev, int32_t n, float* curve) {
+  sepso_status st = evolve_usable(ev);
+  if (st != SEPSO_OK) return st;
+  if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
+  if (curve && n > ev->dev.E) return fail(SEPSO_E_ARG, "curve holds at most `evolutions` values");
+  sepso_batch* b = ev->b;
+  if (ev->graph && ev->graph_gen != b->tune_gen) {
+    hipGraphExecDestroy(ev->graph);
+    ev->graph = nullptr;
+  }
+  if (!ev->graph) {
+    ev->graph_gen = b->tune_gen;
+    hipGraph_t g = nullptr;
+    HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_frame(b, false);
+    launch_evolve_step(ev->dev, b->pl, 0, b->stream);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&ev->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(b, e, "hipGraphInstantiate");
+  }
+  EvolveCtl c0{};
+  if (curve) {
+    HIPCHK(b, hipMemcpyAsync(&c0, ev->dev.ctl, sizeof(EvolveCtl), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+  }
+  for (int k = 0; k < n; ++k) HIPCHK(b, hipGraphLaunch(ev->graph, b->stream));
+  b->frames_done += n;
+  if (curve && n > 0) {
+    const int E = ev->dev.E, first = c0.k % E;
+    const int n1 = std::min(n, E - first);
+    HIPCHK(b, hipMemcpyAsync(curve, ev->dev.curve + first, 4 * (size_t)n1, hipMemcpyDeviceToHost, b->stream));
+    if (n > n1)
+      HIPCHK(b, hipMemcpyAsync(curve + n1, ev->dev.curve, 4 * (size_t)(n - n1), hipMemcpyDeviceToHost,
+                               b->stream));
+  }
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
+sepso_status sepso_evolve_inject(sepso_evolve* ev, const float* lfv) {
+  sepso_status st = evolve_usable(ev);
+  if (st != SEPSO_OK) return st;
+  if (!lfv) return fail(SEPSO_E_ARG, "lfv is NULL");
+  sepso_batch* b = ev->b;
+  const int n = ev->dev.Gh * ev->dev.Nh;
+  HIPCHK(b, hipMemcpyAsync(const_cast<float*>(ev->dev.lfv_in), lfv, 4 * (size_t)n,
+                           hipMemcpyHostToDevice, b->stream));
+  launch_evolve_step(ev->dev, b->pl, 1, b->stream);
+  LAUNCHCHK(b, "evolve step launch");
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
+sepso_status sepso_evolve_get_state(sepso_evolve* ev, sepso_evolve_state* s) {
+  sepso_status st = evolve_usable(ev);
+  if (st != SEPSO_OK) return st;
+  if (!s) return fail(SEPSO_E_ARG, "state is NULL");
+  sepso_batch* b = ev->b;
+  const EvolveDev& d = ev->dev;
+  const size_t n = (size_t)d.Gh * d.Nh, nD = n * d.Dh;
+  auto d2h = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!dst) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, b->stream);
+  };
+  EvolveCtl c{};
+  HIPCHK(b, d2h(s->X, d.X, 4 * nD));
+  HIPCHK(b, d2h(s->V, d.V, 4 * nD));
+  HIPCHK(b, d2h(s->P, d.P, 4 * nD));
+  HIPCHK(b, d2h(s->Pf, d.Pf, 4 * n));
+  HIPCHK(b, d2h(s->lfv, d.lfv, 4 * n));
+  HIPCHK(b, d2h(s->gbest_n, d.gbest_n, 4 * (size_t)d.Gh));
+  HIPCHK(b, d2h(s->gbest_f, d.gbest_f, 4 * (size_t)d.Gh));
+  HIPCHK(b, d2h(&c, d.ctl, sizeof(EvolveCtl)));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  s->tb_g = c.tb_g;
+  s->tb_n = c.tb_n;
+  s->tb_f = c.tb_f;
+  s->k = c.k;
+  s->ctr = c.ctr;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_evolve_best(sepso_evolve* ev, float* hyper, float* lfv) {
+  sepso_status st = evolve_usable(ev);
+  if (st != SEPSO_OK) return st;
+  sepso_batch* b = ev->b;
+  const EvolveDev& d = ev->dev;
+  EvolveCtl c{};
+  HIPCHK(b, hipMemcpyAsync(&c, d.ctl, sizeof(EvolveCtl), hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  if (c.k == 0) return fail(SEPSO_E_STATE, "no evolution has run yet");
+  if (hyper) {
+    const size_t row = (size_t)(c.tb_g * d.Nh + c.tb_n) * d.Dh;
+    HIPCHK(b, hipMemcpyAsync(hyper, d.P + row, 4 * (size_t)d.Dh, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+  }
+  if (lfv) *lfv = c.tb_f;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_evolve_lower(sepso_evolve* ev, sepso_batch** b) {
+  if (!ev || !b) return fail(SEPSO_E_ARG, "evolve/out is NULL");
+  *b = ev->b;
+  return SEPSO_OK;
 }
 
 }  // extern "C"

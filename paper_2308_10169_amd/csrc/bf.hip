@@ -1,0 +1,541 @@
+// Benchmark-function workload (Table BFs; Sec. "Standard benchmark
+// functions" and "Large-scale benchmark functions"): the same DTPSO step
+// (Algorithm 1, Eq.(6)-(8)) minimising Sphere, Rosenbrock, Rastrigin or
+// Griewank over [lo, hi]^D, for swarms up to HBM size (the paper's large
+// case is 16K particles x 1K dimensions).
+//
+// The step is bound by HBM traffic: per element one read of X, V and P and
+// one write of X and V (20 bytes); the group-best rows stay in L2.  One wave
+// owns one particle row (rows padded to a multiple of 4 floats, float4
+// accesses), so the fitness reduction is a wave reduction without LDS or
+// barriers; four particles per 256-thread block.
+//
+//   bf_init_kernel   -- uniform swarm in the box;
+//   bf_iter_kernel   -- pending move (with the previous iteration's bests),
+//                       fitness of the new position, Pbest;
+//   bf_reduce_kernel -- one block per group: Gbest (lowest Pbest, lowest
+//                       index on ties) and its row; block 0 advances the
+//                       control word.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sepso.h"
+#include "common.h"
+#include "internal.h"
+#include "rng.h"
+
+namespace sepso {
+
+enum : uint32_t { TAG_BF_UPDATE = 9, TAG_BF_INIT_X = 10, TAG_BF_INIT_V = 11 };
+enum : int32_t { BF_SPHERE = 1, BF_ROSENBROCK = 2, BF_RASTRIGIN = 3, BF_GRIEWANK = 4 };
+
+struct BFCtl {
+  int32_t k;        // iterations evaluated
+  uint32_t ctr;     // random stream position of the move
+  int32_t pending;  // a move is owed before the next evaluation
+  int32_t pad;
+};
+
+struct BFDev {
+  int32_t func, G, N, D, Dp, T;
+  float lo, hi;
+  uint32_t seed_lo, seed_hi;
+  float *X, *V, *P;  // (G*N) x Dp
+  float *f, *Pf;     // G*N
+  int32_t* gbest_n;  // G
+  float* gbest_f;    // G
+  float* gbest_pos;  // G x Dp
+  const float* hyper;  // G*6
+  BFCtl* ctl;
+};
+
+__global__ __launch_bounds__(256) void bf_init_kernel(BFDev s) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)s.G * s.N * s.Dp;
+  if (e >= total) return;
+  const int i = (int)(e / s.Dp), d = (int)(e - (int64_t)i * s.Dp), g = i / s.N;
+  float x = 0.f, v = 0.f;
+  if (d < s.D) {
+    const uint32_t c0 = (uint32_t)i * (uint32_t)(s.Dp / 4) + (uint32_t)(d / 4);
+    const U4 rx = philox(c0, 0u, 0u, TAG_BF_INIT_X, s.seed_lo, s.seed_hi);
+    const U4 rv = philox(c0, 0u, 0u, TAG_BF_INIT_V, s.seed_lo, s.seed_hi);
+    const float vmax = s.hyper[6 * g + 5] * (s.hi - s.lo) * 0.5f;
+    x = s.lo + u01(rx.v[d & 3]) * (s.hi - s.lo);
+    v = -vmax + u01(rv.v[d & 3]) * (2.f * vmax);
+  }
+  s.X[e] = x;
+  s.P[e] = x;
+  s.V[e] = v;
+  if (d == 0) {
+    s.f[i] = INFINITY;
+    s.Pf[i] = INFINITY;
+  }
+  if (e < s.G) {
+    s.gbest_n[e] = 0;
+    s.gbest_f[e] = INFINITY;
+  }
+  if (e == 0) *s.ctl = BFCtl{0, 0u, 0, 0};
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+__device__ __forceinline__ float wave_prod(float x) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x *= __shfl_xor(x, m);
+  return x;
+}
+
+template <int FUNC, bool FIT>
+__global__ __launch_bounds__(256) void bf_iter_kernel(BFDev s) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);  // particle of this wave
+  if (i >= s.G * s.N) return;                          // whole wave leaves
+  const BFCtl c = *s.ctl;
+  const int g = i / s.N, D = s.D, Dp = s.Dp;
+  float4* X = reinterpret_cast<float4*>(s.X + (int64_t)i * Dp);
+  float4* V = reinterpret_cast<float4*>(s.V + (int64_t)i * Dp);
+  const float4* Pp = reinterpret_cast<const float4*>(s.P + (int64_t)i * Dp);
+
+  // move coefficients (Eq.(6)-(7)) and the Tbest row = Gbest row of the
+  // lowest group (lowest group index on ties)
+  float w = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, vmax = 0.f;
+  const float4 *Gb = nullptr, *Tb = nullptr;
+  if (c.pending) {
+    const float* h = s.hyper + 6 * g;
+    const int kk = c.k < s.T ? c.k : s.T;
+    w = h[3] - (h[3] - h[4]) / (float)s.T * (float)kk;
+    vmax = h[5] * (s.hi - s.lo) * 0.5f;
+    const U4 r = philox((uint32_t)i, c.ctr, 0u, TAG_BF_UPDATE, s.seed_lo, s.seed_hi);
+    a1 = h[0] * u01(r.v[0]);
+    a2 = h[1] * u01(r.v[1]);
+    a3 = h[2] * u01(r.v[2]);
+    float bf = lane < s.G ? s.gbest_f[lane] : INFINITY;
+    int bn = lane < s.G ? lane : 0x7fffffff;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+      const float of = __shfl_xor(bf, m);
+      const int on = __shfl_xor(bn, m);
+      if (of < bf || (of == bf && on < bn)) {
+        bf = of;
+        bn = on;
+      }
+    }
+    const int tg = bn < s.G ? bn : 0;
+    Gb = reinterpret_cast<const float4*>(s.gbest_pos + (int64_t)g * Dp);
+    Tb = reinterpret_cast<const float4*>(s.gbest_pos + (int64_t)tg * Dp);
+  }
+
+  float acc = 0.f, prod = 1.f, carry = 0.f;
+  for (int e0 = 0; e0 < Dp; e0 += 256) {
+    const int e = e0 + 4 * lane, q = e >> 2;
+    float xv[4] = {0.f, 0.f, 0.f, 0.f};
+    if (e < Dp) {
+      float4 x4 = X[q];
+      if (c.pending) {
+        float4 v4 = V[q];
+        const float4 p4 = Pp[q], g4 = Gb[q], t4 = Tb[q];
+        float* xs = &x4.x;
+        float* vs = &v4.x;
+        const float* ps = &p4.x;
+        const float* gs = &g4.x;
+        const float* ts = &t4.x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (e + j < D) {
+            const float x = xs[j];
+            float v = w * vs[j] + a1 * (ps[j] - x) + a2 * (gs[j] - x) + a3 * (ts[j] - x);
+            v = clampf(v, -vmax, vmax);
+            vs[j] = v;
+            xs[j] = clampf(x + v, s.lo, s.hi);
+          }
+        }
+        X[q] = x4;
+        V[q] = v4;
+      }
+      xv[0] = x4.x;
+      xv[1] = x4.y;
+      xv[2] = x4.z;
+      xv[3] = x4.w;
+    }
+    if (FIT) {
+      if (FUNC == BF_ROSENBROCK) {
+        // pairs (x[j-1], x[j]): the element before this lane's first comes
+        // from the previous lane, or for lane 0 from the previous chunk
+        float prev = __shfl_up(xv[3], 1);
+        if (lane == 0) prev = carry;
+        carry = __shfl(xv[3], 63);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int d = e + j;
+          const float xm = j == 0 ? prev : xv[j - 1];
+          if (d >= 1 && d < D) {
+            const float a = xv[j] - xm * xm, b = 1.f - xm;
+            acc += 100.f * a * a + b * b;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int d = e + j;
+          if (d < D) {
+            const float x = xv[j];
+            if (FUNC == BF_SPHERE) acc += x * x;
+            if (FUNC == BF_RASTRIGIN) acc += x * x + 10.f * (1.f - cospif(2.f * x));
+            if (FUNC == BF_GRIEWANK) {
+              acc += x * x * (1.f / 4000.f);
+              prod *= cosf(x / sqrtf((float)(d + 1)));
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!FIT) return;
+  float fv = wave_sum(acc);
+  if (FUNC == BF_GRIEWANK) fv = 1.f + fv - wave_prod(prod);
+  if (!(fabsf(fv) <= 3.402823466e38f)) fv = INFINITY;
+  const bool imp = fv < s.Pf[i];
+  if (lane == 0) {
+    s.f[i] = fv;
+    if (imp) s.Pf[i] = fv;
+  }
+  if (imp) {  // wave-uniform; the row was just written, so it reads from L2
+    float4* P = reinterpret_cast<float4*>(s.P + (int64_t)i * Dp);
+    for (int q = lane; q < Dp / 4; q += 64) P[q] = X[q];
+  }
+}
+
+__global__ __launch_bounds__(256) void bf_reduce_kernel(BFDev s, int fit) {
+  __shared__ float s_f[256];
+  __shared__ int s_n[256];
+  const int g = blockIdx.x, t = threadIdx.x, N = s.N;
+  if (fit) {
+    float bf = INFINITY;
+    int bn = 0x7fffffff;
+    for (int n = t; n < N; n += blockDim.x) {
+      const float f = s.Pf[g * N + n];
+      if (f < bf || (f == bf && n < bn)) {
+        bf = f;
+        bn = n;
+      }
+    }
+    s_f[t] = bf;
+    s_n[t] = bn;
+    __syncthreads();
+    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+      if (t < m) {
+        const float of = s_f[t + m];
+        const int on = s_n[t + m];
+        if (of < s_f[t] || (of == s_f[t] && on < s_n[t])) {
+          s_f[t] = of;
+          s_n[t] = on;
+        }
+      }
+      __syncthreads();
+    }
+    const int n = s_n[0] < N ? s_n[0] : 0;
+    if (t == 0) {
+      s.gbest_n[g] = n;
+      s.gbest_f[g] = s_f[0];
+    }
+    const float4* src = reinterpret_cast<const float4*>(s.P + ((int64_t)g * N + n) * s.Dp);
+    float4* dst = reinterpret_cast<float4*>(s.gbest_pos + (int64_t)g * s.Dp);
+    for (int q = t; q < s.Dp / 4; q += blockDim.x) dst[q] = src[q];
+  }
+  if (g == 0 && t == 0) {  // the control word's only reader and writer in this launch
+    const BFCtl c = *s.ctl;
+    BFCtl n = c;
+    n.ctr = c.ctr + (c.pending ? 1u : 0u);
+    if (fit) {
+      n.k = c.k + 1;
+      n.pending = 1;
+    } else {
+      n.pending = 0;
+    }
+    *s.ctl = n;
+  }
+}
+
+template <int FUNC>
+void launch_bf_iter(const BFDev& s, bool fit, hipStream_t st) {
+  const int blocks = (s.G * s.N + 3) / 4;
+  if (fit)
+    hipLaunchKernelGGL((bf_iter_kernel<FUNC, true>), dim3(blocks), dim3(256), 0, st, s);
+  else
+    hipLaunchKernelGGL((bf_iter_kernel<FUNC, false>), dim3(blocks), dim3(256), 0, st, s);
+}
+
+void launch_bf_step(const BFDev& s, bool fit, hipStream_t st) {
+  switch (s.func) {
+    case BF_SPHERE: launch_bf_iter<BF_SPHERE>(s, fit, st); break;
+    case BF_ROSENBROCK: launch_bf_iter<BF_ROSENBROCK>(s, fit, st); break;
+    case BF_RASTRIGIN: launch_bf_iter<BF_RASTRIGIN>(s, fit, st); break;
+    default: launch_bf_iter<BF_GRIEWANK>(s, fit, st); break;
+  }
+  hipLaunchKernelGGL(bf_reduce_kernel, dim3(s.G), dim3(256), 0, st, s, fit ? 1 : 0);
+}
+
+}  // namespace sepso
+
+using namespace sepso;
+
+struct sepso_bf {
+  BFDev dev{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool broken = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BFLayout {
+  size_t ctl, xvp, fp, gb, gpos, hyper, total;
+};
+
+sepso_status bf_check(const sepso_bf_cfg* c) {
+  if (!c) return fail(SEPSO_E_ARG, "cfg is NULL");
+  if (c->func < 1 || c->func > 4) return fail(SEPSO_E_ARG, "bf: func in 1..4");
+  if (c->groups < 1 || c->groups > 64) return fail(SEPSO_E_ARG, "bf: groups in [1,64]");
+  if (c->particles < 1 || c->dims < 1 || c->max_iters < 1)
+    return fail(SEPSO_E_ARG, "bf: particles, dims, max_iters >= 1");
+  const double elems = (double)c->groups * c->particles * ((c->dims + 3) / 4 * 4);
+  if (elems > 4.0e9 || (double)c->groups * c->particles > 2.0e9)
+    return fail(SEPSO_E_ARG, "bf: swarm too large");
+  if ((double)c->groups * c->particles * ((c->dims + 3) / 4) > 4294967295.0)
+    return fail(SEPSO_E_ARG, "bf: swarm too large for the 32-bit random counter");
+  if (!(std::isfinite(c->lo) && std::isfinite(c->hi) && c->lo < c->hi))
+    return fail(SEPSO_E_ARG, "bf: lo < hi finite");
+  if (!c->hyper) return fail(SEPSO_E_ARG, "bf: hyper is NULL");
+  for (int j = 0; j < 6 * c->groups; ++j)
+    if (!std::isfinite(c->hyper[j]) || (j % 6 == 5 && c->hyper[j] < 0.f))
+      return fail(SEPSO_E_ARG, "bf: hyper not finite or V_limit < 0");
+  return SEPSO_OK;
+}
+
+BFLayout bf_layout(const sepso_bf_cfg* c) {
+  const size_t n = (size_t)c->groups * c->particles, Dp = (size_t)(c->dims + 3) / 4 * 4;
+  BFLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o = a256(o + std::max<size_t>(b, 4));
+    return at;
+  };
+  L.ctl = take(sizeof(BFCtl));
+  L.xvp = take(4 * 3 * n * Dp);
+  L.fp = take(4 * 2 * n);
+  L.gb = take(8 * (size_t)c->groups);
+  L.gpos = take(4 * (size_t)c->groups * Dp);
+  L.hyper = take(4 * 6 * (size_t)c->groups);
+  L.total = o;
+  return L;
+}
+
+sepso_status bf_hip(sepso_bf* b, hipError_t e, const char* what) {
+  b->broken = true;
+  return fail(SEPSO_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define BFCHK(b, expr)                                  \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return bf_hip(b, _e, #expr);  \
+  } while (0)
+
+sepso_status bf_usable(sepso_bf* b) {
+  if (!b) return fail(SEPSO_E_ARG, "bf handle is NULL");
+  if (b->broken) return fail(SEPSO_E_STATE, "handle is unusable after an earlier HIP error");
+  return SEPSO_OK;
+}
+
+sepso_status bf_run(sepso_bf* b, int32_t n) {
+  for (int k = 0; k < n; ++k) launch_bf_step(b->dev, true, b->stream);
+  if (n > 0) launch_bf_step(b->dev, false, b->stream);
+  BFCHK(b, hipGetLastError());
+  return SEPSO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sepso_status sepso_bf_workspace_bytes(const sepso_bf_cfg* cfg, size_t* bytes) {
+  if (!bytes) return fail(SEPSO_E_ARG, "bytes is NULL");
+  sepso_status st = bf_check(cfg);
+  if (st != SEPSO_OK) return st;
+  *bytes = bf_layout(cfg).total;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_create(const sepso_bf_cfg* cfg, void* d_ws, size_t ws_bytes, void* stream,
+                             sepso_bf** out) {
+  if (!out) return fail(SEPSO_E_ARG, "out is NULL");
+  *out = nullptr;
+  sepso_status st = bf_check(cfg);
+  if (st != SEPSO_OK) return st;
+  const BFLayout L = bf_layout(cfg);
+  if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(SEPSO_E_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(SEPSO_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  sepso_bf* b = new (std::nothrow) sepso_bf();
+  if (!b) return fail(SEPSO_E_NOMEM, "host allocation failed");
+  char* w = static_cast<char*>(d_ws);
+  const size_t n = (size_t)cfg->groups * cfg->particles;
+  BFDev& d = b->dev;
+  d.func = cfg->func;
+  d.G = cfg->groups;
+  d.N = cfg->particles;
+  d.D = cfg->dims;
+  d.Dp = (cfg->dims + 3) / 4 * 4;
+  d.T = cfg->max_iters;
+  d.lo = cfg->lo;
+  d.hi = cfg->hi;
+  d.seed_lo = (uint32_t)(cfg->seed & 0xffffffffu);
+  d.seed_hi = (uint32_t)(cfg->seed >> 32);
+  d.ctl = reinterpret_cast<BFCtl*>(w + L.ctl);
+  d.X = reinterpret_cast<float*>(w + L.xvp);
+  d.V = d.X + n * d.Dp;
+  d.P = d.V + n * d.Dp;
+  d.f = reinterpret_cast<float*>(w + L.fp);
+  d.Pf = d.f + n;
+  d.gbest_n = reinterpret_cast<int32_t*>(w + L.gb);
+  d.gbest_f = reinterpret_cast<float*>(w + L.gb + 4 * (size_t)d.G);
+  d.gbest_pos = reinterpret_cast<float*>(w + L.gpos);
+  d.hyper = reinterpret_cast<const float*>(w + L.hyper);
+  if (stream) {
+    b->stream = static_cast<hipStream_t>(stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete b;
+      return fail(SEPSO_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    b->own_stream = true;
+  }
+  hipError_t e = hipMemcpyAsync(w + L.hyper, cfg->hyper, 24 * (size_t)d.G, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e == hipSuccess) {
+    const int64_t total = (int64_t)n * d.Dp;
+    hipLaunchKernelGGL(bf_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, b->stream, d);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    st = fail(SEPSO_E_HIP, "bf create: %s", hipGetErrorString(e));
+    sepso_bf_destroy(b);
+    return st;
+  }
+  *out = b;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_destroy(sepso_bf* b) {
+  if (!b) return fail(SEPSO_E_ARG, "bf handle is NULL");
+  if (b->ev0) hipEventDestroy(b->ev0);
+  if (b->ev1) hipEventDestroy(b->ev1);
+  if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+  delete b;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_step(sepso_bf* b, int32_t n) {
+  sepso_status st = bf_usable(b);
+  if (st != SEPSO_OK) return st;
+  if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
+  return bf_run(b, n);
+}
+
+sepso_status sepso_bf_profile(sepso_bf* b, int32_t n, float* ms_per_iter) {
+  sepso_status st = bf_usable(b);
+  if (st != SEPSO_OK) return st;
+  if (n < 1 || !ms_per_iter) return fail(SEPSO_E_ARG, "n >= 1 and ms_per_iter required");
+  BFCHK(b, hipEventRecord(b->ev0, b->stream));
+  st = bf_run(b, n);
+  if (st != SEPSO_OK) return st;
+  BFCHK(b, hipEventRecord(b->ev1, b->stream));
+  BFCHK(b, hipEventSynchronize(b->ev1));
+  float ms = 0.f;
+  BFCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  *ms_per_iter = ms / (float)n;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_get_state(sepso_bf* b, sepso_bf_state* s) {
+  sepso_status st = bf_usable(b);
+  if (st != SEPSO_OK) return st;
+  if (!s) return fail(SEPSO_E_ARG, "state is NULL");
+  const BFDev& d = b->dev;
+  const size_t n = (size_t)d.G * d.N;
+  float* rows[3] = {s->X, s->V, s->P};
+  const float* src[3] = {d.X, d.V, d.P};
+  for (int a = 0; a < 3; ++a)
+    if (rows[a])
+      BFCHK(b, hipMemcpy2DAsync(rows[a], 4 * (size_t)d.D, src[a], 4 * (size_t)d.Dp, 4 * (size_t)d.D, n,
+                                hipMemcpyDeviceToHost, b->stream));
+  if (s->f) BFCHK(b, hipMemcpyAsync(s->f, d.f, 4 * n, hipMemcpyDeviceToHost, b->stream));
+  if (s->Pf) BFCHK(b, hipMemcpyAsync(s->Pf, d.Pf, 4 * n, hipMemcpyDeviceToHost, b->stream));
+  std::vector<int32_t> gn(d.G);
+  std::vector<float> gf(d.G);
+  BFCtl c{};
+  BFCHK(b, hipMemcpyAsync(gn.data(), d.gbest_n, 4 * (size_t)d.G, hipMemcpyDeviceToHost, b->stream));
+  BFCHK(b, hipMemcpyAsync(gf.data(), d.gbest_f, 4 * (size_t)d.G, hipMemcpyDeviceToHost, b->stream));
+  BFCHK(b, hipMemcpyAsync(&c, d.ctl, sizeof(BFCtl), hipMemcpyDeviceToHost, b->stream));
+  BFCHK(b, hipStreamSynchronize(b->stream));
+  if (s->gbest_n) std::memcpy(s->gbest_n, gn.data(), 4 * (size_t)d.G);
+  if (s->gbest_f) std::memcpy(s->gbest_f, gf.data(), 4 * (size_t)d.G);
+  int tg = 0;
+  for (int g = 1; g < d.G; ++g)
+    if (gf[g] < gf[tg]) tg = g;
+  s->tb_g = tg;
+  s->tb_n = gn[tg];
+  s->tb_f = gf[tg];
+  s->k = c.k;
+  s->ctr = c.ctr;
+  s->pending = c.pending;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_set_state(sepso_bf* b, const sepso_bf_state* s) {
+  sepso_status st = bf_usable(b);
+  if (st != SEPSO_OK) return st;
+  if (!s) return fail(SEPSO_E_ARG, "state is NULL");
+  const BFDev& d = b->dev;
+  const size_t n = (size_t)d.G * d.N;
+  if (s->gbest_n)
+    for (int g = 0; g < d.G; ++g)
+      if (s->gbest_n[g] < 0 || s->gbest_n[g] >= d.N) return fail(SEPSO_E_ARG, "gbest_n[%d] out of range", g);
+  if (s->k < 0) return fail(SEPSO_E_ARG, "k must be >= 0");
+  const float* rows[3] = {s->X, s->V, s->P};
+  float* dst[3] = {d.X, d.V, d.P};
+  for (int a = 0; a < 3; ++a)
+    if (rows[a])
+      BFCHK(b, hipMemcpy2DAsync(dst[a], 4 * (size_t)d.Dp, rows[a], 4 * (size_t)d.D, 4 * (size_t)d.D, n,
+                                hipMemcpyHostToDevice, b->stream));
+  if (s->f) BFCHK(b, hipMemcpyAsync(d.f, s->f, 4 * n, hipMemcpyHostToDevice, b->stream));
+  if (s->Pf) BFCHK(b, hipMemcpyAsync(d.Pf, s->Pf, 4 * n, hipMemcpyHostToDevice, b->stream));
+  if (s->gbest_n) BFCHK(b, hipMemcpyAsync(d.gbest_n, s->gbest_n, 4 * (size_t)d.G, hipMemcpyHostToDevice, b->stream));
+  if (s->gbest_f) BFCHK(b, hipMemcpyAsync(d.gbest_f, s->gbest_f, 4 * (size_t)d.G, hipMemcpyHostToDevice, b->stream));
+  // the Gbest rows follow from P and gbest_n
+  if (s->P && s->gbest_n)
+    for (int g = 0; g < d.G; ++g)
+      BFCHK(b, hipMemcpyAsync(d.gbest_pos + (size_t)g * d.Dp, s->P + ((size_t)g * d.N + s->gbest_n[g]) * d.D,
+                              4 * (size_t)d.D, hipMemcpyHostToDevice, b->stream));
+  const BFCtl c{s->k, s->ctr, s->pending, 0};
+  BFCHK(b, hipMemcpyAsync(d.ctl, &c, sizeof(BFCtl), hipMemcpyHostToDevice, b->stream));
+  BFCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
+}  // extern "C"

@@ -22,7 +22,8 @@ constexpr int kLinGroups = 8, kLinW = 20;
 constexpr int kLinOut = kLinGroups * 2 * kLinW; // 320
 
 // Philox counter tags: which random stream a draw belongs to.
-enum Tag : uint32_t { TAG_UPDATE = 0, TAG_INIT_X = 1, TAG_INIT_V = 2, TAG_PI = 3, TAG_HSEF = 4 };
+enum Tag : uint32_t { TAG_UPDATE = 0, TAG_INIT_X = 1, TAG_INIT_V = 2, TAG_PI = 3, TAG_HSEF = 4,
+                      TAG_EVOLVE = 6, TAG_EVOLVE_X = 7, TAG_EVOLVE_V = 8 };
 
 // Edge flags.
 enum : int32_t { EDGE_FIRST = 1, EDGE_LAST = 2 };
@@ -57,7 +58,11 @@ struct InstDesc {
   uint32_t seed_lo, seed_hi, instance;
   int64_t xo;            // X, V, P pools: G*N*2W floats
   int64_t po;            // per-particle pools: G*N
-  int32_t eo;            // edge records (n_edges) and vertices (n_edges float2)
+  int32_t eo;            // vertices (n_edges float2)
+  int32_t n_rects;       // polygons that are axis-aligned rectangles
+  int32_t n_gedges;      // edges of the other polygons
+  int32_t ro;            // rectangle records (n_rects float4: x0, y0, x1, y1)
+  int32_t geo;           // general edge records (n_gedges)
   int32_t plo;           // poly_ptr pool (n_polys+1)
   int32_t pvo;           // poly_vel pool (n_polys float2)
   int32_t go;            // group pools: G (gbest_n/f, outer Pbest fitness), G*6 hyper, G*3 outer
@@ -99,7 +104,9 @@ struct Pools {
   float *X, *V, *P;
   float *f, *L, *Pf, *PL;
   int32_t *Q, *PQ;
-  EdgeRec* edges;
+  EdgeRec* edges;    // general polygons' edges
+  float4* rects;     // axis-aligned rectangles (x0, y0, x1, y1), x0 < x1, y0 < y1
+  int2* pkind;       // per polygon: (1 = rectangle / 0 = general, slot in its pool)
   float2* verts;
   int32_t* poly_ptr;
   float2* poly_vel;
@@ -118,6 +125,34 @@ struct Pools {
   float* proposal;   // G*2W learned initial path per group (layout of gbest_pos)
   const int2* blk_tiles;  // fused-iteration block -> (instance, first particle)
   const int2* blk_init;   // init block -> (instance, first element)
+};
+
+// Evolution phase: the higher-level swarm (H-SEPSO) over whole lower-level
+// hyper matrices.  H particle i drives lower-level instance i.
+constexpr int kEvolveMaxH = 1024;  // H particles (one block moves them all)
+
+struct EvolveCtl {
+  int32_t k;      // evolutions done
+  uint32_t ctr;   // random stream position of the move
+  int32_t tb_g, tb_n;
+  float tb_f;
+  int32_t pad[3];
+};
+
+struct EvolveDev {
+  int32_t Gh, Nh, Dh, E;       // H groups, particles per group, dims (6 G_L), schedule length
+  uint32_t seed_lo, seed_hi;
+  float *X, *V, *P;            // Gh*Nh*Dh
+  float* Pf;                   // Gh*Nh
+  float* lfv;                  // fitness of the last evolution
+  int32_t* gbest_n;            // Gh
+  float* gbest_f;              // Gh
+  const float* h_hyper;        // Gh*6
+  const float* lo;             // 6 per-column bounds
+  const float* hi;             // 6
+  const float* lfv_in;         // injected fitness (n) or null: lower level's frame result
+  float* curve;                // total best after evolution k, at (k-1) mod E
+  EvolveCtl* ctl;
 };
 
 // Kernel flags of the fused iteration.

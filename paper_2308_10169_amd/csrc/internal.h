@@ -30,6 +30,8 @@ struct Layout {
   size_t desc, ctl, X, V, P, f, L, Pf, PL, Q, PQ, edges, verts, pptr, pvel, ends, endv, gbn, gbf, hyper, ohyper, ov, op, opf, gpos, tpos, prev, prop, blkt, blki, total;
   int64_t sumPD = 0, sumP = 0, sumTilesMax = 0;
   int64_t sumE = 0, sumPP = 0, sumPoly = 0, sumG = 0, sumGD = 0, sumD = 0, initBlocks = 0;
+  int64_t sumR = 0, sumGE = 0;  // rectangles, edges of other polygons
+  size_t rects = 0, pkind = 0;
 };
 
 }  // namespace sepso
@@ -41,6 +43,7 @@ struct sepso_batch {
   std::vector<sepso::InstDesc> desc;
   std::vector<int> n_vert;
   std::vector<int32_t> h_pptr;  // polygon offsets of instance 0
+  std::vector<int2> h_kind;     // polygon kinds of instance 0
   std::vector<int64_t> path_off;
   sepso::Layout lay{};
   sepso::Pools pl{};
@@ -51,6 +54,7 @@ struct sepso_batch {
   sepso_tune tune{16, 256};
   int tile_blocks = 0;
   int frames_done = 0;
+  int tune_gen = 0;  // bumped whenever the tile plan changes (captured graphs go stale)
   // pinned host mirrors
   sepso::InstCtl* h_ctl = nullptr;
   float* h_paths = nullptr;

@@ -1,54 +1,21 @@
-// libsepso device code (gfx950, FP32 VALU).
+// libsepso device code for path planning (gfx950, FP32 VALU).
 //
 // Kernels:
-//   geom_kernel  -- obstacle/endpoint motion for one frame and the derived
-//                   per-edge records the fitness test reads;
-//   init_kernel  -- uniform swarm and Priori Initialization;
-//   step_kernel  -- one fused DTPSO iteration per launch: the previous
-//                   iteration's velocity/position update (Eq.(6)-(8)), the
-//                   path fitness (Eq.(11)-(13)), the Pbest update and a tile
-//                   argmin; the last block of each instance to finish reduces
-//                   the group and total bests and runs Auto Truncation and
-//                   the online hierarchical self-evolution step.
+//   geom_kernel   -- obstacle/endpoint motion for one frame and the derived
+//                    rectangle boxes / per-edge records the fitness reads;
+//   init_kernel   -- uniform swarm and Priori Initialization;
+//   iter_kernel   -- one fused DTPSO iteration per launch: the previous
+//                    iteration's velocity/position update (Eq.(6)-(8)), the
+//                    path fitness (Eq.(11)-(13)) and the Pbest update;
+//   update_kernel -- the pending update alone (end of a stepping call);
+//   reduce_kernel -- per instance: group and total bests, Auto Truncation,
+//                    the online self-evolution step, control advance;
+//   evolve_*      -- the evolution phase's higher level (H-SEPSO).
 #include "common.h"
 #include "kernels.h"
+#include "rng.h"
 
 namespace sepso {
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
-// multiplies by fixed odd constants; high halves are xor-mixed with the other
-// two counter words and the round key, the key advances by two Weyl constants.
-// ---------------------------------------------------------------------------
-struct U4 {
-  uint32_t v[4];
-};
-
-__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                     uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  return U4{{c0, c1, c2, c3}};
-}
-
-// 24-bit uniform in [0,1), exact in FP32.
-__device__ __forceinline__ float u01(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }
-
-__device__ __forceinline__ float clampf(float x, float lo, float hi) {
-  return x < lo ? lo : (x > hi ? hi : x);
-}
 
 __device__ __forceinline__ bool better(float fa, int na, float fb, int nb) {
   return fa < fb || (fa == fb && na < nb);
@@ -112,9 +79,22 @@ __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
     }
     __syncthreads();
   }
-  EdgeRec* er = pl.edges + d.eo;
+  const int2* kind = pl.pkind + d.pvo;
   for (int q = t; q < d.n_polys; q += blockDim.x) {
     const int v0 = pp[q], m = pp[q + 1] - v0;
+    const int2 ks = kind[q];
+    if (ks.x == 1) {  // axis-aligned rectangle: its bounding box
+      float x0 = verts[v0].x, y0 = verts[v0].y, x1 = x0, y1 = y0;
+      for (int j = 1; j < m; ++j) {
+        x0 = fminf(x0, verts[v0 + j].x);
+        x1 = fmaxf(x1, verts[v0 + j].x);
+        y0 = fminf(y0, verts[v0 + j].y);
+        y1 = fmaxf(y1, verts[v0 + j].y);
+      }
+      pl.rects[d.ro + ks.y] = make_float4(x0, y0, x1, y1);
+      continue;
+    }
+    EdgeRec* er = pl.edges + d.geo + ks.y;
     for (int j = 0; j < m; ++j) {
       const float2 a = verts[v0 + j], b = verts[v0 + (j + 1 == m ? 0 : j + 1)];
       EdgeRec r;
@@ -127,7 +107,7 @@ __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
       r.ax = a.x;
       r.ay = a.y;
       r.flags = (j == 0 ? EDGE_FIRST : 0) | (j == m - 1 ? EDGE_LAST : 0);
-      er[v0 + j] = r;
+      er[j] = r;
     }
   }
 }
@@ -231,17 +211,24 @@ __device__ __forceinline__ uint32_t pack_seg_sides(float bx, float by, const flo
 // Auto Truncation (Sec. "Auto Truncation") on the Tbest history ring.
 __device__ bool at_fires(const float* hist, int k, int mode, int window, float delta, int q) {
   if (mode == 0 || q != 0 || window < 1) return false;
-  if (mode == 1) {
-    if (k < window) return false;
+  if (mode == 1 || mode == 3) {
+    // mode 1: the full window must have elapsed; mode 3: the window is
+    // whatever has elapsed (at least two values), capped at `window`
+    int w = window;
+    if (mode == 1 && k < window) return false;
+    if (mode == 3) {
+      if (k < 2) return false;
+      w = k < window ? k : window;
+    }
     float mean = 0.f;
-    for (int i = k - window; i < k; ++i) mean += hist[i % kHist];
-    mean /= (float)window;
+    for (int i = k - w; i < k; ++i) mean += hist[i % kHist];
+    mean /= (float)w;
     float var = 0.f;
-    for (int i = k - window; i < k; ++i) {
+    for (int i = k - w; i < k; ++i) {
       const float dv = hist[i % kHist] - mean;
       var += dv * dv;
     }
-    var /= (float)window;
+    var /= (float)w;
     return sqrtf(var) < delta;
   }
   if (mode == 2) {
@@ -482,6 +469,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     const float* hy = pl.hyper + d.go * 6;
     const int kk = k < d.T ? k : d.T;
     const int nel = np * D;
+#pragma unroll 4
     for (int e = t; e < nel; e += B) {
       float x = X[e];
       if (pending) {
@@ -535,12 +523,16 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
 #pragma unroll
   for (int s = 0; s < K; ++s) {
     const float ddx = px[s + 1] - px[s], ddy = py[s + 1] - py[s];
-    dx[s] = ddx;
-    ndy[s] = -ddy;
-    nc[s] = fmaf(ddy, px[s], -(ddx * py[s]));
     const int m = t * K + s;  // slot between points m and m+1
     const int jm = m / S;
-    if (m < n_pts - 1 && m - jm * S != S - 1) {
+    const bool seg = m < n_pts - 1 && m - jm * S != S - 1;
+    // A slot that is no path segment (a junction or past the stream's end)
+    // gets the zero line: every vertex side is +0 (coordinates are >= 0),
+    // so its side bits never differ and it never counts as a crossing.
+    dx[s] = seg ? ddx : 0.f;
+    ndy[s] = seg ? -ddy : 0.f;
+    nc[s] = seg ? fmaf(ddy, px[s], -(ddx * py[s])) : 0.f;
+    if (seg) {
       const float len = sqrtf(ddx * ddx + ddy * ddy);
       const uint32_t bit = 1u << (K - 1 - s);
       const int pc = jm - jf;
@@ -559,14 +551,66 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   __syncthreads();  // positions consumed: s_buf now stages edges
 
   // ---- C. crossings ----------------------------------------------------------
-  int c0 = 0, c1 = 0, c2 = 0;
+  // Crossing words: bit K-1-s set when segment s properly crosses the edge
+  // (never for masked slots); counted as a total plus pieces 0 and 2 (piece
+  // 1 = the rest).
+  int ct = 0, c0 = 0, c2 = 0;
+  const bool three = __any(mk2 != 0u);  // wave-uniform: some lane has a third piece
+  auto count = [&](uint32_t x) {
+    ct += __popc(x);
+    c0 += __popc(x & mk0);
+    if (three) c2 += __popc(x & mk2);
+  };
+  // C1. axis-aligned rectangles.  Edge sides are exact sign tests of one
+  // coordinate difference; corner sides: (x0,y0) and (x1,y1) as two FMAs,
+  // (x1,y0) and (x0,y1) from (x0,y0) by one FMA each.
+  const float4* rr = pl.rects + d.ro;
+  float4* s_rect = reinterpret_cast<float4*>(s_buf);
+  const int rchunk = pl.buf_floats / 4;
+  for (int r0 = 0; r0 < d.n_rects; r0 += rchunk) {
+    const int nr = d.n_rects - r0 < rchunk ? d.n_rects - r0 : rchunk;
+    if (r0 > 0) __syncthreads();
+    for (int q = t; q < nr; q += B) s_rect[q] = rr[r0 + q];
+    __syncthreads();
+    if (active) {
+      for (int e = 0; e < nr; ++e) {
+        const float4 b = s_rect[e];  // x0, y0, x1, y1
+        const float w = b.z - b.x, h = b.w - b.y;
+        uint32_t w00 = 0, w10 = 0, w11 = 0, w01 = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+          const float o00 = fmaf(dx[s], b.y, fmaf(ndy[s], b.x, nc[s]));
+          const float o11 = fmaf(dx[s], b.w, fmaf(ndy[s], b.z, nc[s]));
+          const float o10 = fmaf(ndy[s], w, o00);
+          const float o01 = fmaf(dx[s], h, o00);
+          w00 = __builtin_amdgcn_alignbit(w00, __float_as_uint(o00), 31);
+          w10 = __builtin_amdgcn_alignbit(w10, __float_as_uint(o10), 31);
+          w11 = __builtin_amdgcn_alignbit(w11, __float_as_uint(o11), 31);
+          w01 = __builtin_amdgcn_alignbit(w01, __float_as_uint(o01), 31);
+        }
+        uint32_t eb = 0, eR = 0, eT = 0, eL = 0;
+#pragma unroll
+        for (int s = 0; s <= K; ++s) {
+          eb = __builtin_amdgcn_alignbit(eb, __float_as_uint(py[s] - b.y), 31);
+          eR = __builtin_amdgcn_alignbit(eR, __float_as_uint(px[s] - b.z), 31);
+          eT = __builtin_amdgcn_alignbit(eT, __float_as_uint(py[s] - b.w), 31);
+          eL = __builtin_amdgcn_alignbit(eL, __float_as_uint(px[s] - b.x), 31);
+        }
+        count((w00 ^ w10) & (eb ^ (eb >> 1)));  // bottom
+        count((w10 ^ w11) & (eR ^ (eR >> 1)));  // right
+        count((w11 ^ w01) & (eT ^ (eT >> 1)));  // top
+        count((w01 ^ w00) & (eL ^ (eL >> 1)));  // left
+      }
+    }
+  }
+  // C2. other polygons, edge by edge.
   uint32_t w0 = 0, wp = 0;
-  const EdgeRec* er = pl.edges + d.eo;
+  const EdgeRec* er = pl.edges + d.geo;
   EdgeRec* s_edge = reinterpret_cast<EdgeRec*>(s_buf);
   const int chunk = pl.buf_floats / 8;  // edge records per LDS pass
-  for (int e0 = 0; e0 < d.n_edges; e0 += chunk) {
-    const int ne = d.n_edges - e0 < chunk ? d.n_edges - e0 : chunk;
-    if (e0 > 0) __syncthreads();
+  for (int e0 = 0; e0 < d.n_gedges; e0 += chunk) {
+    const int ne = d.n_gedges - e0 < chunk ? d.n_gedges - e0 : chunk;
+    if (e0 > 0 || d.n_rects > 0) __syncthreads();
     {
       const float4* src = reinterpret_cast<const float4*>(er + e0);
       float4* dst = reinterpret_cast<float4*>(s_buf);
@@ -595,14 +639,12 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
         }
         // segment s straddles the edge's line iff points s and s+1 differ;
         // the edge straddles segment s's line iff its two vertices differ.
-        const uint32_t x = (wp ^ wn) & (ew ^ (ew >> 1));
-        c0 += __popc(x & mk0);
-        c1 += __popc(x & mk1);
-        c2 += __popc(x & mk2);
+        count((wp ^ wn) & (ew ^ (ew >> 1)));
         wp = wn;
       }
     }
   }
+  const int c1 = ct - c0 - c2;
 
   // ---- D. per-particle fitness and Pbest -------------------------------------
   s_q[3 * t + 0] = c0;
@@ -701,6 +743,129 @@ void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, h
     case 24: launch_k<24>(pl, n_blocks, threads, flags, s); break;
     default: break;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Evolution phase (Sec. "Hierarchical Self-evolving Framework", Eq.(9)): H
+// particle i is lower-level instance i's whole (G_L, 6) hyper matrix; its
+// fitness is that instance's frame result (the lowest fitness value of a full
+// lower-level run).  Column c of a row is boxed to [lo[c], hi[c]].
+// ---------------------------------------------------------------------------
+
+// Uniform positions in the box, velocities in +-V_limit * half the column's
+// extent; the lower level's hyper pool receives the positions.
+__global__ __launch_bounds__(256) void evolve_init_kernel(EvolveDev ev, Pools pl) {
+  const int n = ev.Gh * ev.Nh, Dh = ev.Dh, nb = (Dh + 3) / 4;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n * Dh) {
+    const int i = e / Dh, d = e - i * Dh, c = d % 6, g = i / ev.Nh;
+    const float lo = ev.lo[c], hi = ev.hi[c];
+    const float vmax = ev.h_hyper[6 * g + 5] * (hi - lo) * 0.5f;
+    const uint32_t c0 = (uint32_t)(i * nb + d / 4);
+    const U4 rx = philox(c0, 0u, 0u, TAG_EVOLVE_X, ev.seed_lo, ev.seed_hi);
+    const U4 rv = philox(c0, 0u, 0u, TAG_EVOLVE_V, ev.seed_lo, ev.seed_hi);
+    const float x = lo + u01(rx.v[d & 3]) * (hi - lo);
+    ev.X[e] = x;
+    ev.P[e] = x;
+    ev.V[e] = -vmax + u01(rv.v[d & 3]) * (2.f * vmax);
+    pl.hyper[6 * pl.desc[i].go + d] = x;
+  }
+  if (e < n) {
+    ev.Pf[e] = INFINITY;
+    ev.lfv[e] = INFINITY;
+  }
+  if (e < ev.Gh) {
+    ev.gbest_n[e] = 0;
+    ev.gbest_f[e] = INFINITY;
+  }
+  if (e == 0) {
+    ev.ctl->k = 0;
+    ev.ctl->ctr = 0u;
+    ev.ctl->tb_g = ev.ctl->tb_n = 0;
+    ev.ctl->tb_f = INFINITY;
+  }
+}
+
+// One evolution after the lower-level frame: H bests (Pbest = running
+// minimum, Gbest = lowest Pbest of the group, lowest index on ties; Tbest =
+// lowest Gbest), then the move of Eq.(6)-(8) with one (r1, r2, r3) per H
+// particle; new positions go to the lower level's hyper pool.  One block.
+__global__ __launch_bounds__(1024) void evolve_step_kernel(EvolveDev ev, Pools pl, int injected) {
+  __shared__ float s_r[3 * kEvolveMaxH];
+  __shared__ int s_imp[kEvolveMaxH];
+  __shared__ float s_gf[kMaxG];
+  __shared__ int s_gn[kMaxG];
+  __shared__ int s_tg;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int Gh = ev.Gh, Nh = ev.Nh, n = Gh * Nh, Dh = ev.Dh;
+  const int k = ev.ctl->k + 1;
+  const uint32_t ctr = ev.ctl->ctr;
+  for (int i = t; i < n; i += nt) {
+    float f = injected ? ev.lfv_in[i] : pl.ctl[i].res_cost;
+    if (!(fabsf(f) <= 3.402823466e38f)) f = INFINITY;  // NaN / inf -> +inf
+    ev.lfv[i] = f;
+    const bool imp = f < ev.Pf[i];
+    if (imp) ev.Pf[i] = f;
+    s_imp[i] = imp;
+    const U4 r = philox((uint32_t)i, ctr, 0u, TAG_EVOLVE, ev.seed_lo, ev.seed_hi);
+    s_r[3 * i + 0] = u01(r.v[0]);
+    s_r[3 * i + 1] = u01(r.v[1]);
+    s_r[3 * i + 2] = u01(r.v[2]);
+  }
+  __syncthreads();
+  for (int e = t; e < n * Dh; e += nt)
+    if (s_imp[e / Dh]) ev.P[e] = ev.X[e];
+  if (t < Gh) {
+    int b = 0;
+    for (int m = 1; m < Nh; ++m)
+      if (ev.Pf[t * Nh + m] < ev.Pf[t * Nh + b]) b = m;
+    s_gn[t] = b;
+    s_gf[t] = ev.Pf[t * Nh + b];
+    ev.gbest_n[t] = b;
+    ev.gbest_f[t] = s_gf[t];
+  }
+  __syncthreads();
+  if (t == 0) {
+    int tg = 0;
+    for (int g = 1; g < Gh; ++g)
+      if (s_gf[g] < s_gf[tg]) tg = g;
+    s_tg = tg;
+  }
+  __syncthreads();
+  const int tg = s_tg, tn = s_gn[tg];
+  const int kk = k < ev.E ? k : ev.E;
+  for (int e = t; e < n * Dh; e += nt) {
+    const int i = e / Dh, d = e - i * Dh, c = d % 6, g = i / Nh;
+    const float* hy = ev.h_hyper + 6 * g;
+    const float w = hy[3] - (hy[3] - hy[4]) / (float)ev.E * (float)kk;
+    const float lo = ev.lo[c], hi = ev.hi[c], vmax = hy[5] * (hi - lo) * 0.5f;
+    const float x = ev.X[e], p = ev.P[e];
+    const float gb = ev.P[(g * Nh + s_gn[g]) * Dh + d], tb = ev.P[(tg * Nh + tn) * Dh + d];
+    float v = w * ev.V[e] + hy[0] * s_r[3 * i] * (p - x) + hy[1] * s_r[3 * i + 1] * (gb - x) +
+              hy[2] * s_r[3 * i + 2] * (tb - x);
+    v = clampf(v, -vmax, vmax);
+    const float xn = clampf(x + v, lo, hi);
+    ev.V[e] = v;
+    ev.X[e] = xn;
+    pl.hyper[6 * pl.desc[i].go + d] = xn;
+  }
+  if (t == 0) {
+    ev.curve[(k - 1) % ev.E] = s_gf[tg];
+    ev.ctl->k = k;
+    ev.ctl->ctr = ctr + 1u;
+    ev.ctl->tb_g = tg;
+    ev.ctl->tb_n = tn;
+    ev.ctl->tb_f = s_gf[tg];
+  }
+}
+
+void launch_evolve_init(const EvolveDev& ev, const Pools& pl, hipStream_t s) {
+  const int total = ev.Gh * ev.Nh * ev.Dh;
+  hipLaunchKernelGGL(evolve_init_kernel, dim3((total + 255) / 256), dim3(256), 0, s, ev, pl);
+}
+
+void launch_evolve_step(const EvolveDev& ev, const Pools& pl, int injected, hipStream_t s) {
+  hipLaunchKernelGGL(evolve_step_kernel, dim3(1), dim3(1024), 0, s, ev, pl, injected);
 }
 
 }  // namespace sepso

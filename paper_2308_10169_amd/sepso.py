@@ -62,6 +62,29 @@ class CTune(C.Structure):
     _fields_ = [("seg_per_thread", C.c_int32), ("block_threads", C.c_int32)]
 
 
+class CBFCfg(C.Structure):
+    _fields_ = [("func", C.c_int32), ("groups", C.c_int32), ("particles", C.c_int32),
+                ("dims", C.c_int32), ("max_iters", C.c_int32), ("hyper", fp), ("lo", C.c_float),
+                ("hi", C.c_float), ("seed", C.c_uint64)]
+
+
+class CBFState(C.Structure):
+    _fields_ = [("X", fp), ("V", fp), ("P", fp), ("f", fp), ("Pf", fp), ("gbest_n", ip),
+                ("gbest_f", fp), ("tb_g", C.c_int32), ("tb_n", C.c_int32), ("tb_f", C.c_float),
+                ("k", C.c_int32), ("ctr", C.c_uint32), ("pending", C.c_int32)]
+
+
+class CEvolveCfg(C.Structure):
+    _fields_ = [("h_groups", C.c_int32), ("h_particles", C.c_int32), ("evolutions", C.c_int32),
+                ("h_hyper", fp), ("lo", fp), ("hi", fp), ("seed", C.c_uint64)]
+
+
+class CEvolveState(C.Structure):
+    _fields_ = [("X", fp), ("V", fp), ("P", fp), ("Pf", fp), ("lfv", fp), ("gbest_n", ip),
+                ("gbest_f", fp), ("tb_g", C.c_int32), ("tb_n", C.c_int32), ("tb_f", C.c_float),
+                ("k", C.c_int32), ("ctr", C.c_uint32)]
+
+
 _lib = None
 _torch = None
 
@@ -104,6 +127,24 @@ def _load():
     L.sepso_autotune.argtypes = [vp, C.POINTER(CTune)]
     L.sepso_batch_work.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.sepso_batch_history.argtypes = [vp, fp]
+    L.sepso_batch_set_tune.argtypes = [vp, C.POINTER(CTune)]
+    L.sepso_bf_workspace_bytes.argtypes = [C.POINTER(CBFCfg), C.POINTER(sz)]
+    L.sepso_bf_create.argtypes = [C.POINTER(CBFCfg), vp, sz, vp, C.POINTER(vp)]
+    L.sepso_bf_destroy.argtypes = [vp]
+    L.sepso_bf_step.argtypes = [vp, C.c_int32]
+    L.sepso_bf_profile.argtypes = [vp, C.c_int32, fp]
+    L.sepso_bf_get_state.argtypes = [vp, C.POINTER(CBFState)]
+    L.sepso_bf_set_state.argtypes = [vp, C.POINTER(CBFState)]
+    L.sepso_evolve_workspace_bytes.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm),
+                                               C.POINTER(CEvolveCfg), C.POINTER(sz)]
+    L.sepso_evolve_create.argtypes = [C.POINTER(CMap), C.POINTER(CSwarm), C.POINTER(CEvolveCfg),
+                                      vp, sz, vp, C.POINTER(vp)]
+    L.sepso_evolve_destroy.argtypes = [vp]
+    L.sepso_evolve_run.argtypes = [vp, C.c_int32, fp]
+    L.sepso_evolve_inject.argtypes = [vp, fp]
+    L.sepso_evolve_get_state.argtypes = [vp, C.POINTER(CEvolveState)]
+    L.sepso_evolve_best.argtypes = [vp, fp, fp]
+    L.sepso_evolve_lower.argtypes = [vp, C.POINTER(vp)]
     L.sepso_lin_param_count.restype = C.c_int64
     L.sepso_lin_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.POINTER(sz)]
     L.sepso_lin_create.argtypes = [C.c_int32, C.c_int64, C.c_uint64, vp, sz, vp, C.POINTER(vp)]
@@ -356,6 +397,168 @@ class BatchPlanner:
 
     def attach(self, lin):
         _check(_lib.sepso_lin_attach(self.h, lin.h if lin is not None else None))
+
+    def set_tune(self, K, B):
+        _check(_lib.sepso_batch_set_tune(self.h, C.byref(CTune(int(K), int(B)))))
+
+
+class Evolver:
+    """Evolution phase (sepso_evolve): H-SEPSO over whole lower-level hyper
+    matrices, each H particle's fitness the LFV of a full lower-level run of
+    its own batch instance."""
+
+    def __init__(self, spec, lower, h_groups=8, h_particles=8, evolutions=500, seed=0,
+                 h_hyper=None, lo=None, hi=None, stream=None):
+        L = _load()
+        torch = _torch
+        self.spec, self.lower = spec, lower
+        self.n, self.Dh = h_groups * h_particles, 6 * lower.groups
+        self.Gh, self.E = h_groups, evolutions
+        self._m, self._s = _MapArgs(spec), _SwarmArgs(lower)
+        self._keep = [None if a is None else _f32(a).reshape(-1) for a in (h_hyper, lo, hi)]
+        ptr = lambda a: a.ctypes.data_as(fp) if a is not None else None
+        self._cfg = CEvolveCfg(h_groups, h_particles, evolutions, *[ptr(a) for a in self._keep],
+                               int(seed))
+        nbytes = C.c_size_t()
+        _check(L.sepso_evolve_workspace_bytes(C.byref(self._m.c), C.byref(self._s.c),
+                                              C.byref(self._cfg), C.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = C.c_void_p()
+        _check(L.sepso_evolve_create(C.byref(self._m.c), C.byref(self._s.c), C.byref(self._cfg),
+                                     C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        b = C.c_void_p()
+        _check(L.sepso_evolve_lower(h, C.byref(b)))
+        self._lower_h = b
+
+    def close(self):
+        if self.h:
+            _check(_lib.sepso_evolve_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, n=1):
+        """n evolutions; returns the total-best LFV after each."""
+        out = np.zeros(max(int(n), 1), np.float32)
+        done = 0
+        while done < n:
+            m = min(n - done, self.E)
+            _check(_lib.sepso_evolve_run(self.h, int(m), out[done:].ctypes.data_as(fp)))
+            done += m
+        return out[:n]
+
+    def inject(self, lfv):
+        v = np.ascontiguousarray(lfv, dtype=np.float32)
+        assert v.size == self.n
+        _check(_lib.sepso_evolve_inject(self.h, v.ctypes.data_as(fp)))
+
+    def get_state(self):
+        z = lambda *sh: np.zeros(sh, np.float32)
+        b = dict(X=z(self.n, self.Dh), V=z(self.n, self.Dh), P=z(self.n, self.Dh), Pf=z(self.n),
+                 lfv=z(self.n), gbest_n=np.zeros(self.Gh, np.int32), gbest_f=z(self.Gh))
+        cs = CEvolveState()
+        for k, v in b.items():
+            setattr(cs, k, v.ctypes.data_as(ip if v.dtype == np.int32 else fp))
+        _check(_lib.sepso_evolve_get_state(self.h, C.byref(cs)))
+        b.update(tbest=(cs.tb_g, cs.tb_n, cs.tb_f), k=cs.k, ctr=cs.ctr)
+        return b
+
+    def best(self):
+        hyper = np.zeros(self.Dh, np.float32)
+        f = C.c_float()
+        _check(_lib.sepso_evolve_best(self.h, hyper.ctypes.data_as(fp), C.byref(f)))
+        return hyper.reshape(-1, 6), f.value
+
+    def lower_state(self, i):
+        sw = self.lower
+        b = _state_buffers(sw.groups, sw.particles, sw.waypoints)
+        cs = _cstate(b)
+        _check(_lib.sepso_batch_get_state(self._lower_h, int(i), C.byref(cs)))
+        b.update(tbest=(cs.tbest_g, cs.tbest_n, cs.tbest_f), k=cs.k, ctr=cs.ctr, frame=cs.frame)
+        return b
+
+    def set_tune(self, K, B):
+        _check(_lib.sepso_batch_set_tune(self._lower_h, C.byref(CTune(int(K), int(B)))))
+
+    def autotune(self):
+        t = CTune()
+        _check(_lib.sepso_autotune(self._lower_h, C.byref(t)))
+        return (t.seg_per_thread, t.block_threads)
+
+
+BF_FUNCS = {"sphere": 1, "rosenbrock": 2, "rastrigin": 3, "griewank": 4}
+
+
+class BFSwarm:
+    """DTPSO on a benchmark function of Table BFs (sepso_bf)."""
+
+    def __init__(self, func, groups, particles, dims, iters, hyper, lo=-600.0, hi=600.0, seed=0,
+                 stream=None):
+        L = _load()
+        torch = _torch
+        self.G, self.N, self.D = groups, particles, dims
+        self._hyper = _f32(hyper).reshape(-1)
+        f = BF_FUNCS.get(func, func)
+        self._cfg = CBFCfg(int(f), groups, particles, dims, iters,
+                           self._hyper.ctypes.data_as(fp), float(lo), float(hi), int(seed))
+        nbytes = C.c_size_t()
+        _check(L.sepso_bf_workspace_bytes(C.byref(self._cfg), C.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = C.c_void_p()
+        _check(L.sepso_bf_create(C.byref(self._cfg), C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(_lib.sepso_bf_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(_lib.sepso_bf_step(self.h, int(n)))
+
+    def profile(self, n):
+        ms = C.c_float()
+        _check(_lib.sepso_bf_profile(self.h, int(n), C.byref(ms)))
+        return ms.value
+
+    def get_state(self, rows=True):
+        G, N, D = self.G, self.N, self.D
+        z = lambda *sh: np.zeros(sh, np.float32)
+        b = dict(f=z(G, N), Pf=z(G, N), gbest_n=np.zeros(G, np.int32), gbest_f=z(G))
+        if rows:
+            b.update(X=z(G, N, D), V=z(G, N, D), P=z(G, N, D))
+        cs = CBFState()
+        for k, v in b.items():
+            setattr(cs, k, v.ctypes.data_as(ip if v.dtype == np.int32 else fp))
+        _check(_lib.sepso_bf_get_state(self.h, C.byref(cs)))
+        b.update(tbest=(cs.tb_g, cs.tb_n, cs.tb_f), k=cs.k, ctr=cs.ctr, pending=cs.pending)
+        return b
+
+    def set_state(self, st):
+        cs = CBFState()
+        keep = {}
+        for k in ("X", "V", "P", "f", "Pf", "gbest_f", "gbest_n"):
+            if st.get(k) is not None:
+                dt = np.int32 if k == "gbest_n" else np.float32
+                keep[k] = np.ascontiguousarray(st[k], dtype=dt)
+                setattr(cs, k, keep[k].ctypes.data_as(ip if dt == np.int32 else fp))
+        cs.k, cs.ctr, cs.pending = int(st.get("k", 0)), int(st.get("ctr", 0)), int(st.get("pending", 0))
+        _check(_lib.sepso_bf_set_state(self.h, C.byref(cs)))
 
 
 LIN_IN, LIN_OUT, LIN_HIDDEN = 4100, 320, 512

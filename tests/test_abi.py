@@ -54,7 +54,7 @@ def test_workspace_bytes_valid(lib):
 
 @pytest.mark.parametrize("field,value", [("groups", 0), ("groups", 65), ("waypoints", 0),
                                          ("waypoints", 65), ("particles", 0), ("beta", 0),
-                                         ("max_iters", 0), ("at_mode", 3), ("at_window", 64),
+                                         ("max_iters", 0), ("at_mode", 4), ("at_mode", -1), ("at_window", 64),
                                          ("hsef_every", -1)])
 def test_bad_swarm_rejected(lib, field, value):
     m, s = _args()
