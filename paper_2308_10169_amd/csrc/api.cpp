@@ -234,14 +234,20 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
 // particles (K <= 2(W+2) for the shortest path) and the block's positions
 // fit the LDS buffer (B*K <= 4096 slots).
 bool tune_ok(int K, int B, int w_min) {
-  return step_supported(K) && (B == 64 || B == 128 || B == 256) && K <= 2 * (w_min + 2) &&
-         B * K <= 4096;
+  if (!(step_supported(K) && (B == 64 || B == 128 || B == 256) && K <= 2 * (w_min + 2) &&
+        B * K <= 4096))
+    return false;
+  // dynamic LDS of the fused iteration stays within 64 KiB: positions
+  // (< 2BK floats), 5 words per particle, the group table, 6 words per thread
+  const size_t ppb = (size_t)(B * K) / (w_min + 2);
+  const size_t words = std::max<size_t>(2048, 2 * (size_t)B * K) + 5 * ppb + 2 * kMaxG + 6 * (size_t)B;
+  return 4 * words <= 65536;
 }
 
 sepso_tune default_tune(int w_min) {
-  for (int K : {16, 12, 8, 4})
+  for (int K : {8, 4})
     if (tune_ok(K, 128, w_min)) return sepso_tune{K, 128};
-  return sepso_tune{4, 128};
+  return sepso_tune{4, 64};
 }
 
 }  // namespace

@@ -409,161 +409,27 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Fused iteration over one block = ppb consecutive particles of an instance
-// (flat index g*N + n, possibly spanning groups).
-//
-//  A. previous iteration's update, elementwise and coalesced over the
-//     block's contiguous (particle, coordinate) range; new positions also
-//     go to LDS;
-//  B. the block's paths are laid end to end as a stream of points (start,
-//     W waypoints, target per particle); thread t takes the K segments
-//     starting at stream slot tK.  A slot joining one particle's target to
-//     the next one's start is not a path segment and is masked out; a
-//     thread's K segments belong to at most three particles ("pieces");
-//  C. crossings of the K segments with every obstacle edge (edges staged in
-//     LDS, reusing the position buffer): per edge, one packed side word of
-//     the edge's end vertex against the K segment lines and one of the K+1
-//     points against the edge line; crossing bits = both straddle;
-//  D. per-particle Q and L summed in thread order (deterministic), fitness
-//     and Pbest; improved particles' positions go to P.
-// ---------------------------------------------------------------------------
-template <int K, bool FIT>
-__device__ __forceinline__ void iteration(const Pools& pl, int flags) {
-  // dynamic LDS: positions / edge chunk | r1..r3 per particle | Pbest flags |
-  // per-thread piece counts and lengths
-  extern __shared__ __attribute__((aligned(16))) float s_dyn[];
-  float* s_buf = s_dyn;
-  float* s_r = s_buf + pl.buf_floats;
-  int* s_imp = reinterpret_cast<int*>(s_r + 3 * pl.ppb_max);
-  int* s_q = s_imp + pl.ppb_max;
-  float* s_l = reinterpret_cast<float*>(s_q + 3 * blockDim.x);
-
-  const int2 bt = pl.blk_tiles[blockIdx.x];
-  const int inst = bt.x, p0 = bt.y;
-  const InstDesc& d = pl.desc[inst];
-  InstCtl* ctl = pl.ctl + inst;
-  if ((flags & STEP_FRAME) && ctl->done) return;
-  const int k = ctl->k, pending = ctl->pending;
-  const uint32_t ctr = ctl->ctr;
-  const int N = d.N, W = d.W, D = 2 * W, S = W + 2;
-  const int np = min(d.ppb, d.G * N - p0);  // particles in this block
-  const int t = threadIdx.x, B = blockDim.x;
-
-  // ---- A. update (coalesced) ----------------------------------------------
-  if (pending) {
-    for (int j = t; j < np; j += B) {
-      const U4 r = philox((uint32_t)(p0 + j), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
-      s_r[3 * j + 0] = u01(r.v[0]);
-      s_r[3 * j + 1] = u01(r.v[1]);
-      s_r[3 * j + 2] = u01(r.v[2]);
-    }
-    __syncthreads();
-  }
-  {
-    float* X = pl.X + d.xo + (int64_t)p0 * D;
-    float* V = pl.V + d.xo + (int64_t)p0 * D;
-    const float* Pp = pl.P + d.xo + (int64_t)p0 * D;
-    const float* Gb = pl.gbest_pos + d.gpo;
-    const float* Tb = pl.tbest_pos + d.dpo;
-    const float* hy = pl.hyper + d.go * 6;
-    const int kk = k < d.T ? k : d.T;
-    const int nel = np * D;
-#pragma unroll 4
-    for (int e = t; e < nel; e += B) {
-      float x = X[e];
-      if (pending) {
-        const int j = e / D, dd = e - j * D, g = (p0 + j) / N;
-        const float* h = hy + g * 6;
-        const float w = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
-        const float hi = dd < W ? d.width : d.height;
-        const float vmax = h[5] * hi * 0.5f;
-        const float a1 = h[0] * s_r[3 * j], a2 = h[1] * s_r[3 * j + 1], a3 = h[2] * s_r[3 * j + 2];
-        float v = V[e];
-        v = w * v + a1 * (Pp[e] - x) + a2 * (Gb[g * D + dd] - x) + a3 * (Tb[dd] - x);
-        v = clampf(v, -vmax, vmax);
-        x = clampf(x + v, 0.f, hi);
-        X[e] = x;
-        V[e] = v;
-      }
-      if (FIT) s_buf[e] = x;
-    }
-  }
-  if (!FIT) return;
-  __syncthreads();
-
-  // ---- B. this thread's K segments of the point stream ---------------------
-  const int n_pts = np * S;               // stream points
-  const bool active = t * K < n_pts - 1;  // owns at least one slot
-  const int jf = (t * K) / S;             // first particle touched
-  const float4 ends = pl.ends[inst];
-  float px[K + 1], py[K + 1];
-#pragma unroll
-  for (int s = 0; s <= K; ++s) {
-    int q = t * K + s;
-    q = q < n_pts ? q : n_pts - 1;
-    const int j = q / S, idx = q - j * S;
-    float x, y;
-    if (idx == 0) {
-      x = ends.x;
-      y = ends.y;
-    } else if (idx == S - 1) {
-      x = ends.z;
-      y = ends.w;
-    } else {
-      x = s_buf[j * D + idx - 1];
-      y = s_buf[j * D + W + idx - 1];
-    }
-    px[s] = x;
-    py[s] = y;
-  }
-  float dx[K], ndy[K], nc[K];
-  uint32_t mk0 = 0, mk1 = 0, mk2 = 0;
-  float l0 = 0.f, l1 = 0.f, l2 = 0.f;
-#pragma unroll
-  for (int s = 0; s < K; ++s) {
-    const float ddx = px[s + 1] - px[s], ddy = py[s + 1] - py[s];
-    const int m = t * K + s;  // slot between points m and m+1
-    const int jm = m / S;
-    const bool seg = m < n_pts - 1 && m - jm * S != S - 1;
-    // A slot that is no path segment (a junction or past the stream's end)
-    // gets the zero line: every vertex side is +0 (coordinates are >= 0),
-    // so its side bits never differ and it never counts as a crossing.
-    dx[s] = seg ? ddx : 0.f;
-    ndy[s] = seg ? -ddy : 0.f;
-    nc[s] = seg ? fmaf(ddy, px[s], -(ddx * py[s])) : 0.f;
-    if (seg) {
-      const float len = sqrtf(ddx * ddx + ddy * ddy);
-      const uint32_t bit = 1u << (K - 1 - s);
-      const int pc = jm - jf;
-      if (pc == 0) {
-        mk0 |= bit;
-        l0 += len;
-      } else if (pc == 1) {
-        mk1 |= bit;
-        l1 += len;
-      } else {
-        mk2 |= bit;
-        l2 += len;
-      }
-    }
-  }
-  __syncthreads();  // positions consumed: s_buf now stages edges
-
-  // ---- C. crossings ----------------------------------------------------------
-  // Crossing words: bit K-1-s set when segment s properly crosses the edge
-  // (never for masked slots); counted as a total plus pieces 0 and 2 (piece
-  // 1 = the rest).
-  int ct = 0, c0 = 0, c2 = 0;
-  const bool three = __any(mk2 != 0u);  // wave-uniform: some lane has a third piece
+// Phase C of the fused iteration: crossings of this thread's K segments with
+// every obstacle edge of the instance, edges staged through LDS (s_buf, all
+// threads of the block take part in the staging and barriers).  Crossing
+// words: bit K-1-s set when segment s properly crosses the edge (never for
+// masked slots); counted as a total plus pieces 0 and 2 (piece 1 = the rest).
+template <int K, bool THREE>
+__device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, float* s_buf,
+                                          bool active, const float (&px)[K + 1],
+                                          const float (&py)[K + 1], const float (&dx)[K],
+                                          const float (&ndy)[K], const float (&nc)[K],
+                                          uint32_t mk0, uint32_t mk2, int& ct, int& c0, int& c2) {
   auto count = [&](uint32_t x) {
     ct += __popc(x);
     c0 += __popc(x & mk0);
-    if (three) c2 += __popc(x & mk2);
+    if (THREE) c2 += __popc(x & mk2);
   };
+  const int t = threadIdx.x, B = blockDim.x;
   // C1. axis-aligned rectangles.  Edge sides are exact sign tests of one
-  // coordinate difference; corner sides: (x0,y0) and (x1,y1) as two FMAs,
-  // (x1,y0) and (x0,y1) from (x0,y0) by one FMA each.
+  // coordinate difference; corner sides: (x0,y0) by two FMAs, each other
+  // corner from a neighbour by one FMA along the rectangle's side (three
+  // roundings on the far corner stay well inside the degenerate band).
   const float4* rr = pl.rects + d.ro;
   float4* s_rect = reinterpret_cast<float4*>(s_buf);
   const int rchunk = pl.buf_floats / 4;
@@ -573,16 +439,18 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     for (int q = t; q < nr; q += B) s_rect[q] = rr[r0 + q];
     __syncthreads();
     if (active) {
+      float4 bn = s_rect[0];
       for (int e = 0; e < nr; ++e) {
-        const float4 b = s_rect[e];  // x0, y0, x1, y1
+        const float4 b = bn;  // x0, y0, x1, y1
+        bn = s_rect[e + 1 < nr ? e + 1 : e];  // next rectangle's LDS read overlaps this one
         const float w = b.z - b.x, h = b.w - b.y;
         uint32_t w00 = 0, w10 = 0, w11 = 0, w01 = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
           const float o00 = fmaf(dx[s], b.y, fmaf(ndy[s], b.x, nc[s]));
-          const float o11 = fmaf(dx[s], b.w, fmaf(ndy[s], b.z, nc[s]));
           const float o10 = fmaf(ndy[s], w, o00);
           const float o01 = fmaf(dx[s], h, o00);
+          const float o11 = fmaf(dx[s], h, o10);
           w00 = __builtin_amdgcn_alignbit(w00, __float_as_uint(o00), 31);
           w10 = __builtin_amdgcn_alignbit(w10, __float_as_uint(o10), 31);
           w11 = __builtin_amdgcn_alignbit(w11, __float_as_uint(o11), 31);
@@ -644,6 +512,191 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Fused iteration over one block = ppb consecutive particles of an instance
+// (flat index g*N + n, possibly spanning groups).
+//
+//  A. previous iteration's update, elementwise and coalesced over the
+//     block's contiguous (particle, coordinate) range; new positions also
+//     go to LDS;
+//  B. the block's paths are laid end to end as a stream of points (start,
+//     W waypoints, target per particle); thread t takes the K segments
+//     starting at stream slot tK.  A slot joining one particle's target to
+//     the next one's start is not a path segment and is masked out; a
+//     thread's K segments belong to at most three particles ("pieces");
+//  C. crossings of the K segments with every obstacle edge (edges staged in
+//     LDS, reusing the position buffer): per edge, one packed side word of
+//     the edge's end vertex against the K segment lines and one of the K+1
+//     points against the edge line; crossing bits = both straddle;
+//  D. per-particle Q and L summed in thread order (deterministic), fitness
+//     and Pbest; improved particles' positions go to P.
+// ---------------------------------------------------------------------------
+template <int K, bool FIT>
+__device__ __forceinline__ void iteration(const Pools& pl, int flags) {
+  // dynamic LDS: positions / edge chunk | r1..r3 per particle | Pbest flags |
+  // per-thread piece counts and lengths
+  extern __shared__ __attribute__((aligned(16))) float s_dyn[];
+  float* s_buf = s_dyn;
+  float* s_c = s_buf + pl.buf_floats;  // per particle: a1, a2, a3, group
+  float* s_wv = s_c + 4 * pl.ppb_max;   // per group: w, V_limit / 2
+  int* s_imp = reinterpret_cast<int*>(s_wv + 2 * kMaxG);
+  int* s_q = s_imp + pl.ppb_max;
+  float* s_l = reinterpret_cast<float*>(s_q + 3 * blockDim.x);
+
+  const int2 bt = pl.blk_tiles[blockIdx.x];
+  const int inst = bt.x, p0 = bt.y;
+  const InstDesc& d = pl.desc[inst];
+  InstCtl* ctl = pl.ctl + inst;
+  if ((flags & STEP_FRAME) && ctl->done) return;
+  const int k = ctl->k, pending = ctl->pending;
+  const uint32_t ctr = ctl->ctr;
+  const int N = d.N, W = d.W, D = 2 * W, S = W + 2;
+  const int np = min(d.ppb, d.G * N - p0);  // particles in this block
+  const int t = threadIdx.x, B = blockDim.x;
+
+  // ---- A. update (coalesced) ----------------------------------------------
+  // Per particle one Philox call (r1..r3 scaled by the group's C1..C3) and
+  // its group; per group the inertia of Eq.(6) and V_limit / 2.  The element
+  // loop then walks (particle, coordinate) incrementally, without divisions.
+  if (pending) {
+    const int kk = k < d.T ? k : d.T;
+    const int g_lo = p0 / N, g_hi = (p0 + np - 1) / N;
+    for (int g = g_lo + t; g <= g_hi; g += B) {
+      const float* h = pl.hyper + (d.go + g) * 6;
+      s_wv[2 * (g - g_lo)] = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
+      s_wv[2 * (g - g_lo) + 1] = h[5] * 0.5f;
+    }
+    for (int j = t; j < np; j += B) {
+      const U4 r = philox((uint32_t)(p0 + j), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
+      const int g = (p0 + j) / N;
+      const float* h = pl.hyper + (d.go + g) * 6;
+      s_c[4 * j + 0] = h[0] * u01(r.v[0]);
+      s_c[4 * j + 1] = h[1] * u01(r.v[1]);
+      s_c[4 * j + 2] = h[2] * u01(r.v[2]);
+      s_c[4 * j + 3] = __int_as_float(g - g_lo);
+    }
+    __syncthreads();
+  }
+  {
+    float* X = pl.X + d.xo + (int64_t)p0 * D;
+    float* V = pl.V + d.xo + (int64_t)p0 * D;
+    const float* Pp = pl.P + d.xo + (int64_t)p0 * D;
+    const float* Gb = pl.gbest_pos + d.gpo + (p0 / N) * D;
+    const float* Tb = pl.tbest_pos + d.dpo;
+    const int nel = np * D;
+    const int qB = B / D, rB = B - qB * D;
+    int j = t / D, dd = t - j * D;  // particle and coordinate of element e
+#pragma unroll 4
+    for (int e = t; e < nel; e += B) {
+      float x = X[e];
+      if (pending) {
+        const float4 c = *reinterpret_cast<const float4*>(s_c + 4 * j);
+        const int gl = __float_as_int(c.w);
+        const float w = s_wv[2 * gl], vlh = s_wv[2 * gl + 1];
+        const float hi = dd < W ? d.width : d.height;
+        const float vmax = vlh * hi;
+        float v = V[e];
+        v = w * v + c.x * (Pp[e] - x) + c.y * (Gb[gl * D + dd] - x) + c.z * (Tb[dd] - x);
+        v = clampf(v, -vmax, vmax);
+        x = clampf(x + v, 0.f, hi);
+        X[e] = x;
+        V[e] = v;
+      }
+      if (FIT) s_buf[e] = x;
+      dd += rB;
+      j += qB;
+      if (dd >= D) {
+        dd -= D;
+        ++j;
+      }
+    }
+  }
+  if (!FIT) return;
+  __syncthreads();
+
+  // ---- B. this thread's K segments of the point stream ---------------------
+  const int n_pts = np * S;               // stream points
+  const bool active = t * K < n_pts - 1;  // owns at least one slot
+  const int jf = (t * K) / S;             // first particle touched
+  const int i0 = t * K - jf * S;          // stream slot tK = (particle jf, index i0)
+  const float4 ends = pl.ends[inst];
+  // point tK + s is (particle jf + u, index i0 + s - uS), u = number of
+  // particle boundaries passed (K <= 2S, so u <= 2)
+  auto locate = [&](int s, int& j, int& idx) {
+    const int a = i0 + s;
+    const int u = (a >= S) + (a >= 2 * S);
+    j = jf + u;
+    idx = a - u * S;
+  };
+  float px[K + 1], py[K + 1];
+#pragma unroll
+  for (int s = 0; s <= K; ++s) {
+    int j, idx;
+    if (t * K + s < n_pts) {
+      locate(s, j, idx);
+    } else {  // past the stream's end: repeat its last point
+      j = np - 1;
+      idx = S - 1;
+    }
+    float x, y;
+    if (idx == 0) {
+      x = ends.x;
+      y = ends.y;
+    } else if (idx == S - 1) {
+      x = ends.z;
+      y = ends.w;
+    } else {
+      x = s_buf[j * D + idx - 1];
+      y = s_buf[j * D + W + idx - 1];
+    }
+    px[s] = x;
+    py[s] = y;
+  }
+  float dx[K], ndy[K], nc[K];
+  uint32_t mk0 = 0, mk1 = 0, mk2 = 0;
+  float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const float ddx = px[s + 1] - px[s], ddy = py[s + 1] - py[s];
+    const int m = t * K + s;  // slot between points m and m+1
+    int jm, im;
+    locate(s, jm, im);
+    const bool seg = m < n_pts - 1 && im != S - 1;
+    // A slot that is no path segment (a junction or past the stream's end)
+    // gets the zero line: every vertex side is +0 (coordinates are >= 0),
+    // so its side bits never differ and it never counts as a crossing.
+    dx[s] = seg ? ddx : 0.f;
+    ndy[s] = seg ? -ddy : 0.f;
+    nc[s] = seg ? fmaf(ddy, px[s], -(ddx * py[s])) : 0.f;
+    if (seg) {
+      const float len = sqrtf(ddx * ddx + ddy * ddy);
+      const uint32_t bit = 1u << (K - 1 - s);
+      const int pc = jm - jf;
+      if (pc == 0) {
+        mk0 |= bit;
+        l0 += len;
+      } else if (pc == 1) {
+        mk1 |= bit;
+        l1 += len;
+      } else {
+        mk2 |= bit;
+        l2 += len;
+      }
+    }
+  }
+  __syncthreads();  // positions consumed: s_buf now stages edges
+
+  // ---- C. crossings ----------------------------------------------------------
+  // A thread's K slots reach a third particle only when K > W + 2 (block-
+  // uniform: a block belongs to one instance), so the third piece's count is
+  // compiled in only for such instances.
+  int ct = 0, c0 = 0, c2 = 0;
+  if (K > S)
+    crossings<K, true>(pl, d, s_buf, active, px, py, dx, ndy, nc, mk0, mk2, ct, c0, c2);
+  else
+    crossings<K, false>(pl, d, s_buf, active, px, py, dx, ndy, nc, mk0, mk2, ct, c0, c2);
   const int c1 = ct - c0 - c2;
 
   // ---- D. per-particle fitness and Pbest -------------------------------------
@@ -655,13 +708,15 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   s_l[3 * t + 2] = l2;
   __syncthreads();
   for (int j = t; j < np; j += B) {
-    const int t_lo = (j * S) / K, t_hi = (j * S + W) / K;  // threads holding its W+1 slots
-    int q = 0;
-    float L = 0.f;
-    for (int tt = t_lo; tt <= t_hi; ++tt) {
-      const int pc = j - (tt * K) / S;
-      q += s_q[3 * tt + pc];
-      L += s_l[3 * tt + pc];
+    // threads holding its W+1 slots: the first may hold it as its piece 1 or
+    // 2, every later one starts inside it (piece 0)
+    const int t_lo = (j * S) / K, t_hi = (j * S + W) / K;
+    const int pc_lo = j - (t_lo * K) / S;
+    int q = s_q[3 * t_lo + pc_lo];
+    float L = s_l[3 * t_lo + pc_lo];
+    for (int tt = t_lo + 1; tt <= t_hi; ++tt) {
+      q += s_q[3 * tt];
+      L += s_l[3 * tt];
     }
     const float qf = (float)q;
     float pw = 1.f;
@@ -687,7 +742,8 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     for (int s = 1; s <= K; ++s) {
       const int q = t * K + s;  // points owned by this thread
       if (q < n_pts) {
-        const int j = q / S, idx = q - j * S;
+        int j, idx;
+        locate(s, j, idx);
         if (idx >= 1 && idx <= W && s_imp[j]) {
           Pw[j * D + idx - 1] = px[s];
           Pw[j * D + W + idx - 1] = py[s];
@@ -718,7 +774,7 @@ void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev
 }
 
 size_t iter_lds_bytes(const Pools& pl, int threads) {
-  return 4 * ((size_t)pl.buf_floats + 4 * (size_t)pl.ppb_max + 6 * (size_t)threads);
+  return 4 * ((size_t)pl.buf_floats + 5 * (size_t)pl.ppb_max + 2 * kMaxG + 6 * (size_t)threads);
 }
 
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
