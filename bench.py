@@ -3,7 +3,7 @@
 A step is one planning frame of every instance of the batched workload:
 1024 independent dynamic instances of uneven size (8-32 waypoints, 4-100
 rectangles, 32-256 particles per group over 8 groups, maps 128-512 cells),
-each frame = device obstacle motion + Priori Initialization + up to 50 fused
+each frame (100 timed by default) = device obstacle motion + Priori Initialization + up to 50 fused
 iterations with Auto Truncation and online self-evolution, all in one
 captured HIP graph.  Inputs are resident in HBM before timing starts.
 
@@ -27,6 +27,31 @@ sys.path.insert(0, ROOT)
 METRIC = "plans/sec at oracle-matched cost; seg×edge tests/s vs FP32 VALU peak"
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published (packed FP32)
 F_TEST = 10.0          # algorithmic FLOP per segment x edge test
+COUNTERS = os.path.join(ROOT, "profiles", "iter_kernel_batch1024_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2308_10169_amd", "csrc", "kernels.hip")
+
+
+def counter_record(kernel, tune):
+    """HBM traffic and VALU instruction count per launch of the fused
+    iteration, from the committed rocprofv3 counter summary -- only while it
+    describes this kernel source and tile shape (else None)."""
+    import hashlib
+    try:
+        rec = {}
+        with open(COUNTERS) as f:
+            for line in f:
+                if ": " in line and not line.startswith(("#", "|", "`")):
+                    k, v = line.strip().split(": ", 1)
+                    rec[k] = v
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha or rec.get("kernel") != kernel or \
+            rec.get("tune") != f"{tune[0]},{tune[1]}":
+        return None
+    return dict(hbm_bytes=float(rec["hbm_bytes_per_launch"]),
+                valu_insts=float(rec["valu_insts_per_launch"]))
 
 
 def batch_workload(n_inst, seed_base=0):
@@ -78,12 +103,12 @@ def cpu_baseline(specs, sws, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--instances", type=int, default=1024)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="library default tile instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box here has a single MI355X; run with --gpus 1",
@@ -125,10 +150,18 @@ def main():
     print(f"# {plans} plans in {dt:.3f}s, mean iters {iters.mean():.1f}", file=sys.stderr, flush=True)
 
     achieved = F_TEST * tests_iter / (kern_ms * 1e-3)
+    kname = f"iter_kernel<{tune[0]}>" if tune else "iter_kernel"
+    rec = counter_record(kname, tune) if tune else None
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=achieved / PEAK_FP32, traffic=None,
-                kernel="step_kernel (fused iteration)", ms_per_launch=kern_ms,
-                tests_per_launch=tests_iter)
+                frac=achieved / PEAK_FP32, traffic=rec["hbm_bytes"] if rec else None,
+                kernel=f"{kname} (fused iteration, tile {tune})", ms_per_launch=kern_ms,
+                tests_per_launch=tests_iter, flop_per_test=F_TEST)
+    if rec:
+        # VALU issue: wave instructions x 64 lanes against the lane rate behind
+        # the FP32 peak (157.3 TFLOP/s / 2 FLOP per FMA lane)
+        lanes = rec["valu_insts"] * 64 / (kern_ms * 1e-3)
+        roof["valu_lane_ops_per_s"] = lanes
+        roof["valu_util"] = lanes / (PEAK_FP32 / 2)
 
     # paper-shaped single instance (366 map, 30 rectangles, 8 x 170, W = 20)
     spec2 = I.dynamic_map(0)

@@ -803,18 +803,29 @@ static sepso_status profile_batch(sepso_batch* b, int32_t n, float* avg_ms) {
   sepso_status s = usable(b);
   if (s != SEPSO_OK) return s;
   if (n < 1 || !avg_ms) return fail(SEPSO_E_ARG, "n >= 1 and avg_ms required");
-  HIPCHK(b, hipEventRecord(b->ev0, b->stream));
-  for (int k = 0; k < n; ++k)
-    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
-                b->stream);
-  HIPCHK(b, hipEventRecord(b->ev1, b->stream));
-  LAUNCHCHK(b, "step launch");
-  launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0, b->stream);
-  HIPCHK(b, hipEventSynchronize(b->ev1));
-  float ms = 0.f;
-  HIPCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
-  HIPCHK(b, hipStreamSynchronize(b->stream));
-  *avg_ms = ms / (float)n;
+  // events bracket each fused-iteration launch alone (not the reduce after it)
+  std::vector<hipEvent_t> ev(2 * (size_t)n, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t q = 0; q < ev.size() && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+  float total = 0.f;
+  if (e == hipSuccess) {
+    for (int k = 0; k < n; ++k)
+      launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
+                  b->stream, ev[2 * k], ev[2 * k + 1]);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+      total += ms;
+    }
+  }
+  for (hipEvent_t x : ev)
+    if (x) hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(b, e, "profile");
+  *avg_ms = total / (float)n;
   return SEPSO_OK;
 }
 

@@ -9,7 +9,10 @@ namespace sepso {
 void launch_geom(const Pools& pl, int n_inst, int move, hipStream_t s);
 void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev, hipStream_t s);
 bool step_supported(int K);
-void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s);
+// One iteration: the fused (or update-only) tile kernel, then the per-instance
+// reduce; events, when given, bracket the tile kernel alone.
+void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
+                 hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 void launch_evolve_init(const EvolveDev& ev, const Pools& pl, hipStream_t s);
 void launch_evolve_step(const EvolveDev& ev, const Pools& pl, int injected, hipStream_t s);
 

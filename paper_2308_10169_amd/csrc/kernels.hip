@@ -780,23 +780,27 @@ size_t iter_lds_bytes(const Pools& pl, int threads) {
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
 
 template <int K>
-static void launch_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s) {
+static void launch_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s,
+                     hipEvent_t before, hipEvent_t after) {
+  if (before) hipEventRecord(before, s);
   if (flags & STEP_FIT)
     hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads), s,
                        pl, flags);
   else
     hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads),
                        s, pl, flags);
+  if (after) hipEventRecord(after, s);
   hipLaunchKernelGGL(reduce_kernel, dim3(pl.n_inst), dim3(256), 0, s, pl, flags);
 }
 
-void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s) {
+void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
+                 hipEvent_t before, hipEvent_t after) {
   switch (K) {
-    case 4: launch_k<4>(pl, n_blocks, threads, flags, s); break;
-    case 8: launch_k<8>(pl, n_blocks, threads, flags, s); break;
-    case 12: launch_k<12>(pl, n_blocks, threads, flags, s); break;
-    case 16: launch_k<16>(pl, n_blocks, threads, flags, s); break;
-    case 24: launch_k<24>(pl, n_blocks, threads, flags, s); break;
+    case 4: launch_k<4>(pl, n_blocks, threads, flags, s, before, after); break;
+    case 8: launch_k<8>(pl, n_blocks, threads, flags, s, before, after); break;
+    case 12: launch_k<12>(pl, n_blocks, threads, flags, s, before, after); break;
+    case 16: launch_k<16>(pl, n_blocks, threads, flags, s, before, after); break;
+    case 24: launch_k<24>(pl, n_blocks, threads, flags, s, before, after); break;
     default: break;
   }
 }
