@@ -177,7 +177,7 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
       d.gpo = (int32_t)L.sumGD;
       d.dpo = (int32_t)L.sumD;
     }
-    L.sumPD += P * D;
+    L.sumPD += (P * D + 3) & ~int64_t(3);  // 16-byte aligned per instance (float4 walks)
     L.sumP += P;
     L.sumTilesMax += P;  // at most one tile per particle
     L.sumE += maps[i].n_polys ? maps[i].poly_ptr[maps[i].n_polys] : 0;
@@ -283,7 +283,7 @@ void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
   int buf = 8 * 256, ppb_max = 1;
   for (int i = 0; i < b->n; ++i) {
     InstDesc& d = b->desc[i];
-    d.ppb = std::max(1, (B * K) / (d.W + 2));
+    d.ppb = std::max(2, ((B * K) / (d.W + 2)) & ~1);  // even: every block starts 16-byte aligned
     d.n_blocks = (d.G * d.N + d.ppb - 1) / d.ppb;
     buf = std::max(buf, d.ppb * 2 * d.W);
     ppb_max = std::max(ppb_max, d.ppb);

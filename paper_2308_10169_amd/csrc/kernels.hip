@@ -46,7 +46,7 @@ __device__ void bounce(float* c, int n, int stride, float* vel, float hi) {
 
 __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
   const int inst = blockIdx.x;
-  const InstDesc& d = pl.desc[inst];
+  const InstDesc d = pl.desc[inst];  // by value: stores cannot make it reload
   const int t = threadIdx.x;
   float2* verts = pl.verts + d.eo;
   const int32_t* pp = pl.poly_ptr + d.plo;
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
 __global__ __launch_bounds__(256) void init_kernel(Pools pl, int frame_override, int use_prev) {
   const int2 bi = pl.blk_init[blockIdx.x];
   const int inst = bi.x;
-  const InstDesc& d = pl.desc[inst];
+  const InstDesc d = pl.desc[inst];  // by value: stores cannot make it reload
   InstCtl* ctl = pl.ctl + inst;
   const int W = d.W, D = 2 * W;
   const int64_t PD = (int64_t)d.G * d.N * D;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   __shared__ int s_rn[256];
   __shared__ int s_tg, s_stop, s_at, s_q;
   const int inst = blockIdx.x;
-  const InstDesc& d = pl.desc[inst];
+  const InstDesc d = pl.desc[inst];  // by value: stores cannot make it reload
   InstCtl* ctl = pl.ctl + inst;
   if ((flags & STEP_FRAME) && ctl->done) return;
   const int k = ctl->k, pending = ctl->pending;
@@ -421,6 +421,9 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
                                           const float (&ndy)[K], const float (&nc)[K],
                                           uint32_t mk0, uint32_t mk2, int& ct, int& c0, int& c2) {
   auto count = [&](uint32_t x) {
+    // x is pinned to a register so the piece masks apply to it (one AND each)
+    // instead of being folded back into the crossing expression
+    asm("" : "+v"(x));
     ct += __popc(x);
     c0 += __popc(x & mk0);
     if (THREE) c2 += __popc(x & mk2);
@@ -547,7 +550,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
 
   const int2 bt = pl.blk_tiles[blockIdx.x];
   const int inst = bt.x, p0 = bt.y;
-  const InstDesc& d = pl.desc[inst];
+  const InstDesc d = pl.desc[inst];  // by value: stores cannot make it reload
   InstCtl* ctl = pl.ctl + inst;
   if ((flags & STEP_FRAME) && ctl->done) return;
   const int k = ctl->k, pending = ctl->pending;
@@ -586,30 +589,116 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     const float* Gb = pl.gbest_pos + d.gpo + (p0 / N) * D;
     const float* Tb = pl.tbest_pos + d.dpo;
     const int nel = np * D;
-    const int qB = B / D, rB = B - qB * D;
-    int j = t / D, dd = t - j * D;  // particle and coordinate of element e
-#pragma unroll 4
-    for (int e = t; e < nel; e += B) {
-      float x = X[e];
-      if (pending) {
-        const float4 c = *reinterpret_cast<const float4*>(s_c + 4 * j);
-        const int gl = __float_as_int(c.w);
-        const float w = s_wv[2 * gl], vlh = s_wv[2 * gl + 1];
-        const float hi = dd < W ? d.width : d.height;
-        const float vmax = vlh * hi;
-        float v = V[e];
-        v = w * v + c.x * (Pp[e] - x) + c.y * (Gb[gl * D + dd] - x) + c.z * (Tb[dd] - x);
-        v = clampf(v, -vmax, vmax);
-        x = clampf(x + v, 0.f, hi);
-        X[e] = x;
-        V[e] = v;
+    // The block's range starts 16-byte aligned (even particles per block, pools
+    // padded per instance), so the walk goes by float4 groups of elements;
+    // only an instance's last group can be partial.  Chunks of CH groups per
+    // thread: every load of a chunk is issued before its first store (the
+    // stores could alias later loads for the compiler).
+    const int ng = (nel + 3) >> 2;
+    const int qB = (4 * B) / D, rB = 4 * B - qB * D;
+    int j = (4 * t) / D, dd = 4 * t - j * D;  // particle and coordinate of group's first element
+    float4* X4 = reinterpret_cast<float4*>(X);
+    float4* V4 = reinterpret_cast<float4*>(V);
+    const float4* P4 = reinterpret_cast<const float4*>(Pp);
+    float4* B4 = reinterpret_cast<float4*>(s_buf);
+    constexpr int CH = 4;
+    for (int g0 = t; g0 < ng; g0 += CH * B) {
+      float4 xa[CH], va[CH], pa[CH];
+      float ga[CH][4], ta[CH][4];
+      int ja[CH], da[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int gi = g0 + c * B, e = 4 * gi;
+        ja[c] = j;
+        da[c] = dd;
+        if (gi < ng) {
+          if (e + 4 <= nel) {
+            xa[c] = X4[gi];
+            if (pending) {
+              va[c] = V4[gi];
+              pa[c] = P4[gi];
+            }
+          } else {
+            float* xs = &xa[c].x;
+            float* vs = &va[c].x;
+            float* ps = &pa[c].x;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const bool ok = e + i < nel;
+              xs[i] = ok ? X[e + i] : 0.f;
+              vs[i] = ok && pending ? V[e + i] : 0.f;
+              ps[i] = ok && pending ? Pp[e + i] : 0.f;
+            }
+          }
+          if (pending) {
+            int jj = j, di = dd;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const bool ok = e + i < nel;
+              const int gl = ok ? __float_as_int(s_c[4 * jj + 3]) : 0;
+              ga[c][i] = ok ? Gb[gl * D + di] : 0.f;
+              ta[c][i] = ok ? Tb[di] : 0.f;
+              if (++di == D) {
+                di = 0;
+                ++jj;
+              }
+            }
+          }
+        }
+        dd += rB;
+        j += qB;
+        while (dd >= D) {
+          dd -= D;
+          ++j;
+        }
       }
-      if (FIT) s_buf[e] = x;
-      dd += rB;
-      j += qB;
-      if (dd >= D) {
-        dd -= D;
-        ++j;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int gi = g0 + c * B, e = 4 * gi;
+        if (gi < ng) {
+          float* xs = &xa[c].x;
+          if (pending) {
+            float* vs = &va[c].x;
+            const float* ps = &pa[c].x;
+            int jj = ja[c], di = da[c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (e + i < nel) {
+                const float4 cf = *reinterpret_cast<const float4*>(s_c + 4 * jj);
+                const int gl = __float_as_int(cf.w);
+                const float w = s_wv[2 * gl], vlh = s_wv[2 * gl + 1];
+                const float hi = di < W ? d.width : d.height;
+                const float vmax = vlh * hi;
+                const float x = xs[i];
+                float v = w * vs[i] + cf.x * (ps[i] - x) + cf.y * (ga[c][i] - x) + cf.z * (ta[c][i] - x);
+                v = clampf(v, -vmax, vmax);
+                vs[i] = v;
+                xs[i] = clampf(x + v, 0.f, hi);
+              }
+              if (++di == D) {
+                di = 0;
+                ++jj;
+              }
+            }
+          }
+          if (e + 4 <= nel) {
+            if (pending) {
+              X4[gi] = xa[c];
+              V4[gi] = va[c];
+            }
+            if (FIT) B4[gi] = xa[c];
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (e + i < nel) {
+                if (pending) {
+                  X[e + i] = xs[i];
+                  V[e + i] = (&va[c].x)[i];
+                }
+                if (FIT) s_buf[e + i] = xs[i];
+              }
+          }
+        }
       }
     }
   }
@@ -736,18 +825,36 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     s_imp[j] = imp;
   }
   __syncthreads();
-  if (active) {
-    float* Pw = pl.P + d.xo + (int64_t)p0 * D;
-#pragma unroll
-    for (int s = 1; s <= K; ++s) {
-      const int q = t * K + s;  // points owned by this thread
-      if (q < n_pts) {
-        int j, idx;
-        locate(s, j, idx);
-        if (idx >= 1 && idx <= W && s_imp[j]) {
-          Pw[j * D + idx - 1] = px[s];
-          Pw[j * D + W + idx - 1] = py[s];
+  // Improved particles' rows go to P: the same float4 walk as phase A (each
+  // thread rereads the groups it wrote, from L2).
+  {
+    const float4* X4 = reinterpret_cast<const float4*>(pl.X + d.xo + (int64_t)p0 * D);
+    float4* P4 = reinterpret_cast<float4*>(pl.P + d.xo + (int64_t)p0 * D);
+    const float* Xs = pl.X + d.xo + (int64_t)p0 * D;
+    float* Ps = pl.P + d.xo + (int64_t)p0 * D;
+    const int nel = np * D, ng = (nel + 3) >> 2;
+    const int qB = (4 * B) / D, rB = 4 * B - qB * D;
+    int j = (4 * t) / D, dd = 4 * t - j * D;
+    for (int gi = t; gi < ng; gi += B) {
+      const int e = 4 * gi;
+      const int jl = j + (dd + 3) / D;  // particle of the group's last element
+      if (e + 4 <= nel && s_imp[j] && s_imp[jl]) {
+        P4[gi] = X4[gi];
+      } else if (s_imp[j] || (jl < np && s_imp[jl])) {
+        int jj = j, di = dd;
+        for (int i = 0; i < 4; ++i) {
+          if (e + i < nel && s_imp[jj]) Ps[e + i] = Xs[e + i];
+          if (++di == D) {
+            di = 0;
+            ++jj;
+          }
         }
+      }
+      dd += rB;
+      j += qB;
+      while (dd >= D) {
+        dd -= D;
+        ++j;
       }
     }
   }
