@@ -302,8 +302,6 @@ __device__ void hsef_step(const Pools& pl, const InstDesc& d, InstCtl* ctl, cons
 __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   __shared__ float s_gf[kMaxG];
   __shared__ int s_gn[kMaxG];
-  __shared__ float s_rf[256];
-  __shared__ int s_rn[256];
   __shared__ int s_tg, s_stop, s_at, s_q;
   const int inst = blockIdx.x;
   const InstDesc d = pl.desc[inst];  // by value: stores cannot make it reload
@@ -320,36 +318,38 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
     }
     return;
   }
+  // one wave per group (waves take groups in turn): lanes scan the group's
+  // Pbest fitness, a shuffle argmin (lowest index on ties) picks Gbest
   const float* Pf = pl.Pf + d.po;
-  for (int g = 0; g < G; ++g) {
+  const int lane = t & 63, wave = t >> 6, n_waves = blockDim.x >> 6;
+  for (int g = wave; g < G; g += n_waves) {
     float bf = INFINITY;
     int bn = 0x7fffffff;
-    for (int n = t; n < N; n += blockDim.x) {
+    for (int n = lane; n < N; n += 64) {
       const float f = Pf[g * N + n];
       if (better(f, n, bf, bn)) {
         bf = f;
         bn = n;
       }
     }
-    s_rf[t] = bf;
-    s_rn[t] = bn;
-    __syncthreads();
-    for (int m = blockDim.x / 2; m > 0; m >>= 1) {
-      if (t < m && better(s_rf[t + m], s_rn[t + m], s_rf[t], s_rn[t])) {
-        s_rf[t] = s_rf[t + m];
-        s_rn[t] = s_rn[t + m];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+      const float of = __shfl_xor(bf, m);
+      const int on = __shfl_xor(bn, m);
+      if (better(of, on, bf, bn)) {
+        bf = of;
+        bn = on;
       }
-      __syncthreads();
     }
-    if (t == 0) {
-      const int n = s_rn[0] < N ? s_rn[0] : 0;
+    if (lane == 0) {
+      const int n = bn < N ? bn : 0;
       s_gn[g] = n;
-      s_gf[g] = s_rf[0];
+      s_gf[g] = bf;
       pl.gbest_n[d.go + g] = n;
-      pl.gbest_f[d.go + g] = s_rf[0];
+      pl.gbest_f[d.go + g] = bf;
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (t == 0) {
     int tg = 0;
     for (int g = 1; g < G; ++g)
