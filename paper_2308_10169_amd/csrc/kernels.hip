@@ -429,6 +429,26 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
     if (THREE) c2 += __popc(x & mk2);
   };
   const int t = threadIdx.x, B = blockDim.x;
+  // Bounding box of the wave's points (wave-uniform).  A segment lies in the
+  // box of its end points, so a rectangle that is outside the box (touching
+  // allowed) cannot be properly crossed by any of the wave's segments: its
+  // sign tests could only mark points exactly on its lines, a degenerate
+  // contact, and the whole rectangle is skipped.
+  float bx0 = px[0], bx1 = px[0], by0 = py[0], by1 = py[0];
+#pragma unroll
+  for (int s = 1; s <= K; ++s) {
+    bx0 = fminf(bx0, px[s]);
+    bx1 = fmaxf(bx1, px[s]);
+    by0 = fminf(by0, py[s]);
+    by1 = fmaxf(by1, py[s]);
+  }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    bx0 = fminf(bx0, __shfl_xor(bx0, m));
+    bx1 = fmaxf(bx1, __shfl_xor(bx1, m));
+    by0 = fminf(by0, __shfl_xor(by0, m));
+    by1 = fmaxf(by1, __shfl_xor(by1, m));
+  }
   // C1. axis-aligned rectangles.  Edge sides are exact sign tests of one
   // coordinate difference; corner sides: (x0,y0) by two FMAs, each other
   // corner from a neighbour by one FMA along the rectangle's side (three
@@ -446,6 +466,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       for (int e = 0; e < nr; ++e) {
         const float4 b = bn;  // x0, y0, x1, y1
         bn = s_rect[e + 1 < nr ? e + 1 : e];  // next rectangle's LDS read overlaps this one
+        if (b.z <= bx0 || b.x >= bx1 || b.w <= by0 || b.y >= by1) continue;
         const float w = b.z - b.x, h = b.w - b.y;
         uint32_t w00 = 0, w10 = 0, w11 = 0, w01 = 0;
 #pragma unroll
