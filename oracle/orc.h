@@ -25,7 +25,7 @@ extern "C" {
 enum { ORC_TAG_UPDATE = 0, ORC_TAG_INIT_X = 1, ORC_TAG_INIT_V = 2, ORC_TAG_PI = 3,
        ORC_TAG_HSEF = 4, ORC_TAG_LEARNED = 5, ORC_TAG_EVOLVE = 6, ORC_TAG_EVOLVE_X = 7,
        ORC_TAG_EVOLVE_V = 8, ORC_TAG_BF_UPDATE = 9, ORC_TAG_BF_INIT_X = 10,
-       ORC_TAG_BF_INIT_V = 11 };
+       ORC_TAG_BF_INIT_V = 11, ORC_TAG_UPDATE_DIM = 12 };
 
 /* Philox4x32 with 10 rounds, written from Salmon et al. (SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -76,6 +76,8 @@ typedef struct orc_swarm {
   double tbest_f;
   int32_t k;               /* iteration index within the current plan */
   uint32_t ctr;            /* global iteration counter (random stream position) */
+  int32_t rand_per_dim;    /* 0: one (r1, r2, r3) per particle; 1: one per coordinate,
+                              counter (particle*2W + coordinate, ctr, instance, UPDATE_DIM) */
 } orc_swarm;
 
 void orc_eval(orc_swarm* s, const orc_map* m);        /* f, L, Q of X */

@@ -210,6 +210,8 @@ void orc_update(orc_swarm* s) {
       double* v = s->V + (size_t)i * D;
       const double* p = s->P + (size_t)i * D;
       for (int32_t d = 0; d < D; ++d) {
+        if (s->rand_per_dim)  // variant: independent factors per coordinate
+          draw4(s->seed, (uint32_t)(i * D + d), s->ctr, s->instance, ORC_TAG_UPDATE_DIM, r);
         const double hi = map_hi(s, d);
         const double vmax = vl * hi / 2.0;
         double vn = w * v[d] + C1 * r[0] * (p[d] - x[d]) + C2 * r[1] * (Gb[d] - x[d]) +

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 SOURCES = ["orc_core.cpp", "orc_frame.cpp", "orc_mlp.cpp", "orc_evolve.cpp", "orc_bf.cpp"]
 
 (TAG_UPDATE, TAG_INIT_X, TAG_INIT_V, TAG_PI, TAG_HSEF, TAG_LEARNED, TAG_EVOLVE, TAG_EVOLVE_X,
- TAG_EVOLVE_V, TAG_BF_UPDATE, TAG_BF_INIT_X, TAG_BF_INIT_V) = range(12)
+ TAG_EVOLVE_V, TAG_BF_UPDATE, TAG_BF_INIT_X, TAG_BF_INIT_V, TAG_UPDATE_DIM) = range(13)
 BF_SPHERE, BF_ROSENBROCK, BF_RASTRIGIN, BF_GRIEWANK = 1, 2, 3, 4
 
 
@@ -51,7 +51,8 @@ class OrcSwarm(C.Structure):
                 ("instance", C.c_uint32), ("X", dp), ("V", dp), ("P", dp), ("f", dp),
                 ("L", dp), ("Q", ip), ("Pf", dp), ("PL", dp), ("PQ", ip), ("gbest_n", ip),
                 ("gbest_f", dp), ("tbest_g", C.c_int32), ("tbest_n", C.c_int32),
-                ("tbest_f", C.c_double), ("k", C.c_int32), ("ctr", C.c_uint32)]
+                ("tbest_f", C.c_double), ("k", C.c_int32), ("ctr", C.c_uint32),
+                ("rand_per_dim", C.c_int32)]
 
 
 class OrcHsef(C.Structure):
@@ -216,7 +217,8 @@ class Swarm:
                           float(sw.alpha), int(sw.beta), int(sw.seed), int(sw.instance),
                           _p(self.X), _p(self.V), _p(self.P), _p(self.f), _p(self.L),
                           _p(self.Q, ip), _p(self.Pf), _p(self.PL), _p(self.PQ, ip),
-                          _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0, float("inf"), 0, 0)
+                          _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0, float("inf"), 0, 0,
+                          int(getattr(sw, "rand_per_dim", 0)))
         # online self-evolution state
         self.outer_hyper = np.ascontiguousarray(sw.hsef_hyper, dtype=np.float64).reshape(G, 6)
         self.ov, self.op, self.opf = z(G, 3), z(G, 3), np.full(G, np.inf)

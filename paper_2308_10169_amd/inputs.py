@@ -111,6 +111,7 @@ class SwarmSpec:
     at_delta: float = 1e-3
     hsef_every: int = 0
     hsef_hyper: np.ndarray | None = None
+    rand_per_dim: int = 0     # variant: one (r1, r2, r3) per coordinate instead of per particle
 
     def __post_init__(self):
         self.hyper = f32(self.hyper).reshape(self.groups, 6)

@@ -107,6 +107,35 @@ def test_random_factor_is_per_particle(orc):
             assert np.allclose(r[g, n], orc.u01(w[0]), rtol=1e-12)
 
 
+def test_random_factor_per_coordinate_variant(orc):
+    # Variant of R2: one (r1, r2, r3) per coordinate, counter (particle*2W +
+    # coordinate, iteration, instance, tag 12); only C1, w = 0 so X moves by
+    # r1 (P - X) coordinate by coordinate.
+    import dataclasses
+    h = np.tile([1.0, 0, 0, 0.0, 0.0, 10.0], (2, 1))
+    sw = dataclasses.replace(I.SwarmSpec(2, 8, 4, 5, h, alpha=1e3, beta=1, seed=99),
+                             rand_per_dim=1)
+    s = orc.Swarm(sw, 100.0, 100.0)
+    s.init(0)
+    rng = np.random.default_rng(2)
+    s.X[:] = I.snap(rng.uniform(10, 90, s.X.shape))
+    s.P[:] = I.snap(rng.uniform(10, 90, s.P.shape))
+    s.V[:] = 0.0
+    s.set_scalars(k=1, ctr=41)
+    X0 = s.X.copy()
+    s.update()
+    r = (s.X - X0) / (s.P - X0)
+    D = 8
+    for g in range(2):
+        for n in range(8):
+            i = g * 8 + n
+            for d in range(D):
+                w = orc.philox([i * D + d, 41, 0, 12], [99, 0])
+                assert np.isclose(r[g, n, d], orc.u01(w[0]), rtol=1e-12)
+            assert len(set(np.round(r[g, n], 12))) == D  # independent per coordinate
+    assert np.all((r >= 0) & (r < 1)) and abs(r.mean() - 0.5) < 0.15
+
+
 def test_attractors_select_group_and_total_best(orc):
     # Only C2 (group best) or only C3 (total best), r-factor known: the target
     # of each particle must be its own group's best / the total best Pbest.
