@@ -82,6 +82,10 @@ typedef struct sepso_swarm {
   const float* hsef_hyper;              /* G x 6 hyper of the outer swarm (NULL = Table hyper8 rows) */
   uint64_t seed;                        /* Philox4x32-10 key */
   uint32_t instance;                    /* Philox counter word 2 */
+  int32_t rand_per_dim;                 /* 0: one (r1, r2, r3) per particle and iteration (the
+                                           paper's R of shape (4, G, N)); 1: variant with one
+                                           per coordinate, counter (particle*2W + coordinate,
+                                           iteration, instance, 12) */
 } sepso_swarm;
 
 typedef struct sepso_frame_result {

@@ -88,6 +88,8 @@ sepso_status check_swarm(const sepso_swarm* s, int idx) {
     return fail(SEPSO_E_ARG, "swarm[%d]: at_window in [1,%d]", idx, kHist - 1);
   if (!finite(s->at_delta)) return fail(SEPSO_E_ARG, "swarm[%d]: at_delta", idx);
   if (s->hsef_every < 0) return fail(SEPSO_E_ARG, "swarm[%d]: hsef_every >= 0", idx);
+  if (s->rand_per_dim != 0 && s->rand_per_dim != 1)
+    return fail(SEPSO_E_ARG, "swarm[%d]: rand_per_dim is 0 or 1", idx);
   return SEPSO_OK;
 }
 
@@ -168,6 +170,7 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
       d.seed_lo = (uint32_t)(sw[i].seed & 0xffffffffu);
       d.seed_hi = (uint32_t)(sw[i].seed >> 32);
       d.instance = sw[i].instance;
+      d.rand_per_dim = sw[i].rand_per_dim;
       d.xo = L.sumPD;
       d.po = L.sumP;
       d.eo = (int32_t)L.sumE;
@@ -240,7 +243,7 @@ bool tune_ok(int K, int B, int w_min) {
   // dynamic LDS of the fused iteration stays within 64 KiB: positions
   // (< 2BK floats), 5 words per particle, the group table, 6 words per thread
   const size_t ppb = (size_t)(B * K) / (w_min + 2);
-  const size_t words = std::max<size_t>(2048, 2 * (size_t)B * K) + 5 * ppb + 2 * kMaxG + 6 * (size_t)B;
+  const size_t words = std::max<size_t>(2048, 2 * (size_t)B * K) + 5 * ppb + 5 * kMaxG + 6 * (size_t)B;
   return 4 * words <= 65536;
 }
 

@@ -23,7 +23,7 @@ constexpr int kLinOut = kLinGroups * 2 * kLinW; // 320
 
 // Philox counter tags: which random stream a draw belongs to.
 enum Tag : uint32_t { TAG_UPDATE = 0, TAG_INIT_X = 1, TAG_INIT_V = 2, TAG_PI = 3, TAG_HSEF = 4,
-                      TAG_EVOLVE = 6, TAG_EVOLVE_X = 7, TAG_EVOLVE_V = 8 };
+                      TAG_EVOLVE = 6, TAG_EVOLVE_X = 7, TAG_EVOLVE_V = 8, TAG_UPDATE_DIM = 12 };
 
 // Edge flags.
 enum : int32_t { EDGE_FIRST = 1, EDGE_LAST = 2 };
@@ -56,6 +56,7 @@ struct InstDesc {
   int32_t at_mode, at_window; float at_delta;
   int32_t hsef_every, T_outer;
   uint32_t seed_lo, seed_hi, instance;
+  int32_t rand_per_dim;  // one (r1, r2, r3) per coordinate instead of per particle
   int64_t xo;            // X, V, P pools: G*N*2W floats
   int64_t po;            // per-particle pools: G*N
   int32_t eo;            // vertices (n_edges float2)

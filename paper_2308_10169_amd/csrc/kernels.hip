@@ -564,8 +564,8 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   extern __shared__ __attribute__((aligned(16))) float s_dyn[];
   float* s_buf = s_dyn;
   float* s_c = s_buf + pl.buf_floats;  // per particle: a1, a2, a3, group
-  float* s_wv = s_c + 4 * pl.ppb_max;   // per group: w, V_limit / 2
-  int* s_imp = reinterpret_cast<int*>(s_wv + 2 * kMaxG);
+  float* s_wv = s_c + 4 * pl.ppb_max;   // per group: w, V_limit / 2, C1, C2, C3
+  int* s_imp = reinterpret_cast<int*>(s_wv + 5 * kMaxG);
   int* s_q = s_imp + pl.ppb_max;
   float* s_l = reinterpret_cast<float*>(s_q + 3 * blockDim.x);
 
@@ -589,8 +589,12 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     const int g_lo = p0 / N, g_hi = (p0 + np - 1) / N;
     for (int g = g_lo + t; g <= g_hi; g += B) {
       const float* h = pl.hyper + (d.go + g) * 6;
-      s_wv[2 * (g - g_lo)] = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
-      s_wv[2 * (g - g_lo) + 1] = h[5] * 0.5f;
+      float* q = s_wv + 5 * (g - g_lo);
+      q[0] = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
+      q[1] = h[5] * 0.5f;
+      q[2] = h[0];
+      q[3] = h[1];
+      q[4] = h[2];
     }
     for (int j = t; j < np; j += B) {
       const U4 r = philox((uint32_t)(p0 + j), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
@@ -687,11 +691,20 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
               if (e + i < nel) {
                 const float4 cf = *reinterpret_cast<const float4*>(s_c + 4 * jj);
                 const int gl = __float_as_int(cf.w);
-                const float w = s_wv[2 * gl], vlh = s_wv[2 * gl + 1];
+                const float* q = s_wv + 5 * gl;
+                const float w = q[0], vlh = q[1];
+                float a1 = cf.x, a2 = cf.y, a3 = cf.z;
+                if (d.rand_per_dim) {  // variant: factors per coordinate
+                  const U4 r = philox((uint32_t)((p0 + jj) * D + di), ctr, d.instance,
+                                      TAG_UPDATE_DIM, d.seed_lo, d.seed_hi);
+                  a1 = q[2] * u01(r.v[0]);
+                  a2 = q[3] * u01(r.v[1]);
+                  a3 = q[4] * u01(r.v[2]);
+                }
                 const float hi = di < W ? d.width : d.height;
                 const float vmax = vlh * hi;
                 const float x = xs[i];
-                float v = w * vs[i] + cf.x * (ps[i] - x) + cf.y * (ga[c][i] - x) + cf.z * (ta[c][i] - x);
+                float v = w * vs[i] + a1 * (ps[i] - x) + a2 * (ga[c][i] - x) + a3 * (ta[c][i] - x);
                 v = clampf(v, -vmax, vmax);
                 vs[i] = v;
                 xs[i] = clampf(x + v, 0.f, hi);
@@ -902,7 +915,7 @@ void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev
 }
 
 size_t iter_lds_bytes(const Pools& pl, int threads) {
-  return 4 * ((size_t)pl.buf_floats + 5 * (size_t)pl.ppb_max + 2 * kMaxG + 6 * (size_t)threads);
+  return 4 * ((size_t)pl.buf_floats + 5 * (size_t)pl.ppb_max + 5 * kMaxG + 6 * (size_t)threads);
 }
 
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }

@@ -42,7 +42,7 @@ class CSwarm(C.Structure):
                 ("beta", C.c_int32), ("use_pi", C.c_int32), ("pi_gamma", C.c_float),
                 ("pi_radius", C.c_float), ("at_mode", C.c_int32), ("at_window", C.c_int32),
                 ("at_delta", C.c_float), ("hsef_every", C.c_int32), ("hsef_hyper", fp),
-                ("seed", C.c_uint64), ("instance", C.c_uint32)]
+                ("seed", C.c_uint64), ("instance", C.c_uint32), ("rand_per_dim", C.c_int32)]
 
 
 class CFrameResult(C.Structure):
@@ -199,7 +199,8 @@ class _SwarmArgs:
                         self.hyper.ctypes.data_as(fp), float(sw.alpha), int(sw.beta),
                         int(sw.use_pi), float(sw.pi_gamma), float(sw.pi_radius), int(sw.at_mode),
                         int(sw.at_window), float(sw.at_delta), int(sw.hsef_every),
-                        self.hsef.ctypes.data_as(fp), int(sw.seed), int(sw.instance))
+                        self.hsef.ctypes.data_as(fp), int(sw.seed), int(sw.instance),
+                        int(getattr(sw, "rand_per_dim", 0)))
 
 
 def _result(r):

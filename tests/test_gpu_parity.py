@@ -59,6 +59,25 @@ def test_static_plan_every_step(sp, variant):
     assert stats["paths"] == 3 * 50 * 128
 
 
+@pytest.mark.parametrize("variant", ["hyper8", "dyn"])
+def test_per_coordinate_factors_every_step(sp, variant):
+    # Variant of the update with one (r1, r2, r3) per coordinate: every step
+    # of the HIP path against the oracle's (static plan and a dynamic shape
+    # with a ragged W = 13 stream).
+    import dataclasses
+    stats = {}
+    if variant == "hyper8":
+        spec = I.static_map(5)
+        sw = dataclasses.replace(I.static_swarm(seed=5, variant="hyper8"), rand_per_dim=1)
+        _run_injected(sp, spec, sw, 30, stats)
+    else:
+        spec = I.dynamic_map(6, S=200.0, n_static=6, n_moving=6, side=(8.0, 30.0))
+        sw = dataclasses.replace(I.dynamic_swarm(spec.scale, seed=4, groups=3, particles=37,
+                                                 waypoints=13), rand_per_dim=1)
+        _run_injected(sp, spec, sw, 12, stats)
+    print("parity stats", stats)
+
+
 def test_dynamic_shape_steps(sp):
     # Paper-shaped instance: 366 map, 30 rectangles, 8 x 170 particles, W = 20.
     spec = I.dynamic_map(0)
