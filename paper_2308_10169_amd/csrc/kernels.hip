@@ -495,8 +495,12 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       }
     }
   }
-  // C2. other polygons, edge by edge.
+  // C2. other polygons, edge by edge.  An edge outside the wave's box is
+  // skipped like a rectangle (a proper crossing lies strictly inside both the
+  // segment and the edge); the vertex words are then recomputed for the next
+  // edge instead of carried over.
   uint32_t w0 = 0, wp = 0;
+  bool have_w0 = false, have_wp = false;
   const EdgeRec* er = pl.edges + d.geo;
   EdgeRec* s_edge = reinterpret_cast<EdgeRec*>(s_buf);
   const int chunk = pl.buf_floats / 8;  // edge records per LDS pass
@@ -514,12 +518,24 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
         const EdgeRec r = s_edge[e];
         const int fl = __builtin_amdgcn_readfirstlane(r.flags);
         if (fl & EDGE_FIRST) {
-          w0 = pack_seg_sides<K>(r.ax, r.ay, dx, ndy, nc);
-          wp = w0;
+          have_w0 = false;
+          have_wp = false;
+        }
+        if (fmaxf(r.ax, r.bx) <= bx0 || fminf(r.ax, r.bx) >= bx1 || fmaxf(r.ay, r.by) <= by0 ||
+            fminf(r.ay, r.by) >= by1) {
+          have_wp = false;
+          continue;
+        }
+        if (!have_wp) {
+          wp = pack_seg_sides<K>(r.ax, r.ay, dx, ndy, nc);
+          if (fl & EDGE_FIRST) {
+            w0 = wp;
+            have_w0 = true;
+          }
         }
         uint32_t wn;
-        if (fl & EDGE_LAST)
-          wn = w0;
+        if ((fl & EDGE_LAST) && have_w0)
+          wn = w0;  // the closing edge ends at the first vertex
         else
           wn = pack_seg_sides<K>(r.bx, r.by, dx, ndy, nc);
         // side bits of the K+1 points against the edge's line: bit K-s
@@ -533,6 +549,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
         // the edge straddles segment s's line iff its two vertices differ.
         count((wp ^ wn) & (ew ^ (ew >> 1)));
         wp = wn;
+        have_wp = true;
       }
     }
   }

@@ -159,6 +159,32 @@ def random_quads(rng, width, height, n, ax_lo, ax_hi):
     return np.array(out, dtype=np.float64).reshape(n, 4, 2)
 
 
+def random_stars(rng, width, height, n, r_lo, r_hi, spikes=(5, 8)):
+    """n non-convex star polygons: 2m vertices alternating between an outer
+    radius ~ U[r_lo, r_hi] and 0.4 of it, jittered angles, centred inside the
+    map (simple polygons, counter-clockwise)."""
+    out = []
+    for _ in range(n):
+        m = int(rng.integers(spikes[0], spikes[1] + 1))
+        ro = rng.uniform(r_lo, r_hi)
+        cx, cy = rng.uniform(ro, width - ro), rng.uniform(ro, height - ro)
+        th = (np.arange(2 * m) + rng.uniform(-0.2, 0.2, 2 * m)) * (math.pi / m)
+        rad = np.where(np.arange(2 * m) % 2 == 0, ro, 0.4 * ro)
+        q = np.stack([cx + rad * np.cos(th), cy + rad * np.sin(th)], axis=1)
+        out.append(np.clip(snap(q), 0.0, [width, height]))
+    return out
+
+
+def nonconvex_map(seed, S=200.0, n_rects=6, n_stars=6):
+    """Mixed obstacle set: rectangles and non-convex stars (a variant the
+    polygon representation allows), start and target in opposite corners."""
+    rng = np.random.default_rng(seed)
+    s, t = snap([0.04 * S, 0.06 * S]), snap([0.96 * S, 0.94 * S])
+    rects = random_rects(rng, S, S, n_rects, 0.04 * S, 0.15 * S, avoid=(s, t))
+    stars = random_stars(rng, S, S, n_stars, 0.05 * S, 0.12 * S)
+    return make_map(S, S, list(rects) + stars, s, t)
+
+
 def make_map(width, height, polys, start, target, poly_vel=None, endpoint_vel=None):
     polys = [np.asarray(p, dtype=np.float64) for p in polys]
     ptr = np.zeros(len(polys) + 1, dtype=np.int32)

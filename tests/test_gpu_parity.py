@@ -78,6 +78,18 @@ def test_per_coordinate_factors_every_step(sp, variant):
     print("parity stats", stats)
 
 
+def test_nonconvex_polygons_every_step(sp):
+    # Rectangles mixed with non-convex stars (10-16 vertices each): the
+    # general edge path and the rectangle path in one instance, ragged W = 11.
+    stats = {}
+    for seed in (0, 1):
+        spec = I.nonconvex_map(seed)
+        sw = I.dynamic_swarm(spec.scale, seed=seed, groups=4, particles=48, waypoints=11)
+        _run_injected(sp, spec, sw, 10, stats)
+    print("parity stats", stats)
+    assert stats["paths"] == 2 * 10 * 4 * 48
+
+
 def test_dynamic_shape_steps(sp):
     # Paper-shaped instance: 366 map, 30 rectangles, 8 x 170 particles, W = 20.
     spec = I.dynamic_map(0)
