@@ -33,22 +33,23 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2308_10169_amd", "csrc", "kernels.hip")
 
 def counter_record(kernel, tune):
     """HBM traffic and VALU instruction count per launch of the fused
-    iteration, from the committed rocprofv3 counter summary -- only while it
-    describes this kernel source and tile shape (else None)."""
+    iteration for this tile shape, from the committed rocprofv3 counter
+    summary -- only while it describes this kernel source (else None)."""
     import hashlib
     try:
-        rec = {}
+        sha, rec = None, None
         with open(COUNTERS) as f:
             for line in f:
-                if ": " in line and not line.startswith(("#", "|", "`")):
-                    k, v = line.strip().split(": ", 1)
-                    rec[k] = v
+                line = line.strip()
+                if line.startswith("source_sha256: "):
+                    sha = line.split(": ", 1)[1]
+                elif line.startswith(f"tile {tune[0]},{tune[1]}: "):
+                    rec = dict(kv.split("=", 1) for kv in line.split(": ", 1)[1].split())
         with open(KERNEL_SRC, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+            cur = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if rec.get("source_sha256") != sha or rec.get("kernel") != kernel or \
-            rec.get("tune") != f"{tune[0]},{tune[1]}":
+    if rec is None or sha != cur or rec.get("kernel") != kernel:
         return None
     return dict(hbm_bytes=float(rec["hbm_bytes_per_launch"]),
                 valu_insts=float(rec["valu_insts_per_launch"]))
