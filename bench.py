@@ -58,9 +58,10 @@ def counter_record(kernel, tune):
 def executed_fraction(bp, specs, sws, tune, sample):
     """Share of the segment x edge tests the fused iteration actually runs:
     a wave skips a rectangle outside the bounding box of its points.  The
-    kernel's mapping (blocks of an even number of whole particles, K
-    consecutive stream slots per thread, 64 threads per wave) is replayed on
-    the swarm state left by the timed launches of sampled instances."""
+    kernel's mapping (blocks of an even number of whole particles, thread t
+    on chunk t // ppb of K segments of particle t % ppb, 64 threads per wave)
+    is replayed on the swarm state left by the timed launches of sampled
+    instances."""
     K, B = tune
     run = tot = 0.0
     for i in sample:
@@ -76,20 +77,23 @@ def executed_fraction(bp, specs, sws, tune, sample):
         rects = np.array([[v[:, 0].min(), v[:, 1].min(), v[:, 0].max(), v[:, 1].max()]
                           for v in (spec.verts[spec.poly_ptr[q]:spec.poly_ptr[q + 1]]
                                     for q in range(spec.n_polys))]).reshape(-1, 4)
-        ppb = max(2, ((B * K) // S) & ~1)
+        C = (W + K) // K
+        ppb = max(2, (B // C) & ~1)
+        t = np.arange(B)
+        c, jt = t // ppb, t % ppb
         for p0 in range(0, P, ppb):
             np_ = min(ppb, P - p0)
-            sx, sy = px[p0:p0 + np_].ravel(), py[p0:p0 + np_].ravel()
-            n_pts = len(sx)
             for w0 in range(0, B, 64):
-                a = w0 * K
-                if a >= n_pts - 1:
-                    break
-                b = min(n_pts - 1, (w0 + 64) * K)  # last point the wave reads
-                m = np.arange(a, min(b, (w0 + 64) * K))
-                segs = np.count_nonzero(m % S != S - 1)
-                x0, x1, y0, y1 = sx[a:b + 1].min(), sx[a:b + 1].max(), sy[a:b + 1].min(), sy[a:b + 1].max()
-                keep = ~((rects[:, 2] <= x0) | (rects[:, 0] >= x1) | (rects[:, 3] <= y0) | (rects[:, 1] >= y1))
+                lanes = slice(w0, w0 + 64)
+                ok = (c[lanes] < C) & (jt[lanes] < np_)
+                if not ok.any():
+                    continue
+                cc, jj = c[lanes][ok], jt[lanes][ok]
+                idx = np.minimum(cc[:, None] * K + np.arange(K + 1)[None, :], S - 1)
+                wx, wy = px[p0 + jj[:, None], idx], py[p0 + jj[:, None], idx]
+                segs = np.count_nonzero(cc[:, None] * K + np.arange(K)[None, :] < S - 1)
+                keep = ~((rects[:, 2] <= wx.min()) | (rects[:, 0] >= wx.max()) |
+                         (rects[:, 3] <= wy.min()) | (rects[:, 1] >= wy.max()))
                 run += 4.0 * segs * keep.sum()
                 tot += 4.0 * segs * len(rects)
     return run / tot if tot else 1.0

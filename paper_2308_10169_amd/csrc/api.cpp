@@ -233,17 +233,17 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   return L;
 }
 
-// A tile shape suits a batch when a thread's K segments touch at most three
-// particles (K <= 2(W+2) for the shortest path) and the block's positions
-// fit the LDS buffer (B*K <= 4096 slots).
+// A tile shape suits a batch when a thread's K segments are not mostly empty
+// for the shortest path (K <= 2(W+2)) and the block's positions fit the LDS
+// buffer (B*K <= 4096 slots).
 bool tune_ok(int K, int B, int w_min) {
   if (!(step_supported(K) && (B == 64 || B == 128 || B == 256) && K <= 2 * (w_min + 2) &&
         B * K <= 4096))
     return false;
   // dynamic LDS of the fused iteration stays within 64 KiB: positions
   // (< 2BK floats), 5 words per particle, the group table, 6 words per thread
-  const size_t ppb = (size_t)(B * K) / (w_min + 2);
-  const size_t words = std::max<size_t>(2048, 2 * (size_t)B * K) + 5 * ppb + 5 * kMaxG + 6 * (size_t)B;
+  const size_t ppb = (size_t)B;  // at most one particle per thread
+  const size_t words = std::max<size_t>(2048, 2 * (size_t)B * K) + 5 * ppb + 5 * kMaxG + 2 * (size_t)B;
   return 4 * words <= 65536;
 }
 
@@ -275,8 +275,8 @@ sepso_status hip_fail(sepso_batch* b, hipError_t e, const char* what) {
   } while (0)
 
 // Block geometry for the current tune: each block of the fused iteration
-// takes ppb = floor(B*K / (W+2)) consecutive particles (their W+2 stream
-// slots fill the block's B*K); fills the desc fields, the LDS sizing and the
+// takes ppb = B / C consecutive particles (C = ceil((W+1)/K) chunks of K
+// segments per particle, one thread per chunk); fills the desc fields, the LDS sizing and the
 // block -> (instance, first particle) table, heaviest blocks first (the
 // dispatcher hands blocks out in order).
 void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
@@ -286,7 +286,10 @@ void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
   int buf = 8 * 256, ppb_max = 1;
   for (int i = 0; i < b->n; ++i) {
     InstDesc& d = b->desc[i];
-    d.ppb = std::max(2, ((B * K) / (d.W + 2)) & ~1);  // even: every block starts 16-byte aligned
+    // C chunks of K segments per particle, one thread each; even: every
+    // block starts 16-byte aligned
+    const int C = (d.W + K) / K;
+    d.ppb = std::max(2, (B / C) & ~1);
     d.n_blocks = (d.G * d.N + d.ppb - 1) / d.ppb;
     buf = std::max(buf, d.ppb * 2 * d.W);
     ppb_max = std::max(ppb_max, d.ppb);

@@ -413,34 +413,28 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
 // every obstacle edge of the instance, edges staged through LDS (s_buf, all
 // threads of the block take part in the staging and barriers).  Crossing
 // words: bit K-1-s set when segment s properly crosses the edge (never for
-// masked slots); counted as a total plus pieces 0 and 2 (piece 1 = the rest).
-template <int K, bool THREE>
+// masked slots); ct counts them.
+template <int K>
 __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, float* s_buf,
                                           bool active, const float (&px)[K + 1],
                                           const float (&py)[K + 1], const float (&dx)[K],
-                                          const float (&ndy)[K], const float (&nc)[K],
-                                          uint32_t mk0, uint32_t mk2, int& ct, int& c0, int& c2) {
-  auto count = [&](uint32_t x) {
-    // x is pinned to a register so the piece masks apply to it (one AND each)
-    // instead of being folded back into the crossing expression
-    asm("" : "+v"(x));
-    ct += __popc(x);
-    c0 += __popc(x & mk0);
-    if (THREE) c2 += __popc(x & mk2);
-  };
+                                          const float (&ndy)[K], const float (&nc)[K], int& ct) {
+  auto count = [&](uint32_t x) { ct += __popc(x); };
   const int t = threadIdx.x, B = blockDim.x;
   // Bounding box of the wave's points (wave-uniform).  A segment lies in the
   // box of its end points, so a rectangle that is outside the box (touching
   // allowed) cannot be properly crossed by any of the wave's segments: its
   // sign tests could only mark points exactly on its lines, a degenerate
   // contact, and the whole rectangle is skipped.
-  float bx0 = px[0], bx1 = px[0], by0 = py[0], by1 = py[0];
+  float bx0 = INFINITY, bx1 = -INFINITY, by0 = INFINITY, by1 = -INFINITY;
+  if (active) {
 #pragma unroll
-  for (int s = 1; s <= K; ++s) {
-    bx0 = fminf(bx0, px[s]);
-    bx1 = fmaxf(bx1, px[s]);
-    by0 = fminf(by0, py[s]);
-    by1 = fmaxf(by1, py[s]);
+    for (int s = 0; s <= K; ++s) {
+      bx0 = fminf(bx0, px[s]);
+      bx1 = fmaxf(bx1, px[s]);
+      by0 = fminf(by0, py[s]);
+      by1 = fmaxf(by1, py[s]);
+    }
   }
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) {
@@ -583,8 +577,8 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   float* s_c = s_buf + pl.buf_floats;  // per particle: a1, a2, a3, group
   float* s_wv = s_c + 4 * pl.ppb_max;   // per group: w, V_limit / 2, C1, C2, C3
   int* s_imp = reinterpret_cast<int*>(s_wv + 5 * kMaxG);
-  int* s_q = s_imp + pl.ppb_max;
-  float* s_l = reinterpret_cast<float*>(s_q + 3 * blockDim.x);
+  int* s_q = s_imp + pl.ppb_max;                            // per thread: crossings
+  float* s_l = reinterpret_cast<float*>(s_q + blockDim.x);  // per thread: length
 
   const int2 bt = pl.blk_tiles[blockIdx.x];
   const int inst = bt.x, p0 = bt.y;
@@ -756,30 +750,21 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   if (!FIT) return;
   __syncthreads();
 
-  // ---- B. this thread's K segments of the point stream ---------------------
-  const int n_pts = np * S;               // stream points
-  const bool active = t * K < n_pts - 1;  // owns at least one slot
-  const int jf = (t * K) / S;             // first particle touched
-  const int i0 = t * K - jf * S;          // stream slot tK = (particle jf, index i0)
+  // ---- B. this thread's K segments --------------------------------------------
+  // A particle's W+1 segments are cut into C chunks of K; thread t takes chunk
+  // t / ppb of particle t mod ppb, so the 64 lanes of a wave hold the same
+  // stretch of 64 neighbouring paths -- close together once the swarm
+  // converges, which is what the culling in phase C feeds on.
+  const int C = (W + K) / K;
+  const int c = t / d.ppb, jt = t - c * d.ppb;
+  const bool active = c < C && jt < np;
+  const int jc = active ? jt : 0;  // inactive lanes read a valid particle, count nothing
+  const int i0 = c * K;           // first point index of the chunk
   const float4 ends = pl.ends[inst];
-  // point tK + s is (particle jf + u, index i0 + s - uS), u = number of
-  // particle boundaries passed (K <= 2S, so u <= 2)
-  auto locate = [&](int s, int& j, int& idx) {
-    const int a = i0 + s;
-    const int u = (a >= S) + (a >= 2 * S);
-    j = jf + u;
-    idx = a - u * S;
-  };
   float px[K + 1], py[K + 1];
 #pragma unroll
   for (int s = 0; s <= K; ++s) {
-    int j, idx;
-    if (t * K + s < n_pts) {
-      locate(s, j, idx);
-    } else {  // past the stream's end: repeat its last point
-      j = np - 1;
-      idx = S - 1;
-    }
+    const int idx = i0 + s < S - 1 ? i0 + s : S - 1;
     float x, y;
     if (idx == 0) {
       x = ends.x;
@@ -788,75 +773,42 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
       x = ends.z;
       y = ends.w;
     } else {
-      x = s_buf[j * D + idx - 1];
-      y = s_buf[j * D + W + idx - 1];
+      x = s_buf[jc * D + idx - 1];
+      y = s_buf[jc * D + W + idx - 1];
     }
     px[s] = x;
     py[s] = y;
   }
   float dx[K], ndy[K], nc[K];
-  uint32_t mk0 = 0, mk1 = 0, mk2 = 0;
-  float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+  float len_sum = 0.f;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
     const float ddx = px[s + 1] - px[s], ddy = py[s + 1] - py[s];
-    const int m = t * K + s;  // slot between points m and m+1
-    int jm, im;
-    locate(s, jm, im);
-    const bool seg = m < n_pts - 1 && im != S - 1;
-    // A slot that is no path segment (a junction or past the stream's end)
-    // gets the zero line: every vertex side is +0 (coordinates are >= 0),
-    // so its side bits never differ and it never counts as a crossing.
+    const bool seg = active && i0 + s < S - 1;  // segment i0+s of W+1
+    // A slot that is no path segment gets the zero line: every vertex side
+    // is +0 (coordinates are >= 0), so its side bits never differ and it
+    // never counts as a crossing.
     dx[s] = seg ? ddx : 0.f;
     ndy[s] = seg ? -ddy : 0.f;
     nc[s] = seg ? fmaf(ddy, px[s], -(ddx * py[s])) : 0.f;
-    if (seg) {
-      const float len = sqrtf(ddx * ddx + ddy * ddy);
-      const uint32_t bit = 1u << (K - 1 - s);
-      const int pc = jm - jf;
-      if (pc == 0) {
-        mk0 |= bit;
-        l0 += len;
-      } else if (pc == 1) {
-        mk1 |= bit;
-        l1 += len;
-      } else {
-        mk2 |= bit;
-        l2 += len;
-      }
-    }
+    if (seg) len_sum += sqrtf(ddx * ddx + ddy * ddy);
   }
   __syncthreads();  // positions consumed: s_buf now stages edges
 
   // ---- C. crossings ----------------------------------------------------------
-  // A thread's K slots reach a third particle only when K > W + 2 (block-
-  // uniform: a block belongs to one instance), so the third piece's count is
-  // compiled in only for such instances.
-  int ct = 0, c0 = 0, c2 = 0;
-  if (K > S)
-    crossings<K, true>(pl, d, s_buf, active, px, py, dx, ndy, nc, mk0, mk2, ct, c0, c2);
-  else
-    crossings<K, false>(pl, d, s_buf, active, px, py, dx, ndy, nc, mk0, mk2, ct, c0, c2);
-  const int c1 = ct - c0 - c2;
+  int ct = 0;
+  crossings<K>(pl, d, s_buf, active, px, py, dx, ndy, nc, ct);
 
   // ---- D. per-particle fitness and Pbest -------------------------------------
-  s_q[3 * t + 0] = c0;
-  s_q[3 * t + 1] = c1;
-  s_q[3 * t + 2] = c2;
-  s_l[3 * t + 0] = l0;
-  s_l[3 * t + 1] = l1;
-  s_l[3 * t + 2] = l2;
+  s_q[t] = ct;
+  s_l[t] = len_sum;
   __syncthreads();
   for (int j = t; j < np; j += B) {
-    // threads holding its W+1 slots: the first may hold it as its piece 1 or
-    // 2, every later one starts inside it (piece 0)
-    const int t_lo = (j * S) / K, t_hi = (j * S + W) / K;
-    const int pc_lo = j - (t_lo * K) / S;
-    int q = s_q[3 * t_lo + pc_lo];
-    float L = s_l[3 * t_lo + pc_lo];
-    for (int tt = t_lo + 1; tt <= t_hi; ++tt) {
-      q += s_q[3 * tt];
-      L += s_l[3 * tt];
+    int q = 0;
+    float L = 0.f;
+    for (int cc = 0; cc < C; ++cc) {  // chunk order: deterministic
+      q += s_q[j + cc * d.ppb];
+      L += s_l[j + cc * d.ppb];
     }
     const float qf = (float)q;
     float pw = 1.f;
@@ -932,7 +884,7 @@ void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev
 }
 
 size_t iter_lds_bytes(const Pools& pl, int threads) {
-  return 4 * ((size_t)pl.buf_floats + 5 * (size_t)pl.ppb_max + 5 * kMaxG + 6 * (size_t)threads);
+  return 4 * ((size_t)pl.buf_floats + 5 * (size_t)pl.ppb_max + 5 * kMaxG + 2 * (size_t)threads);
 }
 
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
