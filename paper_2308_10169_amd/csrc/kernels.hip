@@ -637,7 +637,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     float4* V4 = reinterpret_cast<float4*>(V);
     const float4* P4 = reinterpret_cast<const float4*>(Pp);
     float4* B4 = reinterpret_cast<float4*>(s_buf);
-    constexpr int CH = 4;
+    constexpr int CH = 2;
     for (int g0 = t; g0 < ng; g0 += CH * B) {
       float4 xa[CH], va[CH], pa[CH];
       float ga[CH][4], ta[CH][4];
@@ -865,8 +865,10 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
 
 // One fused iteration (fitness path) and the update-only flush, as separate
 // kernels so that profiles separate them.
+// K = 8 fits five waves per SIMD when capped at 96 registers (a few spilled
+// words outside the crossing loop), which beats four waves at 107.
 template <int K>
-__global__ __launch_bounds__(256) void iter_kernel(Pools pl, int flags) {
+__global__ __launch_bounds__(256, K == 8 ? 5 : 1) void iter_kernel(Pools pl, int flags) {
   iteration<K, true>(pl, flags);
 }
 template <int K>
