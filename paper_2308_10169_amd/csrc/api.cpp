@@ -233,25 +233,57 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   return L;
 }
 
+// Particles per block of the fused iteration: C = ceil((W+1)/K) chunks of K
+// segments per particle, one thread per chunk; even, so that every block
+// starts 16-byte aligned.
+int tile_ppb(int W, int K, int B) { return std::max(2, (B / ((W + K) / K)) & ~1); }
+
+// Dynamic LDS areas of the fused iteration for a tile shape: maxima over the
+// instances (floats; counts of groups and particles per block).
+struct TileLds {
+  int pos, stage, gb, ngb, ppb;
+};
+
+TileLds tile_lds(const std::vector<InstDesc>& desc, int K, int B) {
+  TileLds L{8, 8, 4, 1, 2};
+  for (const InstDesc& d : desc) {
+    const int ppb = tile_ppb(d.W, K, B), D = 2 * d.W;
+    const int ngb = std::min(d.G, (ppb - 1) / d.N + 2);  // groups ppb consecutive particles span
+    L.pos = std::max(L.pos, ppb * D);
+    L.stage = std::max(L.stage, std::min(kStageFloats, std::max(4 * d.n_rects, 8 * d.n_gedges)));
+    L.gb = std::max(L.gb, (ngb + 1) * D);
+    L.ngb = std::max(L.ngb, ngb);
+    L.ppb = std::max(L.ppb, ppb);
+  }
+  L.pos = (L.pos + 7) & ~7;      // records after it 32-byte aligned
+  L.stage = (L.stage + 7) & ~7;
+  L.gb = (L.gb + 3) & ~3;        // per-particle float4 words after it
+  return L;
+}
+
 // A tile shape suits a batch when a thread's K segments are not mostly empty
-// for the shortest path (K <= 2(W+2)) and the block's positions fit the LDS
-// buffer (B*K <= 4096 slots).
-bool tune_ok(int K, int B, int w_min) {
+// for the shortest path (K <= 2(W+2)), B*K <= 4096, and the fused
+// iteration's LDS for this batch stays within 64 KiB.
+bool tune_ok(int K, int B, const std::vector<InstDesc>& desc) {
+  int w_min = kMaxW;
+  for (const InstDesc& d : desc) w_min = std::min(w_min, d.W);
   if (!(step_supported(K) && (B == 64 || B == 128 || B == 256) && K <= 2 * (w_min + 2) &&
         B * K <= 4096))
     return false;
-  // dynamic LDS of the fused iteration stays within 64 KiB: positions
-  // (< 2BK floats), 5 words per particle, the group table, 6 words per thread
-  const size_t ppb = (size_t)B;  // at most one particle per thread
-  const size_t words = std::max<size_t>(2048, 2 * (size_t)B * K) + 5 * ppb + 5 * kMaxG + 2 * (size_t)B;
-  return 4 * words <= 65536;
+  const TileLds L = tile_lds(desc, K, B);
+  return 4 * iter_lds_words(L.pos, L.stage, L.gb, L.ngb, L.ppb, B) <= 65536;
 }
 
-sepso_tune default_tune(int w_min) {
+// (4, 64) suits every batch: its LDS need stays far below 64 KiB.
+sepso_tune default_tune(const std::vector<InstDesc>& desc) {
   for (int K : {8, 4})
-    if (tune_ok(K, 128, w_min)) return sepso_tune{K, 128};
+    if (tune_ok(K, 128, desc)) return sepso_tune{K, 128};
   return sepso_tune{4, 64};
 }
+
+constexpr const char* kTuneRule =
+    "tune: seg_per_thread in {4,8,12,16,24} and <= 2*(waypoints+2), block_threads in {64,128,256}, "
+    "product <= 4096, fused-iteration LDS <= 64 KiB";
 
 }  // namespace
 
@@ -275,28 +307,25 @@ sepso_status hip_fail(sepso_batch* b, hipError_t e, const char* what) {
   } while (0)
 
 // Block geometry for the current tune: each block of the fused iteration
-// takes ppb = B / C consecutive particles (C = ceil((W+1)/K) chunks of K
-// segments per particle, one thread per chunk); fills the desc fields, the LDS sizing and the
-// block -> (instance, first particle) table, heaviest blocks first (the
-// dispatcher hands blocks out in order).
+// takes ppb consecutive particles (tile_ppb); fills the desc fields, the LDS
+// sizing and the block -> (instance, first particle) table, heaviest blocks
+// first (the dispatcher hands blocks out in order).
 void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
   const int K = b->tune.seg_per_thread, B = b->tune.block_threads;
   blk->clear();
   std::vector<std::pair<double, int>> order;
-  int buf = 8 * 256, ppb_max = 1;
   for (int i = 0; i < b->n; ++i) {
     InstDesc& d = b->desc[i];
-    // C chunks of K segments per particle, one thread each; even: every
-    // block starts 16-byte aligned
-    const int C = (d.W + K) / K;
-    d.ppb = std::max(2, (B / C) & ~1);
+    d.ppb = tile_ppb(d.W, K, B);
     d.n_blocks = (d.G * d.N + d.ppb - 1) / d.ppb;
-    buf = std::max(buf, d.ppb * 2 * d.W);
-    ppb_max = std::max(ppb_max, d.ppb);
     order.push_back({(double)d.n_edges * d.ppb * (d.W + 2), i});
   }
-  b->pl.buf_floats = (buf + 7) & ~7;
-  b->pl.ppb_max = ppb_max;
+  const TileLds L = tile_lds(b->desc, K, B);
+  b->pl.pos_floats = L.pos;
+  b->pl.stage_floats = L.stage;
+  b->pl.gb_floats = L.gb;
+  b->pl.ngb_max = L.ngb;
+  b->pl.ppb_max = L.ppb;
   std::stable_sort(order.begin(), order.end(),
                    [](const std::pair<double, int>& a, const std::pair<double, int>& c) { return a.first > c.first; });
   for (auto& o : order) {
@@ -352,23 +381,20 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
     st = check_swarm(&sw[i], i);
     if (st != SEPSO_OK) return st;
   }
-  int w_min = kMaxW;
-  for (int i = 0; i < n; ++i) w_min = std::min(w_min, sw[i].waypoints);
-  sepso_tune tn = default_tune(w_min);
-  if (tune) {
-    tn = *tune;
-    if (!tune_ok(tn.seg_per_thread, tn.block_threads, w_min))
-      return fail(SEPSO_E_ARG,
-                  "tune: seg_per_thread in {4,8,12,16,24} and <= 2*(waypoints+2), block_threads in "
-                  "{64,128,256}, product <= 4096");
-  }
   if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(SEPSO_E_ARG, "workspace not 256-byte aligned");
   sepso_batch* b = new (std::nothrow) sepso_batch();
   if (!b) return fail(SEPSO_E_NOMEM, "host allocation failed");
   b->n = n;
-  b->tune = tn;
   b->lay = plan_layout(maps, sw, n, &b->desc);
+  b->tune = default_tune(b->desc);
+  if (tune) {
+    if (!tune_ok(tune->seg_per_thread, tune->block_threads, b->desc)) {
+      delete b;
+      return fail(SEPSO_E_ARG, "%s", kTuneRule);
+    }
+    b->tune = *tune;
+  }
   if (ws_bytes < b->lay.total) {
     const size_t need = b->lay.total;
     delete b;
@@ -892,9 +918,7 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
   float win_ms = INFINITY;
   for (int K : Ks)
     for (int B : Bs) {
-      int w_min = kMaxW;
-      for (auto& d : b->desc) w_min = std::min(w_min, d.W);
-      if (!tune_ok(K, B, w_min)) continue;
+      if (!tune_ok(K, B, b->desc)) continue;
       b->tune = sepso_tune{K, B};
       st = upload_tiles(b);
       if (st != SEPSO_OK) return st;
@@ -923,11 +947,8 @@ sepso_status sepso_batch_set_tune(sepso_batch* b, const sepso_tune* tune) {
   if (!b || !tune) return fail(SEPSO_E_ARG, "batch/tune NULL");
   sepso_status st = usable(b);
   if (st != SEPSO_OK) return st;
-  int w_min = kMaxW;
-  for (const InstDesc& d : b->desc) w_min = std::min(w_min, d.W);
-  if (!tune_ok(tune->seg_per_thread, tune->block_threads, w_min))
-    return fail(SEPSO_E_ARG, "tune: seg_per_thread in {4,8,12,16,24} and <= 2*(waypoints+2), "
-                             "block_threads in {64,128,256}, product <= 4096");
+  if (!tune_ok(tune->seg_per_thread, tune->block_threads, b->desc))
+    return fail(SEPSO_E_ARG, "%s", kTuneRule);
   b->tune = *tune;
   return upload_tiles(b);
 }

@@ -9,6 +9,9 @@ namespace sepso {
 void launch_geom(const Pools& pl, int n_inst, int move, hipStream_t s);
 void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev, hipStream_t s);
 bool step_supported(int K);
+// 32-bit words of dynamic LDS the fused iteration takes per block.
+size_t iter_lds_words(int pos_floats, int stage_floats, int gb_floats, int ngb_max, int ppb_max,
+                      int threads);
 // One iteration: the fused (or update-only) tile kernel, then the per-instance
 // reduce; events, when given, bracket the tile kernel alone.
 void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,

@@ -409,13 +409,33 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   }
 }
 
+// Obstacle records into the LDS staging area: chunk c of the rectangles when
+// the instance has any, else chunk c of the other polygons' edges (float4
+// words, two loads in flight per thread).
+__device__ __forceinline__ void stage_records(const Pools& pl, const InstDesc& d, float* s_stage,
+                                              bool rects, int first, int count) {
+  const int t = threadIdx.x, B = blockDim.x;
+  const float4* src = rects ? pl.rects + d.ro + first
+                            : reinterpret_cast<const float4*>(pl.edges + d.geo + first);
+  const int n4 = rects ? count : 2 * count;
+  float4* dst = reinterpret_cast<float4*>(s_stage);
+  for (int q = t; q < n4; q += 2 * B) {
+    const float4 a = src[q];
+    float4 b;
+    if (q + B < n4) b = src[q + B];
+    dst[q] = a;
+    if (q + B < n4) dst[q + B] = b;
+  }
+}
+
 // Phase C of the fused iteration: crossings of this thread's K segments with
-// every obstacle edge of the instance, edges staged through LDS (s_buf, all
-// threads of the block take part in the staging and barriers).  Crossing
+// every obstacle edge of the instance, records staged through LDS (s_stage:
+// the first chunk was staged before the block's first barrier, later ones
+// are staged here by all threads of the block between barriers).  Crossing
 // words: bit K-1-s set when segment s properly crosses the edge (never for
 // masked slots); ct counts them.
 template <int K>
-__device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, float* s_buf,
+__device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, float* s_stage,
                                           bool active, const float (&px)[K + 1],
                                           const float (&py)[K + 1], const float (&dx)[K],
                                           const float (&ndy)[K], const float (&nc)[K], int& ct) {
@@ -447,14 +467,15 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
   // coordinate difference; corner sides: (x0,y0) by two FMAs, each other
   // corner from a neighbour by one FMA along the rectangle's side (three
   // roundings on the far corner stay well inside the degenerate band).
-  const float4* rr = pl.rects + d.ro;
-  float4* s_rect = reinterpret_cast<float4*>(s_buf);
-  const int rchunk = pl.buf_floats / 4;
+  const float4* s_rect = reinterpret_cast<const float4*>(s_stage);
+  const int rchunk = pl.stage_floats / 4;
   for (int r0 = 0; r0 < d.n_rects; r0 += rchunk) {
     const int nr = d.n_rects - r0 < rchunk ? d.n_rects - r0 : rchunk;
-    if (r0 > 0) __syncthreads();
-    for (int q = t; q < nr; q += B) s_rect[q] = rr[r0 + q];
-    __syncthreads();
+    if (r0 > 0) {
+      __syncthreads();
+      stage_records(pl, d, s_stage, true, r0, nr);
+      __syncthreads();
+    }
     if (active) {
       float4 bn = s_rect[0];
       for (int e = 0; e < nr; ++e) {
@@ -495,18 +516,15 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
   // edge instead of carried over.
   uint32_t w0 = 0, wp = 0;
   bool have_w0 = false, have_wp = false;
-  const EdgeRec* er = pl.edges + d.geo;
-  EdgeRec* s_edge = reinterpret_cast<EdgeRec*>(s_buf);
-  const int chunk = pl.buf_floats / 8;  // edge records per LDS pass
+  const EdgeRec* s_edge = reinterpret_cast<const EdgeRec*>(s_stage);
+  const int chunk = pl.stage_floats / 8;  // edge records per LDS pass
   for (int e0 = 0; e0 < d.n_gedges; e0 += chunk) {
     const int ne = d.n_gedges - e0 < chunk ? d.n_gedges - e0 : chunk;
-    if (e0 > 0 || d.n_rects > 0) __syncthreads();
-    {
-      const float4* src = reinterpret_cast<const float4*>(er + e0);
-      float4* dst = reinterpret_cast<float4*>(s_buf);
-      for (int q = t; q < ne * 2; q += B) dst[q] = src[q];
+    if (e0 > 0 || d.n_rects > 0) {
+      __syncthreads();
+      stage_records(pl, d, s_stage, false, e0, ne);
+      __syncthreads();
     }
-    __syncthreads();
     if (active) {
       for (int e = 0; e < ne; ++e) {
         const EdgeRec r = s_edge[e];
@@ -551,34 +569,40 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
 
 // ---------------------------------------------------------------------------
 // Fused iteration over one block = ppb consecutive particles of an instance
-// (flat index g*N + n, possibly spanning groups).
+// (flat index g*N + n, possibly spanning groups; at most one particle per
+// thread).
 //
 //  A. previous iteration's update, elementwise and coalesced over the
 //     block's contiguous (particle, coordinate) range; new positions also
-//     go to LDS;
-//  B. the block's paths are laid end to end as a stream of points (start,
-//     W waypoints, target per particle); thread t takes the K segments
-//     starting at stream slot tK.  A slot joining one particle's target to
-//     the next one's start is not a path segment and is masked out; a
-//     thread's K segments belong to at most three particles ("pieces");
-//  C. crossings of the K segments with every obstacle edge (edges staged in
-//     LDS, reusing the position buffer): per edge, one packed side word of
-//     the edge's end vertex against the K segment lines and one of the K+1
-//     points against the edge line; crossing bits = both straddle;
-//  D. per-particle Q and L summed in thread order (deterministic), fitness
-//     and Pbest; improved particles' positions go to P.
+//     go to LDS, where they stay for the whole launch.  Every global read
+//     the block needs -- its X, V, P range, the gbest rows of its groups and
+//     Tbest, the hyper-parameters, its particles' old Pbest fitness and the
+//     first chunk of obstacle records -- is issued before the first barrier,
+//     so the block waits on memory about once;
+//  B. a particle's W+1 segments are cut into C chunks of K; thread t takes
+//     chunk t / ppb of particle t mod ppb (slots past the last segment are
+//     masked out);
+//  C. crossings of the K segments with every obstacle edge (records staged
+//     in LDS): per edge, one packed side word of the edge's end vertex
+//     against the K segment lines and one of the K+1 points against the
+//     edge line; crossing bits = both straddle;
+//  D. per-particle Q and L summed in chunk order (deterministic), fitness
+//     and Pbest; improved particles' positions go from LDS to P.
 // ---------------------------------------------------------------------------
 template <int K, bool FIT>
 __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
-  // dynamic LDS: positions / edge chunk | r1..r3 per particle | Pbest flags |
-  // per-thread piece counts and lengths
+  // dynamic LDS: positions | obstacle records | Tbest and the gbest rows of
+  // the block's groups | r1..r3 and group per particle | per group w,
+  // V_limit / 2, C1..C3 | Pbest flags | per-thread crossings and lengths
   extern __shared__ __attribute__((aligned(16))) float s_dyn[];
   float* s_buf = s_dyn;
-  float* s_c = s_buf + pl.buf_floats;  // per particle: a1, a2, a3, group
-  float* s_wv = s_c + 4 * pl.ppb_max;   // per group: w, V_limit / 2, C1, C2, C3
-  int* s_imp = reinterpret_cast<int*>(s_wv + 5 * kMaxG);
-  int* s_q = s_imp + pl.ppb_max;                            // per thread: crossings
-  float* s_l = reinterpret_cast<float*>(s_q + blockDim.x);  // per thread: length
+  float* s_stage = s_buf + pl.pos_floats;
+  float* s_gb = s_stage + pl.stage_floats;
+  float* s_c = s_gb + pl.gb_floats;
+  float* s_wv = s_c + 4 * pl.ppb_max;
+  int* s_imp = reinterpret_cast<int*>(s_wv + 5 * pl.ngb_max);
+  int* s_q = s_imp + pl.ppb_max;
+  float* s_l = reinterpret_cast<float*>(s_q + blockDim.x);
 
   const int2 bt = pl.blk_tiles[blockIdx.x];
   const int inst = bt.x, p0 = bt.y;
@@ -591,13 +615,78 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   const int np = min(d.ppb, d.G * N - p0);  // particles in this block
   const int t = threadIdx.x, B = blockDim.x;
 
-  // ---- A. update (coalesced) ----------------------------------------------
+  // ---- A0. the block's global reads ------------------------------------------
+  // The block's range starts 16-byte aligned (even particles per block, pools
+  // padded per instance), so the walk goes by float4 groups of elements; only
+  // an instance's last group can be partial.  A thread's first CH groups are
+  // read into registers here, ahead of everything else.
+  float* X = pl.X + d.xo + (int64_t)p0 * D;
+  float* V = pl.V + d.xo + (int64_t)p0 * D;
+  const float* Pp = pl.P + d.xo + (int64_t)p0 * D;
+  const int nel = np * D, ng = (nel + 3) >> 2;
+  float4* X4 = reinterpret_cast<float4*>(X);
+  float4* V4 = reinterpret_cast<float4*>(V);
+  const float4* P4 = reinterpret_cast<const float4*>(Pp);
+  float4* B4 = reinterpret_cast<float4*>(s_buf);
+  constexpr int CH = 4;
+  float4 xa[CH], va[CH], pa[CH];
+  auto load = [&](int g0) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int gi = g0 + c * B, e = 4 * gi;
+      if (gi < ng) {
+        if (e + 4 <= nel) {
+          xa[c] = X4[gi];
+          if (pending) {
+            va[c] = V4[gi];
+            pa[c] = P4[gi];
+          }
+        } else {
+          float* xs = &xa[c].x;
+          float* vs = &va[c].x;
+          float* ps = &pa[c].x;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const bool ok = e + i < nel;
+            xs[i] = ok ? X[e + i] : 0.f;
+            vs[i] = ok && pending ? V[e + i] : 0.f;
+            ps[i] = ok && pending ? Pp[e + i] : 0.f;
+          }
+        }
+      }
+    }
+  };
+  load(t);
+  float pf_old = 0.f;
+  if (FIT && t < np) pf_old = pl.Pf[d.po + p0 + t];
+  if (FIT) {
+    if (d.n_rects > 0)
+      stage_records(pl, d, s_stage, true, 0, min(d.n_rects, pl.stage_floats / 4));
+    else if (d.n_gedges > 0)
+      stage_records(pl, d, s_stage, false, 0, min(d.n_gedges, pl.stage_floats / 8));
+  }
+
+  // ---- A1. per-particle and per-group constants --------------------------------
   // Per particle one Philox call (r1..r3 scaled by the group's C1..C3) and
-  // its group; per group the inertia of Eq.(6) and V_limit / 2.  The element
-  // loop then walks (particle, coordinate) incrementally, without divisions.
+  // its group; per group the inertia of Eq.(6) and V_limit / 2; Tbest and the
+  // gbest rows of the block's groups (LDS row 0 and rows 1..).
+  const int g_lo = p0 / N;
   if (pending) {
     const int kk = k < d.T ? k : d.T;
-    const int g_lo = p0 / N, g_hi = (p0 + np - 1) / N;
+    const int g_hi = (p0 + np - 1) / N, ngb = g_hi - g_lo + 1;
+    {
+      const float* src_t = pl.tbest_pos + d.dpo;
+      const float* src_g = pl.gbest_pos + d.gpo + g_lo * D;
+      const int n_rows = (ngb + 1) * D;
+      for (int q = t; q < n_rows; q += 2 * B) {
+        const float a = q < D ? src_t[q] : src_g[q - D];
+        float b = 0.f;
+        const int q2 = q + B;
+        if (q2 < n_rows) b = q2 < D ? src_t[q2] : src_g[q2 - D];
+        s_gb[q] = a;
+        if (q2 < n_rows) s_gb[q2] = b;
+      }
+    }
     for (int g = g_lo + t; g <= g_hi; g += B) {
       const float* h = pl.hyper + (d.go + g) * 6;
       float* q = s_wv + 5 * (g - g_lo);
@@ -607,7 +696,8 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
       q[3] = h[1];
       q[4] = h[2];
     }
-    for (int j = t; j < np; j += B) {
+    if (t < np) {
+      const int j = t;
       const U4 r = philox((uint32_t)(p0 + j), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
       const int g = (p0 + j) / N;
       const float* h = pl.hyper + (d.go + g) * 6;
@@ -616,78 +706,19 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
       s_c[4 * j + 2] = h[2] * u01(r.v[2]);
       s_c[4 * j + 3] = __int_as_float(g - g_lo);
     }
-    __syncthreads();
   }
+  __syncthreads();
+
+  // ---- A2. update ---------------------------------------------------------------
+  // The element loop walks (particle, coordinate) incrementally, without
+  // divisions; groups past a thread's first CH are read chunk by chunk, every
+  // load of a chunk issued before its first store (the stores could alias
+  // later loads for the compiler).
   {
-    float* X = pl.X + d.xo + (int64_t)p0 * D;
-    float* V = pl.V + d.xo + (int64_t)p0 * D;
-    const float* Pp = pl.P + d.xo + (int64_t)p0 * D;
-    const float* Gb = pl.gbest_pos + d.gpo + (p0 / N) * D;
-    const float* Tb = pl.tbest_pos + d.dpo;
-    const int nel = np * D;
-    // The block's range starts 16-byte aligned (even particles per block, pools
-    // padded per instance), so the walk goes by float4 groups of elements;
-    // only an instance's last group can be partial.  Chunks of CH groups per
-    // thread: every load of a chunk is issued before its first store (the
-    // stores could alias later loads for the compiler).
-    const int ng = (nel + 3) >> 2;
     const int qB = (4 * B) / D, rB = 4 * B - qB * D;
     int j = (4 * t) / D, dd = 4 * t - j * D;  // particle and coordinate of group's first element
-    float4* X4 = reinterpret_cast<float4*>(X);
-    float4* V4 = reinterpret_cast<float4*>(V);
-    const float4* P4 = reinterpret_cast<const float4*>(Pp);
-    float4* B4 = reinterpret_cast<float4*>(s_buf);
-    constexpr int CH = 2;
     for (int g0 = t; g0 < ng; g0 += CH * B) {
-      float4 xa[CH], va[CH], pa[CH];
-      float ga[CH][4], ta[CH][4];
-      int ja[CH], da[CH];
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int gi = g0 + c * B, e = 4 * gi;
-        ja[c] = j;
-        da[c] = dd;
-        if (gi < ng) {
-          if (e + 4 <= nel) {
-            xa[c] = X4[gi];
-            if (pending) {
-              va[c] = V4[gi];
-              pa[c] = P4[gi];
-            }
-          } else {
-            float* xs = &xa[c].x;
-            float* vs = &va[c].x;
-            float* ps = &pa[c].x;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const bool ok = e + i < nel;
-              xs[i] = ok ? X[e + i] : 0.f;
-              vs[i] = ok && pending ? V[e + i] : 0.f;
-              ps[i] = ok && pending ? Pp[e + i] : 0.f;
-            }
-          }
-          if (pending) {
-            int jj = j, di = dd;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const bool ok = e + i < nel;
-              const int gl = ok ? __float_as_int(s_c[4 * jj + 3]) : 0;
-              ga[c][i] = ok ? Gb[gl * D + di] : 0.f;
-              ta[c][i] = ok ? Tb[di] : 0.f;
-              if (++di == D) {
-                di = 0;
-                ++jj;
-              }
-            }
-          }
-        }
-        dd += rB;
-        j += qB;
-        while (dd >= D) {
-          dd -= D;
-          ++j;
-        }
-      }
+      if (g0 != t) load(g0);
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         const int gi = g0 + c * B, e = 4 * gi;
@@ -696,7 +727,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
           if (pending) {
             float* vs = &va[c].x;
             const float* ps = &pa[c].x;
-            int jj = ja[c], di = da[c];
+            int jj = j, di = dd;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               if (e + i < nel) {
@@ -715,7 +746,8 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
                 const float hi = di < W ? d.width : d.height;
                 const float vmax = vlh * hi;
                 const float x = xs[i];
-                float v = w * vs[i] + a1 * (ps[i] - x) + a2 * (ga[c][i] - x) + a3 * (ta[c][i] - x);
+                const float gx = s_gb[(gl + 1) * D + di], tx = s_gb[di];
+                float v = w * vs[i] + a1 * (ps[i] - x) + a2 * (gx - x) + a3 * (tx - x);
                 v = clampf(v, -vmax, vmax);
                 vs[i] = v;
                 xs[i] = clampf(x + v, 0.f, hi);
@@ -743,6 +775,12 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
                 if (FIT) s_buf[e + i] = xs[i];
               }
           }
+        }
+        dd += rB;
+        j += qB;
+        while (dd >= D) {
+          dd -= D;
+          ++j;
         }
       }
     }
@@ -793,17 +831,17 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     nc[s] = seg ? fmaf(ddy, px[s], -(ddx * py[s])) : 0.f;
     if (seg) len_sum += sqrtf(ddx * ddx + ddy * ddy);
   }
-  __syncthreads();  // positions consumed: s_buf now stages edges
 
   // ---- C. crossings ----------------------------------------------------------
   int ct = 0;
-  crossings<K>(pl, d, s_buf, active, px, py, dx, ndy, nc, ct);
+  crossings<K>(pl, d, s_stage, active, px, py, dx, ndy, nc, ct);
 
   // ---- D. per-particle fitness and Pbest -------------------------------------
   s_q[t] = ct;
   s_l[t] = len_sum;
   __syncthreads();
-  for (int j = t; j < np; j += B) {
+  if (t < np) {
+    const int j = t;
     int q = 0;
     float L = 0.f;
     for (int cc = 0; cc < C; ++cc) {  // chunk order: deterministic
@@ -819,7 +857,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     pl.L[po] = L;
     pl.Q[po] = q;
     const float fc = isfinite(fv) ? fv : INFINITY;
-    const int imp = fc < pl.Pf[po];
+    const int imp = fc < pf_old;
     if (imp) {
       pl.Pf[po] = fc;
       pl.PL[po] = L;
@@ -828,25 +866,22 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     s_imp[j] = imp;
   }
   __syncthreads();
-  // Improved particles' rows go to P: the same float4 walk as phase A (each
-  // thread rereads the groups it wrote, from L2).
+  // Improved particles' rows go to P from the LDS copy of the new positions,
+  // by the same float4 walk as phase A.
   {
-    const float4* X4 = reinterpret_cast<const float4*>(pl.X + d.xo + (int64_t)p0 * D);
-    float4* P4 = reinterpret_cast<float4*>(pl.P + d.xo + (int64_t)p0 * D);
-    const float* Xs = pl.X + d.xo + (int64_t)p0 * D;
+    float4* P4w = reinterpret_cast<float4*>(pl.P + d.xo + (int64_t)p0 * D);
     float* Ps = pl.P + d.xo + (int64_t)p0 * D;
-    const int nel = np * D, ng = (nel + 3) >> 2;
     const int qB = (4 * B) / D, rB = 4 * B - qB * D;
     int j = (4 * t) / D, dd = 4 * t - j * D;
     for (int gi = t; gi < ng; gi += B) {
       const int e = 4 * gi;
       const int jl = j + (dd + 3) / D;  // particle of the group's last element
       if (e + 4 <= nel && s_imp[j] && s_imp[jl]) {
-        P4[gi] = X4[gi];
+        P4w[gi] = B4[gi];
       } else if (s_imp[j] || (jl < np && s_imp[jl])) {
         int jj = j, di = dd;
         for (int i = 0; i < 4; ++i) {
-          if (e + i < nel && s_imp[jj]) Ps[e + i] = Xs[e + i];
+          if (e + i < nel && s_imp[jj]) Ps[e + i] = s_buf[e + i];
           if (++di == D) {
             di = 0;
             ++jj;
@@ -885,8 +920,15 @@ void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev
   hipLaunchKernelGGL(init_kernel, dim3(n_blocks), dim3(256), 0, s, pl, frame_override, use_prev);
 }
 
+size_t iter_lds_words(int pos_floats, int stage_floats, int gb_floats, int ngb_max, int ppb_max,
+                      int threads) {
+  return (size_t)pos_floats + stage_floats + gb_floats + 5 * (size_t)ppb_max + 5 * (size_t)ngb_max +
+         2 * (size_t)threads;
+}
+
 size_t iter_lds_bytes(const Pools& pl, int threads) {
-  return 4 * ((size_t)pl.buf_floats + 5 * (size_t)pl.ppb_max + 5 * kMaxG + 2 * (size_t)threads);
+  return 4 * iter_lds_words(pl.pos_floats, pl.stage_floats, pl.gb_floats, pl.ngb_max, pl.ppb_max,
+                            threads);
 }
 
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
