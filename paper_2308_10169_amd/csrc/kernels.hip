@@ -409,6 +409,17 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   }
 }
 
+// Direct global -> LDS loads (no registers on the way): lane i of the wave
+// writes its word at dst_wave + i, dst_wave the same for the whole wave.
+__device__ __forceinline__ void lds_dma16(const void* src, void* dst_wave) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)dst_wave, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma4(const void* src, void* dst_wave) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)dst_wave, 4, 0, 0);
+}
+
 // Obstacle records into the LDS staging area: chunk c of the rectangles when
 // the instance has any, else chunk c of the other polygons' edges (float4
 // words, two loads in flight per thread).
@@ -614,167 +625,151 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   const int N = d.N, W = d.W, D = 2 * W, S = W + 2;
   const int np = min(d.ppb, d.G * N - p0);  // particles in this block
   const int t = threadIdx.x, B = blockDim.x;
+  const float4 ends = pl.ends[inst];  // read before the block's first store
 
   // ---- A0. the block's global reads ------------------------------------------
-  // The block's range starts 16-byte aligned (even particles per block, pools
-  // padded per instance), so the walk goes by float4 groups of elements; only
-  // an instance's last group can be partial.  A thread's first CH groups are
-  // read into registers here, ahead of everything else.
-  float* X = pl.X + d.xo + (int64_t)p0 * D;
-  float* V = pl.V + d.xo + (int64_t)p0 * D;
-  const float* Pp = pl.P + d.xo + (int64_t)p0 * D;
+  // The block's range starts 16-byte aligned (even particles per block) and
+  // the pools are padded to whole float4 groups per instance, so the walk
+  // goes by float4 groups of elements and reads and writes whole groups: an
+  // instance's last group carries up to 3 padding floats, which are never
+  // computed on and are written back as read.  Positions (group gi at LDS
+  // word 4 gi), the first chunk of obstacle records, Tbest and the gbest
+  // rows of the block's groups and the particles' old Pbest fitness go
+  // straight to LDS; a thread's V and P groups and its particle's and group's
+  // hyper-parameters to registers.  All of it is issued before the first
+  // barrier, so that the block waits on memory once.
+  const int lane = t & 63, w0 = t - lane;
+  float4* X4 = reinterpret_cast<float4*>(pl.X + d.xo + (int64_t)p0 * D);
+  float4* V4 = reinterpret_cast<float4*>(pl.V + d.xo + (int64_t)p0 * D);
+  const float4* P4 = reinterpret_cast<const float4*>(pl.P + d.xo + (int64_t)p0 * D);
   const int nel = np * D, ng = (nel + 3) >> 2;
-  float4* X4 = reinterpret_cast<float4*>(X);
-  float4* V4 = reinterpret_cast<float4*>(V);
-  const float4* P4 = reinterpret_cast<const float4*>(Pp);
   float4* B4 = reinterpret_cast<float4*>(s_buf);
   constexpr int CH = 4;
-  float4 xa[CH], va[CH], pa[CH];
-  auto load = [&](int g0) {
+  float4 va[CH], pa[CH];
+  auto load = [&](int g0) {  // g0 = t + multiple of CH * B
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int gi = g0 + c * B, e = 4 * gi;
+      const int gi = g0 + c * B;
       if (gi < ng) {
-        if (e + 4 <= nel) {
-          xa[c] = X4[gi];
-          if (pending) {
-            va[c] = V4[gi];
-            pa[c] = P4[gi];
-          }
-        } else {
-          float* xs = &xa[c].x;
-          float* vs = &va[c].x;
-          float* ps = &pa[c].x;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const bool ok = e + i < nel;
-            xs[i] = ok ? X[e + i] : 0.f;
-            vs[i] = ok && pending ? V[e + i] : 0.f;
-            ps[i] = ok && pending ? Pp[e + i] : 0.f;
-          }
+        lds_dma16(X4 + gi, B4 + (gi - lane));
+        if (pending) {
+          va[c] = V4[gi];
+          pa[c] = P4[gi];
         }
       }
     }
   };
   load(t);
-  float pf_old = 0.f;
-  if (FIT && t < np) pf_old = pl.Pf[d.po + p0 + t];
   if (FIT) {
-    if (d.n_rects > 0)
-      stage_records(pl, d, s_stage, true, 0, min(d.n_rects, pl.stage_floats / 4));
-    else if (d.n_gedges > 0)
-      stage_records(pl, d, s_stage, false, 0, min(d.n_gedges, pl.stage_floats / 8));
+    // first chunk of obstacle records: the rectangles when there are any,
+    // else the other polygons' edges (float4 words)
+    int n4 = 0;
+    const float4* src = pl.rects + d.ro;
+    if (d.n_rects > 0) {
+      n4 = min(d.n_rects, pl.stage_floats / 4);
+    } else if (d.n_gedges > 0) {
+      n4 = 2 * min(d.n_gedges, pl.stage_floats / 8);
+      src = reinterpret_cast<const float4*>(pl.edges + d.geo);
+    }
+    float4* dst = reinterpret_cast<float4*>(s_stage);
+    for (int q = t; q < n4; q += B) lds_dma16(src + q, dst + (q - lane));
+    // old Pbest fitness, parked in the particle's Pbest-flag slot until phase D
+    if (t < np) lds_dma4(pl.Pf + d.po + p0 + t, s_imp + w0);
+  }
+  const int g_lo = p0 / N, g_hi = (p0 + np - 1) / N, ngb = g_hi - g_lo + 1;
+  const bool has_p = pending && t < np, has_g = pending && t < ngb;
+  const int gp = (p0 + t) / N;  // the thread's particle's group
+  float hpv[3], hgv[6];
+  if (pending) {
+    // Tbest row, then the gbest rows g_lo..g_hi (contiguous in the pool)
+    const float* src_t = pl.tbest_pos + d.dpo;
+    const float* src_g = pl.gbest_pos + d.gpo + g_lo * D;
+    for (int q = t; q < D; q += B) lds_dma4(src_t + q, s_gb + (q - lane));
+    for (int q = t; q < ngb * D; q += B) lds_dma4(src_g + q, s_gb + D + (q - lane));
+    const float* hp = pl.hyper + (d.go + (has_p ? gp : 0)) * 6;
+    const float* hg = pl.hyper + (d.go + g_lo + (has_g ? t : 0)) * 6;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) hpv[i] = has_p ? hp[i] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) hgv[i] = has_g ? hg[i] : 0.f;
   }
 
-  // ---- A1. per-particle and per-group constants --------------------------------
+  // ---- A1. per-particle and per-group constants into LDS -------------------------
   // Per particle one Philox call (r1..r3 scaled by the group's C1..C3) and
-  // its group; per group the inertia of Eq.(6) and V_limit / 2; Tbest and the
-  // gbest rows of the block's groups (LDS row 0 and rows 1..).
-  const int g_lo = p0 / N;
+  // its group; per group the inertia of Eq.(6) and V_limit / 2.
   if (pending) {
     const int kk = k < d.T ? k : d.T;
-    const int g_hi = (p0 + np - 1) / N, ngb = g_hi - g_lo + 1;
-    {
-      const float* src_t = pl.tbest_pos + d.dpo;
-      const float* src_g = pl.gbest_pos + d.gpo + g_lo * D;
-      const int n_rows = (ngb + 1) * D;
-      for (int q = t; q < n_rows; q += 2 * B) {
-        const float a = q < D ? src_t[q] : src_g[q - D];
-        float b = 0.f;
-        const int q2 = q + B;
-        if (q2 < n_rows) b = q2 < D ? src_t[q2] : src_g[q2 - D];
-        s_gb[q] = a;
-        if (q2 < n_rows) s_gb[q2] = b;
-      }
-    }
-    for (int g = g_lo + t; g <= g_hi; g += B) {
-      const float* h = pl.hyper + (d.go + g) * 6;
-      float* q = s_wv + 5 * (g - g_lo);
+    auto put_group = [&](int gl, const float* h) {
+      float* q = s_wv + 5 * gl;
       q[0] = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
       q[1] = h[5] * 0.5f;
       q[2] = h[0];
       q[3] = h[1];
       q[4] = h[2];
+    };
+    if (has_p) {
+      const U4 r = philox((uint32_t)(p0 + t), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
+      s_c[4 * t + 0] = hpv[0] * u01(r.v[0]);
+      s_c[4 * t + 1] = hpv[1] * u01(r.v[1]);
+      s_c[4 * t + 2] = hpv[2] * u01(r.v[2]);
+      s_c[4 * t + 3] = __int_as_float(gp - g_lo);
     }
-    if (t < np) {
-      const int j = t;
-      const U4 r = philox((uint32_t)(p0 + j), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
-      const int g = (p0 + j) / N;
-      const float* h = pl.hyper + (d.go + g) * 6;
-      s_c[4 * j + 0] = h[0] * u01(r.v[0]);
-      s_c[4 * j + 1] = h[1] * u01(r.v[1]);
-      s_c[4 * j + 2] = h[2] * u01(r.v[2]);
-      s_c[4 * j + 3] = __int_as_float(g - g_lo);
-    }
+    if (has_g) put_group(t, hgv);
+    for (int gl = t + B; gl < ngb; gl += B) put_group(gl, pl.hyper + (d.go + g_lo + gl) * 6);
   }
   __syncthreads();
 
   // ---- A2. update ---------------------------------------------------------------
   // The element loop walks (particle, coordinate) incrementally, without
-  // divisions; groups past a thread's first CH are read chunk by chunk, every
-  // load of a chunk issued before its first store (the stores could alias
-  // later loads for the compiler).
+  // divisions; groups past a thread's first CH are read chunk by chunk (the
+  // thread's own lanes' words, so no barrier).  After the first barrier
+  // nothing in the block waits on the vector-memory counter, which stores and
+  // loads share: the stores drain while the block goes on.
   {
     const int qB = (4 * B) / D, rB = 4 * B - qB * D;
     int j = (4 * t) / D, dd = 4 * t - j * D;  // particle and coordinate of group's first element
-    for (int g0 = t; g0 < ng; g0 += CH * B) {
-      if (g0 != t) load(g0);
+    auto update = [&](int g0) {
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         const int gi = g0 + c * B, e = 4 * gi;
-        if (gi < ng) {
-          float* xs = &xa[c].x;
-          if (pending) {
-            float* vs = &va[c].x;
-            const float* ps = &pa[c].x;
-            int jj = j, di = dd;
+        if (gi < ng && pending) {
+          float4 xv = B4[gi];
+          float* xs = &xv.x;
+          float* vs = &va[c].x;
+          const float* ps = &pa[c].x;
+          int jj = j, di = dd;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (e + i < nel) {
-                const float4 cf = *reinterpret_cast<const float4*>(s_c + 4 * jj);
-                const int gl = __float_as_int(cf.w);
-                const float* q = s_wv + 5 * gl;
-                const float w = q[0], vlh = q[1];
-                float a1 = cf.x, a2 = cf.y, a3 = cf.z;
-                if (d.rand_per_dim) {  // variant: factors per coordinate
-                  const U4 r = philox((uint32_t)((p0 + jj) * D + di), ctr, d.instance,
-                                      TAG_UPDATE_DIM, d.seed_lo, d.seed_hi);
-                  a1 = q[2] * u01(r.v[0]);
-                  a2 = q[3] * u01(r.v[1]);
-                  a3 = q[4] * u01(r.v[2]);
-                }
-                const float hi = di < W ? d.width : d.height;
-                const float vmax = vlh * hi;
-                const float x = xs[i];
-                const float gx = s_gb[(gl + 1) * D + di], tx = s_gb[di];
-                float v = w * vs[i] + a1 * (ps[i] - x) + a2 * (gx - x) + a3 * (tx - x);
-                v = clampf(v, -vmax, vmax);
-                vs[i] = v;
-                xs[i] = clampf(x + v, 0.f, hi);
+          for (int i = 0; i < 4; ++i) {
+            if (e + i < nel) {
+              const float4 cf = *reinterpret_cast<const float4*>(s_c + 4 * jj);
+              const int gl = __float_as_int(cf.w);
+              const float* q = s_wv + 5 * gl;
+              const float w = q[0], vlh = q[1];
+              float a1 = cf.x, a2 = cf.y, a3 = cf.z;
+              if (d.rand_per_dim) {  // variant: factors per coordinate
+                const U4 r = philox((uint32_t)((p0 + jj) * D + di), ctr, d.instance,
+                                    TAG_UPDATE_DIM, d.seed_lo, d.seed_hi);
+                a1 = q[2] * u01(r.v[0]);
+                a2 = q[3] * u01(r.v[1]);
+                a3 = q[4] * u01(r.v[2]);
               }
-              if (++di == D) {
-                di = 0;
-                ++jj;
-              }
+              const float hi = di < W ? d.width : d.height;
+              const float vmax = vlh * hi;
+              const float x = xs[i];
+              const float gx = s_gb[(gl + 1) * D + di], tx = s_gb[di];
+              float v = w * vs[i] + a1 * (ps[i] - x) + a2 * (gx - x) + a3 * (tx - x);
+              v = clampf(v, -vmax, vmax);
+              vs[i] = v;
+              xs[i] = clampf(x + v, 0.f, hi);
+            }
+            if (++di == D) {
+              di = 0;
+              ++jj;
             }
           }
-          if (e + 4 <= nel) {
-            if (pending) {
-              X4[gi] = xa[c];
-              V4[gi] = va[c];
-            }
-            if (FIT) B4[gi] = xa[c];
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (e + i < nel) {
-                if (pending) {
-                  X[e + i] = xs[i];
-                  V[e + i] = (&va[c].x)[i];
-                }
-                if (FIT) s_buf[e + i] = xs[i];
-              }
-          }
+          B4[gi] = xv;
+          X4[gi] = xv;
+          V4[gi] = va[c];
         }
         dd += rB;
         j += qB;
@@ -783,6 +778,11 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
           ++j;
         }
       }
+    };
+    update(t);
+    for (int g0 = t + CH * B; g0 < ng; g0 += CH * B) {
+      load(g0);
+      update(g0);
     }
   }
   if (!FIT) return;
@@ -798,7 +798,6 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   const bool active = c < C && jt < np;
   const int jc = active ? jt : 0;  // inactive lanes read a valid particle, count nothing
   const int i0 = c * K;           // first point index of the chunk
-  const float4 ends = pl.ends[inst];
   float px[K + 1], py[K + 1];
 #pragma unroll
   for (int s = 0; s <= K; ++s) {
@@ -857,7 +856,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     pl.L[po] = L;
     pl.Q[po] = q;
     const float fc = isfinite(fv) ? fv : INFINITY;
-    const int imp = fc < pf_old;
+    const int imp = fc < reinterpret_cast<const float*>(s_imp)[j];
     if (imp) {
       pl.Pf[po] = fc;
       pl.PL[po] = L;
@@ -903,7 +902,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
 // K = 8 fits five waves per SIMD when capped at 96 registers (a few spilled
 // words outside the crossing loop), which beats four waves at 107.
 template <int K>
-__global__ __launch_bounds__(256, K == 8 ? 5 : 1) void iter_kernel(Pools pl, int flags) {
+__global__ __launch_bounds__(256) void iter_kernel(Pools pl, int flags) {
   iteration<K, true>(pl, flags);
 }
 template <int K>
