@@ -250,7 +250,7 @@ TileLds tile_lds(const std::vector<InstDesc>& desc, int K, int B) {
     const int ppb = tile_ppb(d.W, K, B), D = 2 * d.W;
     const int ngb = std::min(d.G, (ppb - 1) / d.N + 2);  // groups ppb consecutive particles span
     L.pos = std::max(L.pos, ppb * D);
-    L.stage = std::max(L.stage, std::min(kStageFloats, std::max(4 * d.n_rects, 8 * d.n_gedges)));
+    L.stage = std::max(L.stage, std::min(kStageFloats, 8 * d.n_gedges));
     L.gb = std::max(L.gb, (ngb + 1) * D);
     L.ngb = std::max(L.ngb, ngb);
     L.ppb = std::max(L.ppb, ppb);

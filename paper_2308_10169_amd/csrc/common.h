@@ -10,7 +10,7 @@ namespace sepso {
 constexpr int kMaxW = 64;        // interior waypoints per path
 constexpr int kMaxG = 64;        // groups per instance
 constexpr int kHist = 64;        // Auto-Truncation history ring
-constexpr int kStageFloats = 2048;  // obstacle records staged in LDS per pass (512 rects / 256 edges)
+constexpr int kStageFloats = 2048;  // general-polygon edge records staged in LDS per pass (256)
 
 // Learned initializer: 64 x 64 occupancy raster + start/target (4 values)
 // -> 3 x 512 hidden -> 8 groups x 20 waypoints x 2 coordinates.
@@ -100,7 +100,7 @@ struct Pools {
   int32_t n_inst;
   // fused-iteration LDS areas (floats), maxima over the instances
   int32_t pos_floats;    // a block's new positions (ppb * 2W)
-  int32_t stage_floats;  // one chunk of obstacle records
+  int32_t stage_floats;  // one chunk of general-polygon edge records
   int32_t gb_floats;     // Tbest and the gbest rows of a block's groups
   int32_t ngb_max;       // groups a block spans
   int32_t ppb_max;       // particles per block

@@ -409,6 +409,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   }
 }
 
+// Integer key of a float that orders as the values do (-0 just below +0).
+__device__ __forceinline__ int float_key(float x) {
+  const int b = __float_as_int(x);
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+
 // Direct global -> LDS loads (no registers on the way): lane i of the wave
 // writes its word at dst_wave + i, dst_wave the same for the whole wave.
 __device__ __forceinline__ void lds_dma16(const void* src, void* dst_wave) {
@@ -420,15 +426,13 @@ __device__ __forceinline__ void lds_dma4(const void* src, void* dst_wave) {
                                    (__attribute__((address_space(3))) void*)dst_wave, 4, 0, 0);
 }
 
-// Obstacle records into the LDS staging area: chunk c of the rectangles when
-// the instance has any, else chunk c of the other polygons' edges (float4
-// words, two loads in flight per thread).
+// Edge records of the other polygons, from record first on, into the LDS
+// staging area (float4 words, two loads in flight per thread).
 __device__ __forceinline__ void stage_records(const Pools& pl, const InstDesc& d, float* s_stage,
-                                              bool rects, int first, int count) {
+                                              int first, int count) {
   const int t = threadIdx.x, B = blockDim.x;
-  const float4* src = rects ? pl.rects + d.ro + first
-                            : reinterpret_cast<const float4*>(pl.edges + d.geo + first);
-  const int n4 = rects ? count : 2 * count;
+  const float4* src = reinterpret_cast<const float4*>(pl.edges + d.geo + first);
+  const int n4 = 2 * count;
   float4* dst = reinterpret_cast<float4*>(s_stage);
   for (int q = t; q < n4; q += 2 * B) {
     const float4 a = src[q];
@@ -440,9 +444,10 @@ __device__ __forceinline__ void stage_records(const Pools& pl, const InstDesc& d
 }
 
 // Phase C of the fused iteration: crossings of this thread's K segments with
-// every obstacle edge of the instance, records staged through LDS (s_stage:
-// the first chunk was staged before the block's first barrier, later ones
-// are staged here by all threads of the block between barriers).  Crossing
+// every obstacle edge of the instance.  Rectangles are read through the
+// scalar cache; the other polygons' edge records are staged through LDS
+// (s_stage: the first chunk was staged before the block's first barrier,
+// later ones are staged here by all threads of the block between barriers).  Crossing
 // words: bit K-1-s set when segment s properly crosses the edge (never for
 // masked slots); ct counts them.
 template <int K>
@@ -474,51 +479,51 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
     by0 = fminf(by0, __shfl_xor(by0, m));
     by1 = fmaxf(by1, __shfl_xor(by1, m));
   }
-  // C1. axis-aligned rectangles.  Edge sides are exact sign tests of one
+  // C1. axis-aligned rectangles, read through the scalar cache: a record is
+  // the same for every lane, so it stays in scalar registers and the culling
+  // test runs on the scalar unit, on integer keys that order floats as their
+  // values do (the key order puts -0 below +0, so it never culls more than
+  // the float comparison would).  Edge sides are exact sign tests of one
   // coordinate difference; corner sides: (x0,y0) by two FMAs, each other
   // corner from a neighbour by one FMA along the rectangle's side (three
   // roundings on the far corner stay well inside the degenerate band).
-  const float4* s_rect = reinterpret_cast<const float4*>(s_stage);
-  const int rchunk = pl.stage_floats / 4;
-  for (int r0 = 0; r0 < d.n_rects; r0 += rchunk) {
-    const int nr = d.n_rects - r0 < rchunk ? d.n_rects - r0 : rchunk;
-    if (r0 > 0) {
-      __syncthreads();
-      stage_records(pl, d, s_stage, true, r0, nr);
-      __syncthreads();
-    }
-    if (active) {
-      float4 bn = s_rect[0];
-      for (int e = 0; e < nr; ++e) {
-        const float4 b = bn;  // x0, y0, x1, y1
-        bn = s_rect[e + 1 < nr ? e + 1 : e];  // next rectangle's LDS read overlaps this one
-        if (b.z <= bx0 || b.x >= bx1 || b.w <= by0 || b.y >= by1) continue;
-        const float w = b.z - b.x, h = b.w - b.y;
-        uint32_t w00 = 0, w10 = 0, w11 = 0, w01 = 0;
+  {
+    const int kx0 = __builtin_amdgcn_readfirstlane(float_key(bx0));
+    const int kx1 = __builtin_amdgcn_readfirstlane(float_key(bx1));
+    const int ky0 = __builtin_amdgcn_readfirstlane(float_key(by0));
+    const int ky1 = __builtin_amdgcn_readfirstlane(float_key(by1));
+    typedef const __attribute__((address_space(4))) float cfloat;
+    cfloat* rc = (cfloat*)(pl.rects + d.ro);
+    for (int e = 0; e < d.n_rects; ++e) {
+      const float4 b = make_float4(rc[4 * e], rc[4 * e + 1], rc[4 * e + 2], rc[4 * e + 3]);  // x0, y0, x1, y1
+      if (float_key(b.z) <= kx0 || float_key(b.x) >= kx1 || float_key(b.w) <= ky0 ||
+          float_key(b.y) >= ky1)
+        continue;
+      const float w = b.z - b.x, h = b.w - b.y;
+      uint32_t w00 = 0, w10 = 0, w11 = 0, w01 = 0;
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-          const float o00 = fmaf(dx[s], b.y, fmaf(ndy[s], b.x, nc[s]));
-          const float o10 = fmaf(ndy[s], w, o00);
-          const float o01 = fmaf(dx[s], h, o00);
-          const float o11 = fmaf(dx[s], h, o10);
-          w00 = __builtin_amdgcn_alignbit(w00, __float_as_uint(o00), 31);
-          w10 = __builtin_amdgcn_alignbit(w10, __float_as_uint(o10), 31);
-          w11 = __builtin_amdgcn_alignbit(w11, __float_as_uint(o11), 31);
-          w01 = __builtin_amdgcn_alignbit(w01, __float_as_uint(o01), 31);
-        }
-        uint32_t eb = 0, eR = 0, eT = 0, eL = 0;
-#pragma unroll
-        for (int s = 0; s <= K; ++s) {
-          eb = __builtin_amdgcn_alignbit(eb, __float_as_uint(py[s] - b.y), 31);
-          eR = __builtin_amdgcn_alignbit(eR, __float_as_uint(px[s] - b.z), 31);
-          eT = __builtin_amdgcn_alignbit(eT, __float_as_uint(py[s] - b.w), 31);
-          eL = __builtin_amdgcn_alignbit(eL, __float_as_uint(px[s] - b.x), 31);
-        }
-        count((w00 ^ w10) & (eb ^ (eb >> 1)));  // bottom
-        count((w10 ^ w11) & (eR ^ (eR >> 1)));  // right
-        count((w11 ^ w01) & (eT ^ (eT >> 1)));  // top
-        count((w01 ^ w00) & (eL ^ (eL >> 1)));  // left
+      for (int s = 0; s < K; ++s) {
+        const float o00 = fmaf(dx[s], b.y, fmaf(ndy[s], b.x, nc[s]));
+        const float o10 = fmaf(ndy[s], w, o00);
+        const float o01 = fmaf(dx[s], h, o00);
+        const float o11 = fmaf(dx[s], h, o10);
+        w00 = __builtin_amdgcn_alignbit(w00, __float_as_uint(o00), 31);
+        w10 = __builtin_amdgcn_alignbit(w10, __float_as_uint(o10), 31);
+        w11 = __builtin_amdgcn_alignbit(w11, __float_as_uint(o11), 31);
+        w01 = __builtin_amdgcn_alignbit(w01, __float_as_uint(o01), 31);
       }
+      uint32_t eb = 0, eR = 0, eT = 0, eL = 0;
+#pragma unroll
+      for (int s = 0; s <= K; ++s) {
+        eb = __builtin_amdgcn_alignbit(eb, __float_as_uint(py[s] - b.y), 31);
+        eR = __builtin_amdgcn_alignbit(eR, __float_as_uint(px[s] - b.z), 31);
+        eT = __builtin_amdgcn_alignbit(eT, __float_as_uint(py[s] - b.w), 31);
+        eL = __builtin_amdgcn_alignbit(eL, __float_as_uint(px[s] - b.x), 31);
+      }
+      count((w00 ^ w10) & (eb ^ (eb >> 1)));  // bottom
+      count((w10 ^ w11) & (eR ^ (eR >> 1)));  // right
+      count((w11 ^ w01) & (eT ^ (eT >> 1)));  // top
+      count((w01 ^ w00) & (eL ^ (eL >> 1)));  // left
     }
   }
   // C2. other polygons, edge by edge.  An edge outside the wave's box is
@@ -531,9 +536,9 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
   const int chunk = pl.stage_floats / 8;  // edge records per LDS pass
   for (int e0 = 0; e0 < d.n_gedges; e0 += chunk) {
     const int ne = d.n_gedges - e0 < chunk ? d.n_gedges - e0 : chunk;
-    if (e0 > 0 || d.n_rects > 0) {
+    if (e0 > 0) {
       __syncthreads();
-      stage_records(pl, d, s_stage, false, e0, ne);
+      stage_records(pl, d, s_stage, e0, ne);
       __syncthreads();
     }
     if (active) {
@@ -661,16 +666,9 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   };
   load(t);
   if (FIT) {
-    // first chunk of obstacle records: the rectangles when there are any,
-    // else the other polygons' edges (float4 words)
-    int n4 = 0;
-    const float4* src = pl.rects + d.ro;
-    if (d.n_rects > 0) {
-      n4 = min(d.n_rects, pl.stage_floats / 4);
-    } else if (d.n_gedges > 0) {
-      n4 = 2 * min(d.n_gedges, pl.stage_floats / 8);
-      src = reinterpret_cast<const float4*>(pl.edges + d.geo);
-    }
+    // first chunk of the other polygons' edge records (float4 words)
+    const int n4 = 2 * min(d.n_gedges, pl.stage_floats / 8);
+    const float4* src = reinterpret_cast<const float4*>(pl.edges + d.geo);
     float4* dst = reinterpret_cast<float4*>(s_stage);
     for (int q = t; q < n4; q += B) lds_dma16(src + q, dst + (q - lane));
     // old Pbest fitness, parked in the particle's Pbest-flag slot until phase D
