@@ -51,8 +51,13 @@ def counter_record(kernel, tune):
         return None
     if rec is None or sha != cur or rec.get("kernel") != kernel:
         return None
-    return dict(hbm_bytes=float(rec["hbm_bytes_per_launch"]),
-                valu_insts=float(rec["valu_insts_per_launch"]))
+    out = dict(hbm_bytes=float(rec["hbm_bytes_per_launch"]),
+               valu_insts=float(rec["valu_insts_per_launch"]))
+    if "valu_busy" in rec:
+        out["valu_issue_ratio"] = float(rec["valu_busy"])
+    if "fp32_flop_per_launch" in rec:
+        out["fp32_flop"] = float(rec["fp32_flop_per_launch"])
+    return out
 
 
 def executed_fraction(bp, specs, sws, tune, sample):
@@ -212,6 +217,14 @@ def main():
         lanes = rec["valu_insts"] * 64 / (kern_ms * 1e-3)
         roof["valu_lane_ops_per_s"] = lanes
         roof["valu_util"] = lanes / (PEAK_FP32 / 2)
+        # VALU issue against one wave64 instruction per SIMD every 4 cycles
+        # (the ceiling without packed FP32), from the counter run's own cycles
+        if "valu_issue_ratio" in rec:
+            roof["valu_issue_ratio"] = rec["valu_issue_ratio"]
+        # FP32 FLOP the counters saw (64 per ADD/MUL, 128 per FMA wave instruction)
+        if "fp32_flop" in rec:
+            roof["counter_tflops"] = rec["fp32_flop"] / (kern_ms * 1e-3) / 1e12
+            roof["counter_frac"] = rec["fp32_flop"] / (kern_ms * 1e-3) / PEAK_FP32
 
     # paper-shaped single instance (366 map, 30 rectangles, 8 x 170, W = 20)
     spec2 = I.dynamic_map(0)
