@@ -144,16 +144,43 @@ def test_adversarial_degenerate_paths(sp):
     pl.close()
 
 
+@pytest.mark.parametrize("tune", [(8, 256), (4, 256)])
+def test_full_batch_sampled(sp, tune):
+    # The benchmark workload at full size (1024 uneven dynamic instances) in the
+    # launch configuration the benchmark times: its tile, after 20 iterations
+    # (a converging swarm, wave culling active).  One more injected iteration is
+    # checked against the oracle on 16 instances spread over the batch, every
+    # particle of each: crossings, fitness, bests, update.
+    specs, sws = [], []
+    for i in range(1024):
+        m, shape = I.batch_instance(i, 0)
+        sws.append(I.dynamic_swarm(m.scale, seed=0, instance=i, **shape))
+        specs.append(m)
+    bp = sp.BatchPlanner(specs, sws, tune=tune)
+    bp.profile_step(20)
+    sample = list(range(0, 1024, 64))
+    st0 = {i: bp.get_state(i) for i in sample}
+    bp.profile_step(1)
+    stats = {}
+    for i in sample:
+        o = orc.Swarm(sws[i], specs[i].width, specs[i].height)
+        check_step(o, orc.Map(specs[i]), st0[i], bp.get_state(i), specs[i].scale, stats)
+    bp.close()
+    print("parity stats", stats)
+    assert stats["paths"] == sum(sws[i].groups * sws[i].particles for i in sample)
+
+
 def test_large_stress_sampled(sp):
-    # Stress scene (512 map, 2400 edges, W = 64) at a reduced particle count;
-    # fitness of a sample of particles against the oracle.
+    # Stress scene at full size (512 map, 500 rectangles + 100 quads = 2400
+    # edges, 8 x 4096 particles, W = 64); fitness of a sample of particles
+    # against the oracle.
     spec = I.stress_map(0)
-    sw = I.SwarmSpec(8, 256, 64, 200, I.HYPER8PATH, alpha=30.0, beta=4, seed=4)
+    sw = I.SwarmSpec(8, 4096, 64, 200, I.HYPER8PATH, alpha=30.0, beta=4, seed=4)
     pl = sp.Planner(spec, sw)
     st0 = pl.get_state()
     pl.step(1)
     st1 = pl.get_state()
-    idx = np.random.default_rng(1).choice(8 * 256, 96, replace=False)
+    idx = np.random.default_rng(1).choice(8 * 4096, 96, replace=False)
     sub = lambda st: dict(X=st["X"].reshape(-1, 128)[idx][None], Q=st["Q"].reshape(-1)[idx][None],
                           L=st["L"].reshape(-1)[idx][None], f=st["f"].reshape(-1)[idx][None])
     check_fitness(orc.Map(spec), sub(st0), sub(st1), 64, sw.alpha, sw.beta)
