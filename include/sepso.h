@@ -113,7 +113,10 @@ typedef struct sepso_state {
   int32_t frame;       /* frames planned so far */
 } sepso_state;
 
-/* Tile configuration of the fused iteration kernel. */
+/* Tile configuration of the fused iteration kernel.  Valid for a batch when
+ * K <= 2*(smallest waypoint count + 2), K * block_threads <= 4096 and the
+ * kernel's LDS for the batch's shapes stays within 64 KiB (otherwise
+ * SEPSO_E_ARG). */
 typedef struct sepso_tune {
   int32_t seg_per_thread; /* K: path segments per thread, one of 4, 8, 12, 16, 24 */
   int32_t block_threads;  /* 64, 128, 256 */
@@ -185,8 +188,21 @@ sepso_status sepso_batch_plan(sepso_batch* b, int32_t n_frames, sepso_frame_resu
 sepso_status sepso_batch_get_state(sepso_batch* b, int32_t i, sepso_state* st);
 sepso_status sepso_batch_profile_step(sepso_batch* b, int32_t n, float* avg_ms);
 /* Choose seg_per_thread / block_threads by timing candidates on this batch;
- * the winner is applied to the batch and written to *best (may be NULL). */
+ * the winner is applied to the batch and written to *best (may be NULL).
+ * Afterwards the batch is as new: control blocks (random-stream positions,
+ * frame index, previous plans) reset and the frame-0 swarm initialised.
+ * Synchronous. */
 sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best);
+/* sepso_autotune with a persistent cache: cache_path is a text file of lines
+ * "<key> <K> <block_threads>", the key a 64-bit hash (16 hex digits) of the
+ * device architecture name and every instance's groups, particles,
+ * waypoints, rectangles and other-polygon edges.  When the file holds this
+ * batch's key with a valid tile, that tile is applied without timing
+ * (and the batch is reset as after sepso_autotune);
+ * otherwise the batch is autotuned and a line is appended.  A missing file is
+ * created; a file that cannot be read or written gives SEPSO_E_ARG, and an
+ * unreadable line is skipped.  Synchronous.  best may be NULL. */
+sepso_status sepso_autotune_cached(sepso_batch* b, const char* cache_path, sepso_tune* best);
 /* Apply a tile configuration to every instance (same bounds as sepso_set_tune,
  * with the smallest waypoint count of the batch). */
 sepso_status sepso_batch_set_tune(sepso_batch* b, const sepso_tune* tune);

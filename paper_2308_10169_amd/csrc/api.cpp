@@ -909,6 +909,26 @@ sepso_status sepso_batch_work(sepso_batch* b, double* tests, double* elems) {
   return SEPSO_OK;
 }
 
+namespace {
+
+// Back to the state of a new batch: control blocks as created (random-stream
+// counters, frame index, previous plan and learned-start flags zero), then the
+// frame-0 initial swarm.  Synchronous.
+sepso_status restart(sepso_batch* b) {
+  std::vector<InstCtl> ctl(b->n);
+  std::memset(ctl.data(), 0, sizeof(InstCtl) * b->n);
+  for (InstCtl& c : ctl) c.tb_f = INFINITY;
+  HIPCHK(b, hipMemcpyAsync(b->pl.ctl, ctl.data(), sizeof(InstCtl) * b->n, hipMemcpyHostToDevice,
+                           b->stream));
+  launch_init(b->pl, init_blocks(b), 0, 0, b->stream);
+  LAUNCHCHK(b, "init launch");
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  b->frames_done = 0;
+  return SEPSO_OK;
+}
+
+}  // namespace
+
 sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
   sepso_status st = usable(b);
   if (st != SEPSO_OK) return st;
@@ -934,11 +954,76 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
     }
   b->tune = win;
   st = upload_tiles(b);
+  if (st == SEPSO_OK) st = restart(b);
   if (st != SEPSO_OK) return st;
-  launch_init(b->pl, init_blocks(b), 0, 0, b->stream);
-  LAUNCHCHK(b, "init launch");
-  HIPCHK(b, hipStreamSynchronize(b->stream));
-  b->frames_done = 0;
+  if (best) *best = win;
+  return SEPSO_OK;
+}
+
+namespace {
+
+// Key of a batch for the tune cache: FNV-1a over the device architecture name
+// and the shape fields of every instance that decide the tile's cost.
+uint64_t tune_key(const sepso_batch* b) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  };
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    mix(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+  mix(&b->n, sizeof(b->n));
+  for (const InstDesc& d : b->desc) {
+    const int32_t f[5] = {d.G, d.N, d.W, d.n_rects, d.n_gedges};
+    mix(f, sizeof(f));
+  }
+  return h;
+}
+
+}  // namespace
+
+sepso_status sepso_autotune_cached(sepso_batch* b, const char* cache_path, sepso_tune* best) {
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (!cache_path) return fail(SEPSO_E_ARG, "cache_path is NULL");
+  const uint64_t key = tune_key(b);
+  if (FILE* f = fopen(cache_path, "r")) {
+    char line[256];
+    bool hit = false;
+    sepso_tune t{};
+    while (!hit && fgets(line, sizeof line, f)) {
+      unsigned long long k = 0;
+      int K = 0, B = 0;
+      if (sscanf(line, "%llx %d %d", &k, &K, &B) == 3 && k == key && tune_ok(K, B, b->desc)) {
+        t = sepso_tune{K, B};
+        hit = true;
+      }
+    }
+    const bool bad = ferror(f) != 0;
+    fclose(f);
+    if (bad) return fail(SEPSO_E_ARG, "tune cache %s: read error", cache_path);
+    if (hit) {
+      b->tune = t;
+      st = upload_tiles(b);
+      if (st == SEPSO_OK) st = restart(b);
+      if (st != SEPSO_OK) return st;
+      if (best) *best = t;
+      return SEPSO_OK;
+    }
+  }
+  sepso_tune win{};
+  st = sepso_autotune(b, &win);
+  if (st != SEPSO_OK) return st;
+  FILE* f = fopen(cache_path, "a");
+  if (!f) return fail(SEPSO_E_ARG, "tune cache %s: cannot open for writing", cache_path);
+  const bool ok = fprintf(f, "%016llx %d %d\n", (unsigned long long)key, win.seg_per_thread,
+                          win.block_threads) > 0;
+  if (fclose(f) != 0 || !ok) return fail(SEPSO_E_ARG, "tune cache %s: write failed", cache_path);
   if (best) *best = win;
   return SEPSO_OK;
 }

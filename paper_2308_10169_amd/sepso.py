@@ -125,6 +125,7 @@ def _load():
     L.sepso_batch_get_state.argtypes = [vp, C.c_int32, C.POINTER(CState)]
     L.sepso_batch_profile_step.argtypes = [vp, C.c_int32, fp]
     L.sepso_autotune.argtypes = [vp, C.POINTER(CTune)]
+    L.sepso_autotune_cached.argtypes = [vp, C.c_char_p, C.POINTER(CTune)]
     L.sepso_batch_work.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.sepso_batch_history.argtypes = [vp, fp]
     L.sepso_batch_set_tune.argtypes = [vp, C.POINTER(CTune)]
@@ -380,9 +381,14 @@ class BatchPlanner:
         _check(_lib.sepso_batch_profile_step(self.h, int(n), C.byref(ms)))
         return ms.value
 
-    def autotune(self):
+    def autotune(self, cache_path=None):
+        """Time the tile candidates (or take this batch's entry of the tune
+        cache file cache_path, appending one when it has none)."""
         t = CTune()
-        _check(_lib.sepso_autotune(self.h, C.byref(t)))
+        if cache_path is None:
+            _check(_lib.sepso_autotune(self.h, C.byref(t)))
+        else:
+            _check(_lib.sepso_autotune_cached(self.h, os.fsencode(cache_path), C.byref(t)))
         return (t.seg_per_thread, t.block_threads)
 
     def work(self):

@@ -165,3 +165,33 @@ def test_batch_paths_score_as_reported(sp):
             assert chk["Q"][0] == r["crossings"][0, i]
             assert abs(chk["f"][0] - r["cost"][0, i]) <= REL * max(chk["f"][0], 1.0)
     bp.close()
+
+
+def test_tune_cache(sp, tmp_path):
+    # The first call times the candidates and appends this batch's line; a
+    # second batch of the same shape takes the tile from the file without
+    # timing and plans exactly as the autotuned one (both start again at
+    # frame 0); a batch of another shape appends its own line; unreadable
+    # lines are skipped.
+    specs, sws = _ragged(5)
+    path = tmp_path / "tune.txt"
+    path.write_text("not a tune line\n")
+    a = sp.BatchPlanner(specs, sws)
+    ta = a.autotune(str(path))
+    lines = path.read_text().split("\n")[1:-1]
+    assert len(lines) == 1
+    key, K, B = lines[0].split()
+    assert len(key) == 16 and (int(K), int(B)) == ta
+    ra = a.plan(2, want_paths=True)
+    a.close()
+    b = sp.BatchPlanner(specs, sws)
+    assert b.autotune(str(path)) == ta
+    assert len(path.read_text().split("\n")[1:-1]) == 1
+    rb = b.plan(2, want_paths=True)
+    b.close()
+    assert np.array_equal(ra["cost"], rb["cost"]) and np.array_equal(ra["iters"], rb["iters"])
+    c = sp.BatchPlanner(specs[:3], sws[:3])
+    c.autotune(str(path))
+    c.close()
+    lines = path.read_text().split("\n")[1:-1]
+    assert len(lines) == 2 and lines[0].split()[0] != lines[1].split()[0]
