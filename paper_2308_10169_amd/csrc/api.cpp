@@ -76,7 +76,8 @@ sepso_status check_swarm(const sepso_swarm* s, int idx) {
     if (s->hyper[6 * g + 5] < 0.f) return fail(SEPSO_E_ARG, "swarm[%d]: V_limit < 0", idx);
   if (s->hsef_hyper)
     for (int j = 0; j < 6 * s->groups; ++j)
-      if (!finite(s->hsef_hyper[j])) return fail(SEPSO_E_ARG, "swarm[%d]: hsef_hyper", idx);
+      if (!finite(s->hsef_hyper[j]) || (j % 6 == 5 && s->hsef_hyper[j] < 0.f))
+        return fail(SEPSO_E_ARG, "swarm[%d]: hsef_hyper not finite or V_limit < 0", idx);
   if (!(finite(s->alpha) && s->alpha >= 0.f)) return fail(SEPSO_E_ARG, "swarm[%d]: alpha", idx);
   if (s->beta < 1 || s->beta > 16) return fail(SEPSO_E_ARG, "swarm[%d]: beta in [1,16]", idx);
   if (!(finite(s->pi_gamma) && s->pi_gamma >= 0.f && s->pi_gamma <= 1.f))
@@ -782,7 +783,8 @@ sepso_status sepso_set_state(sepso_ctx* ctx, const sepso_state* st) {
     }
   if (st->hyper)
     for (int j = 0; j < 6 * d.G; ++j)
-      if (!finite(st->hyper[j])) return fail(SEPSO_E_ARG, "set_state: hyper");
+      if (!finite(st->hyper[j]) || (j % 6 == 5 && st->hyper[j] < 0.f))
+        return fail(SEPSO_E_ARG, "set_state: hyper not finite or V_limit < 0");
   auto h2d = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     if (!src || !bytes) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream);

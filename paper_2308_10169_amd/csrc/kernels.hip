@@ -608,17 +608,18 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
 template <int K, bool FIT>
 __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   // dynamic LDS: positions | obstacle records | Tbest and the gbest rows of
-  // the block's groups | r1..r3 and group per particle | per group w,
-  // V_limit / 2, C1..C3 | Pbest flags | per-thread crossings and lengths
+  // the block's groups | an 8-word record per particle (Pbest flags in phase
+  // D) | per group w, V_limit / 2, C1..C3 | per-thread crossings (the old
+  // Pbest fitness of particle t until then) and lengths
   extern __shared__ __attribute__((aligned(16))) float s_dyn[];
   float* s_buf = s_dyn;
   float* s_stage = s_buf + pl.pos_floats;
   float* s_gb = s_stage + pl.stage_floats;
   float* s_c = s_gb + pl.gb_floats;
-  float* s_wv = s_c + 4 * pl.ppb_max;
-  int* s_imp = reinterpret_cast<int*>(s_wv + 5 * pl.ngb_max);
-  int* s_q = s_imp + pl.ppb_max;
+  float* s_wv = s_c + 8 * pl.ppb_max;
+  int* s_q = reinterpret_cast<int*>(s_wv + 5 * pl.ngb_max);
   float* s_l = reinterpret_cast<float*>(s_q + blockDim.x);
+  int* s_imp = reinterpret_cast<int*>(s_c);  // phase D: the records are dead by then
 
   const int2 bt = pl.blk_tiles[blockIdx.x];
   const int inst = bt.x, p0 = bt.y;
@@ -671,13 +672,13 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     const float4* src = reinterpret_cast<const float4*>(pl.edges + d.geo);
     float4* dst = reinterpret_cast<float4*>(s_stage);
     for (int q = t; q < n4; q += B) lds_dma16(src + q, dst + (q - lane));
-    // old Pbest fitness, parked in the particle's Pbest-flag slot until phase D
-    if (t < np) lds_dma4(pl.Pf + d.po + p0 + t, s_imp + w0);
+    // old Pbest fitness of particle t, parked in thread t's crossing slot
+    if (t < np) lds_dma4(pl.Pf + d.po + p0 + t, s_q + w0);
   }
   const int g_lo = p0 / N, g_hi = (p0 + np - 1) / N, ngb = g_hi - g_lo + 1;
   const bool has_p = pending && t < np, has_g = pending && t < ngb;
   const int gp = (p0 + t) / N;  // the thread's particle's group
-  float hpv[3], hgv[6];
+  float hpv[6], hgv[6];
   if (pending) {
     // Tbest row, then the gbest rows g_lo..g_hi (contiguous in the pool)
     const float* src_t = pl.tbest_pos + d.dpo;
@@ -687,19 +688,22 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     const float* hp = pl.hyper + (d.go + (has_p ? gp : 0)) * 6;
     const float* hg = pl.hyper + (d.go + g_lo + (has_g ? t : 0)) * 6;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) hpv[i] = has_p ? hp[i] : 0.f;
+    for (int i = 0; i < 6; ++i) hpv[i] = has_p ? hp[i] : 0.f;
 #pragma unroll
     for (int i = 0; i < 6; ++i) hgv[i] = has_g ? hg[i] : 0.f;
   }
 
   // ---- A1. per-particle and per-group constants into LDS -------------------------
-  // Per particle one Philox call (r1..r3 scaled by the group's C1..C3) and
-  // its group; per group the inertia of Eq.(6) and V_limit / 2.
+  // Per particle an 8-word record: one Philox call's r1..r3 scaled by the
+  // group's C1..C3, the group's inertia of Eq.(6) and V_limit / 2, the LDS
+  // offset of its gbest row and its group.  Per group the same inertia and
+  // V_limit / 2 and C1..C3 (read by the per-coordinate variant).
   if (pending) {
     const int kk = k < d.T ? k : d.T;
+    auto inertia = [&](const float* h) { return h[3] - (h[3] - h[4]) / (float)d.T * (float)kk; };
     auto put_group = [&](int gl, const float* h) {
       float* q = s_wv + 5 * gl;
-      q[0] = h[3] - (h[3] - h[4]) / (float)d.T * (float)kk;
+      q[0] = inertia(h);
       q[1] = h[5] * 0.5f;
       q[2] = h[0];
       q[3] = h[1];
@@ -707,10 +711,11 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     };
     if (has_p) {
       const U4 r = philox((uint32_t)(p0 + t), ctr, d.instance, TAG_UPDATE, d.seed_lo, d.seed_hi);
-      s_c[4 * t + 0] = hpv[0] * u01(r.v[0]);
-      s_c[4 * t + 1] = hpv[1] * u01(r.v[1]);
-      s_c[4 * t + 2] = hpv[2] * u01(r.v[2]);
-      s_c[4 * t + 3] = __int_as_float(gp - g_lo);
+      const int gl = gp - g_lo;
+      float4* rec = reinterpret_cast<float4*>(s_c + 8 * t);
+      rec[0] = make_float4(hpv[0] * u01(r.v[0]), hpv[1] * u01(r.v[1]), hpv[2] * u01(r.v[2]),
+                           inertia(hpv));
+      rec[1] = make_float4(hpv[5] * 0.5f, __int_as_float((gl + 1) * D), __int_as_float(gl), 0.f);
     }
     if (has_g) put_group(t, hgv);
     for (int gl = t + B; gl < ngb; gl += B) put_group(gl, pl.hyper + (d.go + g_lo + gl) * 6);
@@ -739,12 +744,12 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (e + i < nel) {
-              const float4 cf = *reinterpret_cast<const float4*>(s_c + 4 * jj);
-              const int gl = __float_as_int(cf.w);
-              const float* q = s_wv + 5 * gl;
-              const float w = q[0], vlh = q[1];
-              float a1 = cf.x, a2 = cf.y, a3 = cf.z;
+              const float4 c0 = *reinterpret_cast<const float4*>(s_c + 8 * jj);
+              const float4 c1 = *reinterpret_cast<const float4*>(s_c + 8 * jj + 4);
+              const float w = c0.w, vlh = c1.x;
+              float a1 = c0.x, a2 = c0.y, a3 = c0.z;
               if (d.rand_per_dim) {  // variant: factors per coordinate
+                const float* q = s_wv + 5 * __float_as_int(c1.z);
                 const U4 r = philox((uint32_t)((p0 + jj) * D + di), ctr, d.instance,
                                     TAG_UPDATE_DIM, d.seed_lo, d.seed_hi);
                 a1 = q[2] * u01(r.v[0]);
@@ -754,7 +759,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
               const float hi = di < W ? d.width : d.height;
               const float vmax = vlh * hi;
               const float x = xs[i];
-              const float gx = s_gb[(gl + 1) * D + di], tx = s_gb[di];
+              const float gx = s_gb[__float_as_int(c1.y) + di], tx = s_gb[di];
               float v = w * vs[i] + a1 * (ps[i] - x) + a2 * (gx - x) + a3 * (tx - x);
               v = clampf(v, -vmax, vmax);
               vs[i] = v;
@@ -834,6 +839,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   crossings<K>(pl, d, s_stage, active, px, py, dx, ndy, nc, ct);
 
   // ---- D. per-particle fitness and Pbest -------------------------------------
+  const float pf_old = reinterpret_cast<const float*>(s_q)[t];  // before the slot is reused
   s_q[t] = ct;
   s_l[t] = len_sum;
   __syncthreads();
@@ -854,7 +860,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     pl.L[po] = L;
     pl.Q[po] = q;
     const float fc = isfinite(fv) ? fv : INFINITY;
-    const int imp = fc < reinterpret_cast<const float*>(s_imp)[j];
+    const int imp = fc < pf_old;
     if (imp) {
       pl.Pf[po] = fc;
       pl.PL[po] = L;
@@ -919,7 +925,7 @@ void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev
 
 size_t iter_lds_words(int pos_floats, int stage_floats, int gb_floats, int ngb_max, int ppb_max,
                       int threads) {
-  return (size_t)pos_floats + stage_floats + gb_floats + 5 * (size_t)ppb_max + 5 * (size_t)ngb_max +
+  return (size_t)pos_floats + stage_floats + gb_floats + 8 * (size_t)ppb_max + 5 * (size_t)ngb_max +
          2 * (size_t)threads;
 }
 

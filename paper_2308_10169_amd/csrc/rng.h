@@ -38,8 +38,10 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 // 24-bit uniform in [0,1), exact in FP32.
 __device__ __forceinline__ float u01(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }
 
+// x clamped to [lo, hi] for lo <= hi and x not NaN: the median of the three,
+// one v_med3_f32 (the same value as comparing and selecting).
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {
-  return x < lo ? lo : (x > hi ? hi : x);
+  return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
 
 }  // namespace sepso
