@@ -801,20 +801,22 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   const bool active = c < C && jt < np;
   const int jc = active ? jt : 0;  // inactive lanes read a valid particle, count nothing
   const int i0 = c * K;           // first point index of the chunk
+  // Point i0+s of the path (clamped to the target): start, waypoint, or
+  // target.  Waypoints are read at a clamped index, without branches; only
+  // point 0 of chunk 0 can be the start.
   float px[K + 1], py[K + 1];
+  const float* sx = s_buf + jc * D;
 #pragma unroll
   for (int s = 0; s <= K; ++s) {
-    const int idx = i0 + s < S - 1 ? i0 + s : S - 1;
-    float x, y;
-    if (idx == 0) {
-      x = ends.x;
-      y = ends.y;
-    } else if (idx == S - 1) {
-      x = ends.z;
-      y = ends.w;
-    } else {
-      x = s_buf[jc * D + idx - 1];
-      y = s_buf[jc * D + W + idx - 1];
+    const int idx = min(i0 + s, S - 1);
+    const int wi = min(max(idx - 1, 0), W - 1);
+    const bool tgt = idx == S - 1;
+    float x = sx[wi], y = sx[W + wi];
+    x = tgt ? ends.z : x;
+    y = tgt ? ends.w : y;
+    if (s == 0) {
+      x = idx == 0 ? ends.x : x;
+      y = idx == 0 ? ends.y : y;
     }
     px[s] = x;
     py[s] = y;
@@ -831,7 +833,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     dx[s] = seg ? ddx : 0.f;
     ndy[s] = seg ? -ddy : 0.f;
     nc[s] = seg ? fmaf(ddy, px[s], -(ddx * py[s])) : 0.f;
-    if (seg) len_sum += sqrtf(ddx * ddx + ddy * ddy);
+    if (seg) len_sum += __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy);  // v_sqrt_f32, 1 ulp
   }
 
   // ---- C. crossings ----------------------------------------------------------
