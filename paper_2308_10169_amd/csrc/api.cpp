@@ -347,7 +347,7 @@ sepso_status upload_tiles(sepso_batch* b) {
   b->tune_gen += 1;
   for (int m = 0; m < 2; ++m)
     if (b->graph[m]) {
-      hipGraphExecDestroy(b->graph[m]);
+      (void)hipGraphExecDestroy(b->graph[m]);  // retired; re-captured on next use
       b->graph[m] = nullptr;
     }
   return SEPSO_OK;
@@ -356,12 +356,13 @@ sepso_status upload_tiles(sepso_batch* b) {
 void destroy_batch(sepso_batch* b) {
   if (!b) return;
   for (int m = 0; m < 2; ++m)
-    if (b->graph[m]) hipGraphExecDestroy(b->graph[m]);
-  if (b->ev0) hipEventDestroy(b->ev0);
-  if (b->ev1) hipEventDestroy(b->ev1);
-  if (b->h_ctl) hipHostFree(b->h_ctl);
-  if (b->h_paths) hipHostFree(b->h_paths);
-  if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    if (b->graph[m]) (void)hipGraphExecDestroy(b->graph[m]);
+  // teardown is best effort: a failure here leaves nothing to recover
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+  if (b->h_paths) (void)hipHostFree(b->h_paths);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
 
@@ -544,19 +545,26 @@ sepso_status usable(sepso_batch* b) {
 
 int init_blocks(sepso_batch* b) { return (int)b->lay.initBlocks; }
 
-// Enqueue one whole frame of every instance.
-void enqueue_frame(sepso_batch* b, bool move) {
+// Enqueue one whole frame of every instance; the first error of the
+// enqueued work (launch errors included).
+hipError_t enqueue_frame(sepso_batch* b, bool move) {
   if (move) launch_geom(b->pl, b->n, 1, b->stream);
   if (b->lin) lin_enqueue_proposals(b->lin, b);
   launch_init(b->pl, init_blocks(b), -1, 1, b->stream);
   int tmax = 0;
   for (auto& d : b->desc) tmax = std::max(tmax, d.T);
-  for (int k = 0; k < tmax; ++k)
-    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
-                STEP_FIT | STEP_FRAME, b->stream);
-  hipMemcpyAsync(b->h_ctl, b->pl.ctl, sizeof(InstCtl) * b->n, hipMemcpyDeviceToHost, b->stream);
-  hipMemcpyAsync(b->h_paths, b->pl.prev_path, sizeof(float) * b->path_off[b->n],
-                 hipMemcpyDeviceToHost, b->stream);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < tmax && e == hipSuccess; ++k)
+    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
+                    STEP_FIT | STEP_FRAME, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->h_ctl, b->pl.ctl, sizeof(InstCtl) * b->n, hipMemcpyDeviceToHost,
+                       b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->h_paths, b->pl.prev_path, sizeof(float) * b->path_off[b->n],
+                       hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e;
 }
 
 sepso_status run_frame(sepso_batch* b, bool move, float* ms) {
@@ -564,11 +572,15 @@ sepso_status run_frame(sepso_batch* b, bool move, float* ms) {
   if (!b->graph[m]) {
     hipGraph_t g = nullptr;
     HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    enqueue_frame(b, move);
+    const hipError_t eq = enqueue_frame(b, move);
     hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (eq != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(b, eq, "frame capture");
+    }
     if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&b->graph[m], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);  // the instantiated graph keeps what it needs
     if (e != hipSuccess) return hip_fail(b, e, "hipGraphInstantiate");
   }
   HIPCHK(b, hipEventRecord(b->ev0, b->stream));
@@ -686,11 +698,14 @@ static sepso_status step_batch(sepso_batch* b, int32_t n) {
   sepso_status st = usable(b);
   if (st != SEPSO_OK) return st;
   if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
-  for (int k = 0; k < n; ++k)
-    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
-                b->stream);
-  if (n > 0)
-    launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0, b->stream);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < n && e == hipSuccess; ++k)
+    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
+                    b->stream);
+  if (n > 0 && e == hipSuccess)
+    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0,
+                    b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "step launch");
   LAUNCHCHK(b, "step launch");
   return SEPSO_OK;
 }
@@ -843,12 +858,13 @@ static sepso_status profile_batch(sepso_batch* b, int32_t n, float* avg_ms) {
   for (size_t q = 0; q < ev.size() && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
   float total = 0.f;
   if (e == hipSuccess) {
-    for (int k = 0; k < n; ++k)
-      launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
-                  b->stream, ev[2 * k], ev[2 * k + 1]);
-    e = hipGetLastError();
+    for (int k = 0; k < n && e == hipSuccess; ++k)
+      e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
+                      STEP_FIT, b->stream, ev[2 * k], ev[2 * k + 1]);
+    if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess)
-      launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0, b->stream);
+      e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0,
+                      b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     for (int k = 0; k < n && e == hipSuccess; ++k) {
       float ms = 0.f;
@@ -857,7 +873,7 @@ static sepso_status profile_batch(sepso_batch* b, int32_t n, float* avg_ms) {
     }
   }
   for (hipEvent_t x : ev)
-    if (x) hipEventDestroy(x);
+    if (x) (void)hipEventDestroy(x);
   if (e != hipSuccess) return hip_fail(b, e, "profile");
   *avg_ms = total / (float)n;
   return SEPSO_OK;
@@ -1213,7 +1229,7 @@ sepso_status sepso_evolve_create(const sepso_map* map, const sepso_swarm* lower,
 
 sepso_status sepso_evolve_destroy(sepso_evolve* ev) {
   if (!ev) return fail(SEPSO_E_ARG, "evolve handle is NULL");
-  if (ev->graph) hipGraphExecDestroy(ev->graph);
+  if (ev->graph) (void)hipGraphExecDestroy(ev->graph);  // teardown: best effort
   destroy_batch(ev->b);
   delete ev;
   return SEPSO_OK;
@@ -1226,19 +1242,24 @@ sepso_status sepso_evolve_run(sepso_evolve* ev, int32_t n, float* curve) {
   if (curve && n > ev->dev.E) return fail(SEPSO_E_ARG, "curve holds at most `evolutions` values");
   sepso_batch* b = ev->b;
   if (ev->graph && ev->graph_gen != b->tune_gen) {
-    hipGraphExecDestroy(ev->graph);
+    (void)hipGraphExecDestroy(ev->graph);  // retired: the tile plan changed
     ev->graph = nullptr;
   }
   if (!ev->graph) {
     ev->graph_gen = b->tune_gen;
     hipGraph_t g = nullptr;
     HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    enqueue_frame(b, false);
+    hipError_t eq = enqueue_frame(b, false);
     launch_evolve_step(ev->dev, b->pl, 0, b->stream);
+    if (eq == hipSuccess) eq = hipGetLastError();
     hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (eq != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(b, eq, "evolution capture");
+    }
     if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&ev->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);  // the instantiated graph keeps what it needs
     if (e != hipSuccess) return hip_fail(b, e, "hipGraphInstantiate");
   }
   EvolveCtl c0{};

@@ -443,9 +443,10 @@ sepso_status sepso_bf_create(const sepso_bf_cfg* cfg, void* d_ws, size_t ws_byte
 
 sepso_status sepso_bf_destroy(sepso_bf* b) {
   if (!b) return fail(SEPSO_E_ARG, "bf handle is NULL");
-  if (b->ev0) hipEventDestroy(b->ev0);
-  if (b->ev1) hipEventDestroy(b->ev1);
-  if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+  // teardown is best effort: a failure here leaves nothing to recover
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return SEPSO_OK;
 }

@@ -13,9 +13,10 @@ bool step_supported(int K);
 size_t iter_lds_words(int pos_floats, int stage_floats, int gb_floats, int ngb_max, int ppb_max,
                       int threads);
 // One iteration: the fused (or update-only) tile kernel, then the per-instance
-// reduce; events, when given, bracket the tile kernel alone.
-void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
-                 hipEvent_t before = nullptr, hipEvent_t after = nullptr);
+// reduce; events, when given, bracket the tile kernel alone.  Returns the
+// event records' status (launch errors are left for hipGetLastError).
+hipError_t launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
+                       hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 void launch_evolve_init(const EvolveDev& ev, const Pools& pl, hipStream_t s);
 void launch_evolve_step(const EvolveDev& ev, const Pools& pl, int injected, hipStream_t s);
 

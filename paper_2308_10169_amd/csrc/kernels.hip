@@ -456,7 +456,6 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
                                           const float (&py)[K + 1], const float (&dx)[K],
                                           const float (&ndy)[K], const float (&nc)[K], int& ct) {
   auto count = [&](uint32_t x) { ct += __popc(x); };
-  const int t = threadIdx.x, B = blockDim.x;
   // Bounding box of the wave's points (wave-uniform).  A segment lies in the
   // box of its end points, so a rectangle that is outside the box (touching
   // allowed) cannot be properly crossed by any of the wave's segments: its
@@ -939,28 +938,30 @@ size_t iter_lds_bytes(const Pools& pl, int threads) {
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
 
 template <int K>
-static void launch_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s,
-                     hipEvent_t before, hipEvent_t after) {
-  if (before) hipEventRecord(before, s);
+static hipError_t launch_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s,
+                           hipEvent_t before, hipEvent_t after) {
+  hipError_t e = hipSuccess;
+  if (before) e = hipEventRecord(before, s);
   if (flags & STEP_FIT)
     hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads), s,
                        pl, flags);
   else
     hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads),
                        s, pl, flags);
-  if (after) hipEventRecord(after, s);
+  if (after && e == hipSuccess) e = hipEventRecord(after, s);
   hipLaunchKernelGGL(reduce_kernel, dim3(pl.n_inst), dim3(256), 0, s, pl, flags);
+  return e;
 }
 
-void launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
-                 hipEvent_t before, hipEvent_t after) {
+hipError_t launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
+                       hipEvent_t before, hipEvent_t after) {
   switch (K) {
-    case 4: launch_k<4>(pl, n_blocks, threads, flags, s, before, after); break;
-    case 8: launch_k<8>(pl, n_blocks, threads, flags, s, before, after); break;
-    case 12: launch_k<12>(pl, n_blocks, threads, flags, s, before, after); break;
-    case 16: launch_k<16>(pl, n_blocks, threads, flags, s, before, after); break;
-    case 24: launch_k<24>(pl, n_blocks, threads, flags, s, before, after); break;
-    default: break;
+    case 4: return launch_k<4>(pl, n_blocks, threads, flags, s, before, after);
+    case 8: return launch_k<8>(pl, n_blocks, threads, flags, s, before, after);
+    case 12: return launch_k<12>(pl, n_blocks, threads, flags, s, before, after);
+    case 16: return launch_k<16>(pl, n_blocks, threads, flags, s, before, after);
+    case 24: return launch_k<24>(pl, n_blocks, threads, flags, s, before, after);
+    default: return hipErrorInvalidValue;
   }
 }
 

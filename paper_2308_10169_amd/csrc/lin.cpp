@@ -219,8 +219,8 @@ sepso_status sepso_lin_create(int32_t max_rows, int64_t max_samples, uint64_t se
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) {
     sepso_status s2 = fail(SEPSO_E_HIP, "lin create: %s", hipGetErrorString(e));
-    if (L->own_stream) hipStreamDestroy(L->stream);
-    if (L->h_loss) hipHostFree(L->h_loss);
+    if (L->own_stream) (void)hipStreamDestroy(L->stream);  // unwinding a failed create
+    if (L->h_loss) (void)hipHostFree(L->h_loss);
     delete L;
     return s2;
   }
@@ -230,8 +230,8 @@ sepso_status sepso_lin_create(int32_t max_rows, int64_t max_samples, uint64_t se
 
 sepso_status sepso_lin_destroy(sepso_lin* L) {
   if (!L) return fail(SEPSO_E_ARG, "handle is NULL");
-  if (L->h_loss) hipHostFree(L->h_loss);
-  if (L->own_stream) hipStreamDestroy(L->stream);
+  if (L->h_loss) (void)hipHostFree(L->h_loss);  // teardown: best effort
+  if (L->own_stream) (void)hipStreamDestroy(L->stream);
   delete L;
   return SEPSO_OK;
 }
@@ -394,7 +394,7 @@ sepso_status sepso_lin_attach(sepso_batch* b, sepso_lin* L) {
   b->lin = L;
   for (int m = 0; m < 2; ++m)
     if (b->graph[m]) {
-      hipGraphExecDestroy(b->graph[m]);
+      (void)hipGraphExecDestroy(b->graph[m]);  // retired; re-captured with the new initializer
       b->graph[m] = nullptr;
     }
   if (!L) {  // back to plain initialisation

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* y, const float* 
   }
   s[threadIdx.x] = acc;
   __syncthreads();
-  for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+  for (unsigned m = blockDim.x / 2; m > 0; m >>= 1) {
     if (threadIdx.x < m) s[threadIdx.x] += s[threadIdx.x + m];
     __syncthreads();
   }
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void loss_sum_kernel(const float* row_sq, int 
   for (int r = threadIdx.x; r < B; r += blockDim.x) acc += row_sq[r];
   s[threadIdx.x] = acc;
   __syncthreads();
-  for (int m = blockDim.x / 2; m > 0; m >>= 1) {
+  for (unsigned m = blockDim.x / 2; m > 0; m >>= 1) {
     if (threadIdx.x < m) s[threadIdx.x] += s[threadIdx.x + m];
     __syncthreads();
   }
