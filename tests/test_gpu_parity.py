@@ -116,6 +116,26 @@ def test_tile_shapes_agree(sp, K, B):
     bp.close()
 
 
+@pytest.mark.parametrize("K,B", [(4, 64), (8, 256), (16, 256)])
+def test_many_groups_per_block(sp, K, B):
+    # 64 groups of 3 particles at W = 64: a block spans dozens of groups, so
+    # dozens of gbest rows are staged per block; every step against the oracle.
+    spec = I.dynamic_map(4, S=300.0, n_static=5, n_moving=5, side=(8.0, 30.0))
+    sw = I.dynamic_swarm(spec.scale, seed=21, groups=64, particles=3, waypoints=64)
+    bp = sp.BatchPlanner([spec], [sw], tune=(K, B))
+    o = orc.Swarm(sw, spec.width, spec.height)
+    m = orc.Map(spec)
+    stats = {}
+    st0 = bp.get_state(0)
+    for _ in range(4):
+        bp.profile_step(1)
+        st1 = bp.get_state(0)
+        check_step(o, m, st0, st1, spec.scale, stats)
+        st0 = st1
+    bp.close()
+    assert stats["paths"] == 4 * 64 * 3
+
+
 def test_adversarial_degenerate_paths(sp):
     # Waypoints placed exactly on obstacle vertices, on edges and along edge
     # lines: many degenerate tests; counts must stay in the oracle bracket.
