@@ -511,18 +511,24 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
         w11 = __builtin_amdgcn_alignbit(w11, __float_as_uint(o11), 31);
         w01 = __builtin_amdgcn_alignbit(w01, __float_as_uint(o01), 31);
       }
-      uint32_t eb = 0, eR = 0, eT = 0, eL = 0;
+      // An edge whose line does not pass strictly through the wave's box has
+      // every point on one side of it (or on it: a degenerate contact), so no
+      // segment crosses it and its point-side word is not formed.
+      auto edge = [&](const float (&p)[K + 1], float c, uint32_t wa, uint32_t wb) {
+        uint32_t ew = 0;
 #pragma unroll
-      for (int s = 0; s <= K; ++s) {
-        eb = __builtin_amdgcn_alignbit(eb, __float_as_uint(py[s] - b.y), 31);
-        eR = __builtin_amdgcn_alignbit(eR, __float_as_uint(px[s] - b.z), 31);
-        eT = __builtin_amdgcn_alignbit(eT, __float_as_uint(py[s] - b.w), 31);
-        eL = __builtin_amdgcn_alignbit(eL, __float_as_uint(px[s] - b.x), 31);
-      }
-      count((w00 ^ w10) & (eb ^ (eb >> 1)));  // bottom
-      count((w10 ^ w11) & (eR ^ (eR >> 1)));  // right
-      count((w11 ^ w01) & (eT ^ (eT >> 1)));  // top
-      count((w01 ^ w00) & (eL ^ (eL >> 1)));  // left
+        for (int s = 0; s <= K; ++s) ew = __builtin_amdgcn_alignbit(ew, __float_as_uint(p[s] - c), 31);
+        count((wa ^ wb) & (ew ^ (ew >> 1)));
+      };
+      // lo < c < hi as one unsigned comparison of the coordinate's bits (the
+      // box is not empty here; a coordinate of -0 lies on the map's border,
+      // its bits test as outside, and no segment can cross that line).
+      const uint32_t ny = (uint32_t)(ky1 - ky0 - 1), nx = (uint32_t)(kx1 - kx0 - 1);
+      auto inside = [](float c, int lo, uint32_t n) { return (uint32_t)(__float_as_int(c) - lo - 1) < n; };
+      if (inside(b.y, ky0, ny)) edge(py, b.y, w00, w10);  // bottom
+      if (inside(b.z, kx0, nx)) edge(px, b.z, w10, w11);  // right
+      if (inside(b.w, ky0, ny)) edge(py, b.w, w11, w01);  // top
+      if (inside(b.x, kx0, nx)) edge(px, b.x, w01, w00);  // left
     }
   }
   // C2. other polygons, edge by edge.  An edge outside the wave's box is
