@@ -62,7 +62,9 @@ def counter_record(kernel, tune):
 
 def executed_fraction(bp, specs, sws, tune, sample):
     """Share of the segment x edge tests the fused iteration actually runs:
-    a wave skips a rectangle outside the bounding box of its points.  The
+    a wave skips a rectangle outside the bounding box of its points, and of a
+    rectangle it keeps, every edge whose line does not pass strictly through
+    that box.  The
     kernel's mapping (blocks of an even number of whole particles, thread t
     on chunk t // ppb of K segments of particle t % ppb, 64 threads per wave)
     is replayed on the swarm state left by the timed launches of sampled
@@ -97,9 +99,13 @@ def executed_fraction(bp, specs, sws, tune, sample):
                 idx = np.minimum(cc[:, None] * K + np.arange(K + 1)[None, :], S - 1)
                 wx, wy = px[p0 + jj[:, None], idx], py[p0 + jj[:, None], idx]
                 segs = np.count_nonzero(cc[:, None] * K + np.arange(K)[None, :] < S - 1)
-                keep = ~((rects[:, 2] <= wx.min()) | (rects[:, 0] >= wx.max()) |
-                         (rects[:, 3] <= wy.min()) | (rects[:, 1] >= wy.max()))
-                run += 4.0 * segs * keep.sum()
+                x0, x1, y0, y1 = wx.min(), wx.max(), wy.min(), wy.max()
+                keep = ~((rects[:, 2] <= x0) | (rects[:, 0] >= x1) |
+                         (rects[:, 3] <= y0) | (rects[:, 1] >= y1))
+                r = rects[keep]
+                edges = (((r[:, 1] > y0) & (r[:, 1] < y1)).sum() + ((r[:, 3] > y0) & (r[:, 3] < y1)).sum()
+                         + ((r[:, 0] > x0) & (r[:, 0] < x1)).sum() + ((r[:, 2] > x0) & (r[:, 2] < x1)).sum())
+                run += float(segs) * edges
                 tot += 4.0 * segs * len(rects)
     return run / tot if tot else 1.0
 
