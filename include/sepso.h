@@ -51,6 +51,16 @@ typedef enum sepso_status {
 const char* sepso_last_error(void);
 const char* sepso_version(void);
 
+/* The planner's random numbers are Philox4x32-10 blocks (Salmon et al.,
+ * SC'11; the random factors of Eq.(4) and the initial, PI and evolution
+ * draws).  For checking the streams: d_out (device, 16-byte aligned, 4*n
+ * words) receives, for i < n, the block of counter (first + i mod 2^32, c1,
+ * c2, c3) under the 64-bit key (low word first).  The planner's draws use
+ * counter (index, step, instance, stream tag) and key = the swarm's seed.
+ * Asynchronous on stream (NULL = the default stream); n <= 2^32. */
+sepso_status sepso_philox(uint32_t first, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t key,
+                          int64_t n, uint32_t* d_out, void* stream);
+
 /* Polygonal map (Sec. "Map representation"): obstacles are closed polygons
  * given by their vertices; a path collides where one of its segments
  * properly crosses a polygon edge.  Map = [0,width] x [0,height]. */

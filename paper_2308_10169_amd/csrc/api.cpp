@@ -641,6 +641,19 @@ extern "C" {
 const char* sepso_last_error(void) { return g_err.c_str(); }
 const char* sepso_version(void) { return "libsepso 0.1 (gfx950)"; }
 
+sepso_status sepso_philox(uint32_t first, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t key,
+                          int64_t n, uint32_t* d_out, void* stream) {
+  if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
+  if (n > ((int64_t)1 << 32)) return fail(SEPSO_E_ARG, "n exceeds the 32-bit counter word");
+  if (n > 0 && !d_out) return fail(SEPSO_E_ARG, "out is NULL");
+  if (reinterpret_cast<uintptr_t>(d_out) % 16) return fail(SEPSO_E_ARG, "out not 16-byte aligned");
+  if (n == 0) return SEPSO_OK;
+  launch_philox(first, c1, c2, c3, key, n, d_out, static_cast<hipStream_t>(stream));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SEPSO_E_HIP, "philox launch: %s", hipGetErrorString(e));
+  return SEPSO_OK;
+}
+
 sepso_status sepso_batch_workspace_bytes(const sepso_map* maps, const sepso_swarm* swarms,
                                          int32_t n_inst, size_t* bytes) {
   if (!bytes) return fail(SEPSO_E_ARG, "bytes is NULL");

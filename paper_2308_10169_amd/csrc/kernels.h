@@ -7,6 +7,8 @@
 namespace sepso {
 
 void launch_geom(const Pools& pl, int n_inst, int move, hipStream_t s);
+void launch_philox(uint32_t first, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t key, int64_t n,
+                   uint32_t* out, hipStream_t s);
 void launch_init(const Pools& pl, int n_blocks, int frame_override, int use_prev, hipStream_t s);
 bool step_supported(int K);
 // 32-bit words of dynamic LDS the fused iteration takes per block.

@@ -124,6 +124,8 @@ def _load():
     L.sepso_batch_plan.argtypes = [vp, C.c_int32, C.POINTER(CFrameResult), fp]
     L.sepso_batch_get_state.argtypes = [vp, C.c_int32, C.POINTER(CState)]
     L.sepso_batch_profile_step.argtypes = [vp, C.c_int32, fp]
+    L.sepso_philox.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
+                               C.c_int64, vp, vp]
     L.sepso_autotune.argtypes = [vp, C.POINTER(CTune)]
     L.sepso_autotune_cached.argtypes = [vp, C.c_char_p, C.POINTER(CTune)]
     L.sepso_batch_work.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -166,6 +168,20 @@ def _load():
 
 def lib():
     return _load()
+
+
+def philox(first, c1, c2, c3, key, n):
+    """n Philox4x32-10 blocks of counters (first + i, c1, c2, c3) under the
+    64-bit key, computed by the library on the GPU: (n, 4) uint32."""
+    _load()
+    torch = _torch
+    out = torch.empty((max(int(n), 1), 4), dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream()
+    _check(_lib.sepso_philox(int(first) & 0xFFFFFFFF, int(c1) & 0xFFFFFFFF, int(c2) & 0xFFFFFFFF,
+                             int(c3) & 0xFFFFFFFF, int(key) & (2**64 - 1), int(n),
+                             C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+    st.synchronize()
+    return out[:int(n)].cpu().numpy().view(np.uint32)
 
 
 def _check(st):

@@ -233,3 +233,20 @@ def test_end_to_end_median_cost(sp):
     mg, mc = np.median(g), np.median(c)
     print("median cost gpu", mg, "oracle", mc)
     assert abs(mg - mc) <= 0.01 * mc
+
+
+@pytest.mark.parametrize("first,c1,c2,c3,key", [
+    (0, 0, 0, 0, 0),                                    # the published all-zero case and on
+    (0, 7, 513, 0, 0x0123456789ABCDEF),                # an update stream: step 7, instance 513
+    (0xFFC00000, 0xFFFFFFFF, 1023, 12, 2**64 - 1),     # counters that wrap the first word
+])
+def test_philox_stream_bit_exact(sp, first, c1, c2, c3, key):
+    # 4.2 million consecutive blocks of the GPU's generator, word for word
+    # against the oracle's own implementation.
+    n = 1 << 22
+    g = sp.philox(first, c1, c2, c3, key, n)
+    ctr = np.empty((n, 4), dtype=np.uint32)
+    ctr[:, 0] = (np.uint64(first) + np.arange(n, dtype=np.uint64)).astype(np.uint32)
+    ctr[:, 1], ctr[:, 2], ctr[:, 3] = c1, c2, c3
+    o = orc.philox_many(ctr, np.array([key & 0xFFFFFFFF, key >> 32], dtype=np.uint32))
+    assert np.array_equal(g, o)
