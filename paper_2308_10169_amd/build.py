@@ -34,7 +34,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     objs = []
-    for src in ("kernels.hip", "mlp.hip", "bf.hip", "api.cpp", "lin.cpp"):
+    for src in ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "api.cpp", "lin.cpp"):
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         cmd = [hipcc] + HIPFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
