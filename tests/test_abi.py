@@ -94,3 +94,26 @@ def test_create_rejects_small_or_misaligned_workspace(lib):
     st = lib.sepso_create(C.byref(m.c), C.byref(s.c), C.c_void_p(257), C.c_size_t(1 << 30), None,
                           C.byref(h))
     assert st == 1
+
+
+def test_philox_rejects_bad_arguments(lib):
+    f = lib.sepso_philox
+    f.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, C.c_int64,
+                  C.c_void_p, C.c_void_p]
+    assert f(0, 0, 0, 0, 0, -1, C.c_void_p(256), None) == 1          # negative count
+    assert f(0, 0, 0, 0, 0, (1 << 32) + 1, C.c_void_p(256), None) == 1  # beyond the counter word
+    assert f(0, 0, 0, 0, 0, 8, None, None) == 1                      # no output
+    assert f(0, 0, 0, 0, 0, 8, C.c_void_p(260), None) == 1           # misaligned output
+    assert f(0, 0, 0, 0, 0, 0, None, None) == 0                      # nothing to do
+
+
+def test_negative_vlimit_rejected(lib):
+    m, s = _args()
+    s.hyper[5] = -0.1  # group 0's V_limit
+    assert _ws_bytes(lib, m, s)[0] == 1
+    assert b"V_limit" in lib.sepso_last_error()
+
+
+def test_tune_cache_and_set_tune_need_a_batch(lib):
+    assert lib.sepso_autotune_cached(None, b"/tmp/x", None) == 1
+    assert lib.sepso_batch_set_tune(None, None) == 1
