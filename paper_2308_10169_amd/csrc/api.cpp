@@ -237,7 +237,27 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
 // Particles per block of the fused iteration: C = ceil((W+1)/K) chunks of K
 // segments per particle, one thread per chunk; even, so that every block
 // starts 16-byte aligned.
-int tile_ppb(int W, int K, int B) { return std::max(2, (B / ((W + K) / K)) & ~1); }
+int tile_ppb(int W, int K, int B, int R) { return std::max(2, ((B / R) / ((W + K) / K)) & ~1); }
+
+// Wave groups a block's rectangles are dealt over: 1 for a launch with
+// enough blocks, else doubled (while whole waves remain: B/R >= 64) as long
+// as the launch stays within two blocks per CU of the 256 -- small instances
+// then run their crossing tests on up to four times as many waves.
+constexpr int kCUs = 256;
+
+int tile_rsplit(const std::vector<InstDesc>& desc, int K, int B) {
+  auto blocks = [&](int R) {
+    int64_t n = 0;
+    for (const InstDesc& d : desc) {
+      const int ppb = tile_ppb(d.W, K, B, R);
+      n += ((int64_t)d.G * d.N + ppb - 1) / ppb;
+    }
+    return n;
+  };
+  int R = 1;
+  while (2 * R <= B / 64 && blocks(2 * R) <= 2 * kCUs) R *= 2;
+  return R;
+}
 
 // Dynamic LDS areas of the fused iteration for a tile shape: maxima over the
 // instances (floats; counts of groups and particles per block).
@@ -247,8 +267,9 @@ struct TileLds {
 
 TileLds tile_lds(const std::vector<InstDesc>& desc, int K, int B) {
   TileLds L{8, 8, 4, 1, 2};
+  const int R = tile_rsplit(desc, K, B);
   for (const InstDesc& d : desc) {
-    const int ppb = tile_ppb(d.W, K, B), D = 2 * d.W;
+    const int ppb = tile_ppb(d.W, K, B, R), D = 2 * d.W;
     const int ngb = std::min(d.G, (ppb - 1) / d.N + 2);  // groups ppb consecutive particles span
     L.pos = std::max(L.pos, ppb * D);
     L.stage = std::max(L.stage, std::min(kStageFloats, 8 * d.n_gedges));
@@ -315,9 +336,11 @@ void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
   const int K = b->tune.seg_per_thread, B = b->tune.block_threads;
   blk->clear();
   std::vector<std::pair<double, int>> order;
+  const int R = tile_rsplit(b->desc, K, B);
+  b->pl.rsplit = R;
   for (int i = 0; i < b->n; ++i) {
     InstDesc& d = b->desc[i];
-    d.ppb = tile_ppb(d.W, K, B);
+    d.ppb = tile_ppb(d.W, K, B, R);
     d.n_blocks = (d.G * d.N + d.ppb - 1) / d.ppb;
     order.push_back({(double)d.n_edges * d.ppb * (d.W + 2), i});
   }

@@ -104,6 +104,7 @@ struct Pools {
   int32_t gb_floats;     // Tbest and the gbest rows of a block's groups
   int32_t ngb_max;       // groups a block spans
   int32_t ppb_max;       // particles per block
+  int32_t rsplit;        // wave groups the rectangles are dealt over (1, 2 or 4)
   const InstDesc* desc;
   InstCtl* ctl;
   float *X, *V, *P;

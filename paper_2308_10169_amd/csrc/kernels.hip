@@ -450,9 +450,9 @@ __device__ __forceinline__ void stage_records(const Pools& pl, const InstDesc& d
 // later ones are staged here by all threads of the block between barriers).  Crossing
 // words: bit K-1-s set when segment s properly crosses the edge (never for
 // masked slots); ct counts them.
-template <int K>
+template <int K, int R>
 __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, float* s_stage,
-                                          bool active, const float (&px)[K + 1],
+                                          bool active, int rg, const float (&px)[K + 1],
                                           const float (&py)[K + 1], const float (&dx)[K],
                                           const float (&ndy)[K], const float (&nc)[K], int& ct) {
   auto count = [&](uint32_t x) { ct += __popc(x); };
@@ -493,7 +493,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
     const int ky1 = __builtin_amdgcn_readfirstlane(float_key(by1));
     typedef const __attribute__((address_space(4))) float cfloat;
     cfloat* rc = (cfloat*)(pl.rects + d.ro);
-    for (int e = 0; e < d.n_rects; ++e) {
+    for (int e = rg; e < d.n_rects; e += R) {  // this wave group's share
       const float4 b = make_float4(rc[4 * e], rc[4 * e + 1], rc[4 * e + 2], rc[4 * e + 3]);  // x0, y0, x1, y1
       if (float_key(b.z) <= kx0 || float_key(b.x) >= kx1 || float_key(b.w) <= ky0 ||
           float_key(b.y) >= ky1)
@@ -531,10 +531,11 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       if (inside(b.x, kx0, nx)) edge(px, b.x, w01, w00);  // left
     }
   }
-  // C2. other polygons, edge by edge.  An edge outside the wave's box is
-  // skipped like a rectangle (a proper crossing lies strictly inside both the
-  // segment and the edge); the vertex words are then recomputed for the next
-  // edge instead of carried over.
+  // C2. other polygons, edge by edge, by wave group 0 (consecutive edges
+  // share vertex words; the other groups still take part in the staging
+  // barriers).  An edge outside the wave's box is skipped like a rectangle (a
+  // proper crossing lies strictly inside both the segment and the edge); the
+  // vertex words are then recomputed for the next edge instead of carried over.
   uint32_t w0 = 0, wp = 0;
   bool have_w0 = false, have_wp = false;
   const EdgeRec* s_edge = reinterpret_cast<const EdgeRec*>(s_stage);
@@ -546,7 +547,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       stage_records(pl, d, s_stage, e0, ne);
       __syncthreads();
     }
-    if (active) {
+    if (active && rg == 0) {
       for (int e = 0; e < ne; ++e) {
         const EdgeRec r = s_edge[e];
         const int fl = __builtin_amdgcn_readfirstlane(r.flags);
@@ -610,7 +611,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
 //  D. per-particle Q and L summed in chunk order (deterministic), fitness
 //     and Pbest; improved particles' positions go from LDS to P.
 // ---------------------------------------------------------------------------
-template <int K, bool FIT>
+template <int K, int R, bool FIT>
 __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   // dynamic LDS: positions | obstacle records | Tbest and the gbest rows of
   // the block's groups | an 8-word record per particle (Pbest flags in phase
@@ -797,12 +798,18 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   __syncthreads();
 
   // ---- B. this thread's K segments --------------------------------------------
-  // A particle's W+1 segments are cut into C chunks of K; thread t takes chunk
-  // t / ppb of particle t mod ppb, so the 64 lanes of a wave hold the same
-  // stretch of 64 neighbouring paths -- close together once the swarm
-  // converges, which is what the culling in phase C feeds on.
+  // A particle's W+1 segments are cut into C chunks of K.  The block's waves
+  // form R groups of B/R threads (R = 1 unless the launch would leave most
+  // CUs idle); in each group thread u takes chunk u / ppb of particle
+  // u mod ppb, so the 64 lanes of a wave hold the same stretch of 64
+  // neighbouring paths -- close together once the swarm converges, which is
+  // what the culling in phase C feeds on -- and group r tests every R-th
+  // rectangle from the r-th on.
   const int C = (W + K) / K;
-  const int c = t / d.ppb, jt = t - c * d.ppb;
+  const int BR = R == 1 ? B : B / R;
+  const int rg = R == 1 ? 0 : __builtin_amdgcn_readfirstlane(t / BR);  // whole waves: uniform
+  const int u = t - rg * BR;
+  const int c = u / d.ppb, jt = u - c * d.ppb;
   const bool active = c < C && jt < np;
   const int jc = active ? jt : 0;  // inactive lanes read a valid particle, count nothing
   const int i0 = c * K;           // first point index of the chunk
@@ -840,10 +847,11 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     nc[s] = seg ? fmaf(ddy, px[s], -(ddx * py[s])) : 0.f;
     if (seg) len_sum += __builtin_amdgcn_sqrtf(ddx * ddx + ddy * ddy);  // v_sqrt_f32, 1 ulp
   }
+  if (rg != 0) len_sum = 0.f;  // each length is summed once, by group 0
 
   // ---- C. crossings ----------------------------------------------------------
   int ct = 0;
-  crossings<K>(pl, d, s_stage, active, px, py, dx, ndy, nc, ct);
+  crossings<K, R>(pl, d, s_stage, active, rg, px, py, dx, ndy, nc, ct);
 
   // ---- D. per-particle fitness and Pbest -------------------------------------
   const float pf_old = reinterpret_cast<const float*>(s_q)[t];  // before the slot is reused
@@ -855,8 +863,8 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     int q = 0;
     float L = 0.f;
     for (int cc = 0; cc < C; ++cc) {  // chunk order: deterministic
-      q += s_q[j + cc * d.ppb];
-      L += s_l[j + cc * d.ppb];
+      for (int r = 0; r < R; ++r) q += s_q[r * BR + j + cc * d.ppb];
+      L += s_l[j + cc * d.ppb];  // lengths from group 0 only
     }
     const float qf = (float)q;
     float pw = 1.f;
@@ -908,17 +916,20 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
   }
 }
 
-// One fused iteration (fitness path) and the update-only flush, as separate
-// kernels so that profiles separate them.
-// K = 8 fits five waves per SIMD when capped at 96 registers (a few spilled
-// words outside the crossing loop), which beats four waves at 107.
+// One fused iteration (fitness path), the same with the rectangles dealt over
+// R wave groups (launches with few blocks), and the update-only flush, as
+// separate kernels so that profiles separate them.
 template <int K>
 __global__ __launch_bounds__(256) void iter_kernel(Pools pl, int flags) {
-  iteration<K, true>(pl, flags);
+  iteration<K, 1, true>(pl, flags);
+}
+template <int K, int R>
+__global__ __launch_bounds__(256) void iter_kernel_split(Pools pl, int flags) {
+  iteration<K, R, true>(pl, flags);
 }
 template <int K>
 __global__ __launch_bounds__(256) void update_kernel(Pools pl, int flags) {
-  iteration<K, false>(pl, flags);
+  iteration<K, 1, false>(pl, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,9 +959,13 @@ static hipError_t launch_k(const Pools& pl, int n_blocks, int threads, int flags
                            hipEvent_t before, hipEvent_t after) {
   hipError_t e = hipSuccess;
   if (before) e = hipEventRecord(before, s);
-  if (flags & STEP_FIT)
-    hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads), s,
-                       pl, flags);
+  const size_t lds = iter_lds_bytes(pl, threads);
+  if ((flags & STEP_FIT) && pl.rsplit == 4)
+    hipLaunchKernelGGL((iter_kernel_split<K, 4>), dim3(n_blocks), dim3(threads), lds, s, pl, flags);
+  else if ((flags & STEP_FIT) && pl.rsplit == 2)
+    hipLaunchKernelGGL((iter_kernel_split<K, 2>), dim3(n_blocks), dim3(threads), lds, s, pl, flags);
+  else if (flags & STEP_FIT)
+    hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), lds, s, pl, flags);
   else
     hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads),
                        s, pl, flags);
