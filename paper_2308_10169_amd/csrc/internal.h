@@ -94,6 +94,7 @@ struct sepso_lin {
   uint16_t* dZ16[3];
   float* rowsq;
   float* dloss;       // loss per training step
+  float* splitk;      // split-K GEMM slices
   int32_t* eligible;  // max_rows
   uint16_t* DX;       // max_samples x kLinInPad
   float* DT;          // max_samples x 320

@@ -20,6 +20,7 @@ const int kInPad[4] = {kLinInPad, kLinHidden, kLinHidden, kLinHidden};
 const int kInReal[4] = {kLinIn, kLinHidden, kLinHidden, kLinHidden};
 const int kOutN[4] = {kLinHidden, kLinHidden, kLinHidden, kLinOut};
 constexpr int kLossHist = 1 << 16;
+constexpr int64_t kSplitWs = 8 * 256 * kLinHidden;  // split-K slices (FP32)
 
 int64_t n_params() {
   int64_t n = 0;
@@ -65,6 +66,7 @@ size_t lin_layout(int max_rows, int64_t max_samples, sepso_lin* L, char* base) {
   p = take(4 * (size_t)max_rows); if (L) L->rowsq = (float*)p;
   p = take(4 * (size_t)max_rows); if (L) L->eligible = (int32_t*)p;
   p = take(4 * (size_t)kLossHist); if (L) L->dloss = (float*)p;
+  p = take(4 * (size_t)kSplitWs); if (L) L->splitk = (float*)p;
   p = take(2 * (size_t)max_samples * kLinInPad); if (L) L->DX = (uint16_t*)p;
   p = take(4 * (size_t)max_samples * kLinOut); if (L) L->DT = (float*)p;
   return o;
@@ -99,12 +101,12 @@ void forward(sepso_lin* L, const uint16_t* X, int M, hipStream_t s) {
   int ldi = kLinInPad;
   for (int l = 0; l < 3; ++l) {
     const Epi ep{EPI_BIAS_RELU_BF16, L->b32[l], nullptr, L->A16[l], nullptr, kLinHidden};
-    launch_gemm(false, false, in, ldi, L->W16[l], kInPad[l], M, kLinHidden, kInPad[l], ep, s);
+    launch_gemm(false, false, in, ldi, L->W16[l], kInPad[l], M, kLinHidden, kInPad[l], ep, L->splitk, kSplitWs, s);
     in = L->A16[l];
     ldi = kLinHidden;
   }
   const Epi ep{EPI_BIAS_F32, L->b32[3], L->Y, nullptr, nullptr, kLinOut};
-  launch_gemm(false, false, L->A16[2], kLinHidden, L->W16[3], kLinHidden, M, kLinOut, kLinHidden, ep, s);
+  launch_gemm(false, false, L->A16[2], kLinHidden, L->W16[3], kLinHidden, M, kLinOut, kLinHidden, ep, L->splitk, kSplitWs, s);
 }
 
 // Gradients of the mean squared error for rows X (B rows) against targets T.
@@ -114,19 +116,19 @@ void backward(sepso_lin* L, const uint16_t* X, const float* T, int B, float* los
   launch_loss_sum(L->rowsq, B, 1.f / ((float)B * kLinOut), loss_slot, s);
   launch_colsum(L->dY, B, kLinOut, L->gb[3], s);
   launch_gemm(true, true, L->dY16, kLinOut, L->A16[2], kLinHidden, kLinOut, kLinHidden, B,
-              Epi{EPI_F32, nullptr, L->gW[3], nullptr, nullptr, kLinHidden}, s);
+              Epi{EPI_F32, nullptr, L->gW[3], nullptr, nullptr, kLinHidden}, L->splitk, kSplitWs, s);
   launch_gemm(false, true, L->dY16, kLinOut, L->W16[3], kLinHidden, B, kLinHidden, kLinOut,
-              Epi{EPI_MASK, nullptr, L->dZ[2], L->dZ16[2], L->A16[2], kLinHidden}, s);
+              Epi{EPI_MASK, nullptr, L->dZ[2], L->dZ16[2], L->A16[2], kLinHidden}, L->splitk, kSplitWs, s);
   for (int l = 2; l >= 1; --l) {
     launch_colsum(L->dZ[l], B, kLinHidden, L->gb[l], s);
     launch_gemm(true, true, L->dZ16[l], kLinHidden, L->A16[l - 1], kLinHidden, kLinHidden,
-                kLinHidden, B, Epi{EPI_F32, nullptr, L->gW[l], nullptr, nullptr, kLinHidden}, s);
+                kLinHidden, B, Epi{EPI_F32, nullptr, L->gW[l], nullptr, nullptr, kLinHidden}, L->splitk, kSplitWs, s);
     launch_gemm(false, true, L->dZ16[l], kLinHidden, L->W16[l], kLinHidden, B, kLinHidden,
-                kLinHidden, Epi{EPI_MASK, nullptr, L->dZ[l - 1], L->dZ16[l - 1], L->A16[l - 1], kLinHidden}, s);
+                kLinHidden, Epi{EPI_MASK, nullptr, L->dZ[l - 1], L->dZ16[l - 1], L->A16[l - 1], kLinHidden}, L->splitk, kSplitWs, s);
   }
   launch_colsum(L->dZ[0], B, kLinHidden, L->gb[0], s);
   launch_gemm(true, true, L->dZ16[0], kLinHidden, X, kLinInPad, kLinHidden, kLinInPad, B,
-              Epi{EPI_F32, nullptr, L->gW[0], nullptr, nullptr, kLinInPad}, s);
+              Epi{EPI_F32, nullptr, L->gW[0], nullptr, nullptr, kLinInPad}, L->splitk, kSplitWs, s);
 }
 
 void adam(sepso_lin* L, float lr, hipStream_t s) {

@@ -20,8 +20,9 @@ struct Epi {
 
 void launch_raster(const Pools& pl, int n_inst, uint16_t* X, int ldx, int32_t* eligible,
                    hipStream_t s);
+// ws: FP32 split-K workspace of ws_floats (S x M x N are used when K is split).
 void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_t* B, int ldb,
-                 int M, int N, int K, const Epi& ep, hipStream_t s);
+                 int M, int N, int K, const Epi& ep, float* ws, int64_t ws_floats, hipStream_t s);
 void launch_loss(const float* y, const float* target, int B, int n, float* dy, uint16_t* dy16,
                  float* row_sq, hipStream_t s);
 void launch_colsum(const float* dz, int B, int n, float* out, hipStream_t s);

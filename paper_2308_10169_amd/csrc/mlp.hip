@@ -61,17 +61,43 @@ __global__ __launch_bounds__(256) void raster_kernel(Pools pl, uint16_t* X, int 
   if (threadIdx.x == 0) eligible[inst] = (d.G == kLinGroups && d.W == kLinW) ? 1 : 0;
 }
 
+// The GEMM epilogue applied to one FP32 result C(row, col) = v.
+__device__ __forceinline__ void apply_epi(const Epi& ep, int row, int col, float v) {
+  const int64_t o = (int64_t)row * ep.ldo + col;
+  switch (ep.mode) {
+    case EPI_BIAS_RELU_BF16:
+      v += ep.bias[col];
+      ep.out_bf16[o] = to_bf16(v > 0.f ? v : 0.f);
+      break;
+    case EPI_BIAS_F32:
+      ep.out_f32[o] = v + ep.bias[col];
+      break;
+    case EPI_F32:
+      ep.out_f32[o] = v;
+      break;
+    case EPI_MASK: {
+      const float dz = from_bf16(ep.mask[o]) > 0.f ? v : 0.f;
+      ep.out_f32[o] = dz;
+      ep.out_bf16[o] = to_bf16(dz);
+      break;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // C[M x N] = op(A)[M x K] * op(B)[K x N], BF16 in, FP32 accumulate.
 //   A_KM = false: A(m, k) = A[m*lda + k]   A_KM = true: A(m, k) = A[k*lda + m]
 //   B_KN = false: B(k, n) = B[n*ldb + k]   B_KN = true: B(k, n) = B[k*ldb + n]
 // Block tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA 16x16x32 tiles).
 // Requires K % 32 == 0; M % 8 == 0 when A_KM; N % 8 == 0 when B_KN.
+// Split K: block z takes k-steps [z*kper, (z+1)*kper) of 32 and, when
+// `part` is given, stores its raw sums as slice z of part (M x N each) for
+// splitk_epi_kernel; otherwise it applies the epilogue itself.
 // ---------------------------------------------------------------------------
 template <bool A_KM, bool B_KN>
 __global__ __launch_bounds__(256) void gemm_kernel(const uint16_t* __restrict__ A, int lda,
                                                    const uint16_t* __restrict__ B, int ldb, int M,
-                                                   int N, int K, Epi ep) {
+                                                   int N, int K, int kper, float* part, Epi ep) {
   constexpr int LDS = 40;  // padded row (k) length
   __shared__ __attribute__((aligned(16))) uint16_t As[64 * LDS];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * LDS];
@@ -81,7 +107,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const uint16_t* __restrict__ 
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  const int kbeg = blockIdx.z * kper * 32, kend = min(K, kbeg + kper * 32);
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
     if (!A_KM) {
       const int row = t >> 2, kc = (t & 3) * 8;
       uint4 v = make_uint4(0, 0, 0, 0);
@@ -125,27 +152,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(const uint16_t* __restrict__ 
         const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
         const int col = n0 + wn + j * 16 + (lane & 15);
         if (row >= M || col >= N) continue;
-        float v = acc[i][j][r];
-        const int64_t o = (int64_t)row * ep.ldo + col;
-        switch (ep.mode) {
-          case EPI_BIAS_RELU_BF16:
-            v += ep.bias[col];
-            ep.out_bf16[o] = to_bf16(v > 0.f ? v : 0.f);
-            break;
-          case EPI_BIAS_F32:
-            ep.out_f32[o] = v + ep.bias[col];
-            break;
-          case EPI_F32:
-            ep.out_f32[o] = v;
-            break;
-          case EPI_MASK: {
-            const float dz = from_bf16(ep.mask[o]) > 0.f ? v : 0.f;
-            ep.out_f32[o] = dz;
-            ep.out_bf16[o] = to_bf16(dz);
-            break;
-          }
-        }
+        if (part)
+          part[((int64_t)blockIdx.z * M + row) * N + col] = acc[i][j][r];
+        else
+          apply_epi(ep, row, col, acc[i][j][r]);
       }
+}
+
+// Sum of the S split-K slices of part in slice order, then the epilogue.
+__global__ __launch_bounds__(256) void splitk_epi_kernel(const float* __restrict__ part, int S,
+                                                         int M, int N, Epi ep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, MN = (int64_t)M * N;
+  if (i >= MN) return;
+  float v = part[i];
+  for (int z = 1; z < S; ++z) v += part[z * MN + i];
+  apply_epi(ep, (int)(i / N), (int)(i % N), v);
 }
 
 // dy = 2 (y - target) / (B * n) (FP32 and BF16) and per-row squared-error sums.
@@ -199,13 +220,21 @@ __global__ __launch_bounds__(256) void targets_kernel(Pools pl, float* T, int ld
   }
 }
 
-// Column sums of a B x n FP32 matrix (bias gradients), fixed order.
+// Column sums of a B x n FP32 matrix (bias gradients), in a fixed order: a
+// block takes 64 columns, its wave w sums rows w, w+4, ... (eight loads in
+// flight per lane), and the four partial sums are added in wave order.
 __global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int n, float* out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int r = 0; r < B; ++r) s += dz[(int64_t)r * n + j];
-  out[j] = s;
+  if (j < n) {
+#pragma unroll 8
+    for (int r = w; r < B; r += 4) s += dz[(int64_t)r * n + j];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < n) out[j] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // Adam on FP32 master weights (rows x cols with `cols` real columns stored
@@ -265,16 +294,31 @@ void launch_raster(const Pools& pl, int n_inst, uint16_t* X, int ldx, int32_t* e
 }
 
 void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_t* B, int ldb,
-                 int M, int N, int K, const Epi& ep, hipStream_t s) {
-  const dim3 grid((N + 63) / 64, (M + 63) / 64);
+                 int M, int N, int K, const Epi& ep, float* ws, int64_t ws_floats, hipStream_t s) {
+  // Split K while the tile grid leaves most CUs idle, as far as the k-steps
+  // and the workspace allow.
+  const int tiles = ((N + 63) / 64) * ((M + 63) / 64), steps = K / 32;
+  int S = 1;
+  while (S < 8 && tiles * S * 2 <= 256 && S * 2 <= steps &&
+         (int64_t)S * 2 * M * N <= ws_floats)
+    S *= 2;
+  const int kper = steps > 0 ? (steps + S - 1) / S : 1;
+  S = steps > 0 ? (steps + kper - 1) / kper : 1;
+  float* part = S > 1 ? ws : nullptr;
+  const dim3 grid((N + 63) / 64, (M + 63) / 64, S);
   if (!a_km && !b_kn)
-    hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+    hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
   else if (!a_km && b_kn)
-    hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+    hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
   else if (a_km && b_kn)
-    hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+    hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
   else
-    hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+    hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+  if (part) {
+    const int64_t MN = (int64_t)M * N;
+    hipLaunchKernelGGL(splitk_epi_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s,
+                       part, S, M, N, ep);
+  }
 }
 
 void launch_loss(const float* y, const float* target, int B, int n, float* dy, uint16_t* dy16,
@@ -291,7 +335,7 @@ void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t 
 }
 
 void launch_colsum(const float* dz, int B, int n, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dz, B, n, out);
+  hipLaunchKernelGGL(colsum_kernel, dim3((n + 63) / 64), dim3(256), 0, s, dz, B, n, out);
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, uint16_t* p16, int64_t count,

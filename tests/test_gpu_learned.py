@@ -55,10 +55,11 @@ def test_forward_matches_oracle(sp):
     lin.close()
 
 
-def test_gradients_match_oracle(sp):
-    lin = sp.LearnedInit(max_rows=64, seed=5)
+@pytest.mark.parametrize("rows", [64, 256])  # 256: the training batch (split-K GEMMs)
+def test_gradients_match_oracle(sp, rows):
+    lin = sp.LearnedInit(max_rows=rows, seed=5)
     W, b = sp.split_params(lin.get_weights().astype(np.float64))
-    x, t = _inputs(64, 2)
+    x, t = _inputs(rows, 2)
     loss, g = lin.grads(x, t)
     ref = orc.mlp(SIZES, W, b, x.astype(np.float64), target=t.astype(np.float64), round=True)
     assert abs(loss - ref["loss"]) <= 1e-2 * ref["loss"]
