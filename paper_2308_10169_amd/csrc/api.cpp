@@ -146,7 +146,7 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
       d.ro = (int32_t)L.sumR;
       d.geo = (int32_t)L.sumGE;
     }
-    L.sumR += n_rects;
+    L.sumR += (n_rects + 3) & ~3;  // whole 64-byte quads per instance
     L.sumGE += n_gedges;
     if (desc) {
       InstDesc& d = (*desc)[i];

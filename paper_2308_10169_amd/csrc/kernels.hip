@@ -91,7 +91,9 @@ __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
         y0 = fminf(y0, verts[v0 + j].y);
         y1 = fmaxf(y1, verts[v0 + j].y);
       }
-      pl.rects[d.ro + ks.y] = make_float4(x0, y0, x1, y1);
+      // + 0 turns a -0 corner into +0: every stored coordinate then has its
+      // sign bit clear, and its bits order as its value does
+      pl.rects[d.ro + ks.y] = make_float4(x0 + 0.f, y0 + 0.f, x1 + 0.f, y1 + 0.f);
       continue;
     }
     EdgeRec* er = pl.edges + d.geo + ks.y;
@@ -491,12 +493,20 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
     const int kx1 = __builtin_amdgcn_readfirstlane(float_key(bx1));
     const int ky0 = __builtin_amdgcn_readfirstlane(float_key(by0));
     const int ky1 = __builtin_amdgcn_readfirstlane(float_key(by1));
-    typedef const __attribute__((address_space(4))) float cfloat;
-    cfloat* rc = (cfloat*)(pl.rects + d.ro);
-    for (int e = rg; e < d.n_rects; e += R) {  // this wave group's share
-      const float4 b = make_float4(rc[4 * e], rc[4 * e + 1], rc[4 * e + 2], rc[4 * e + 3]);  // x0, y0, x1, y1
-      if (float_key(b.z) <= kx0 || float_key(b.x) >= kx1 || float_key(b.w) <= ky0 ||
-          float_key(b.y) >= ky1)
+    // Rectangles come in 64-byte quads (an instance's slice is padded to a
+    // whole number of them), one scalar load per quad; wave group rg takes
+    // quads rg, rg + R, ...  Padding rectangles are loaded, never tested.
+    typedef float quad16 __attribute__((ext_vector_type(16)));
+    const __attribute__((address_space(4))) quad16* rq =
+        (const __attribute__((address_space(4))) quad16*)(pl.rects + d.ro);
+    for (int c4 = rg; 4 * c4 < d.n_rects; c4 += R) {
+      const quad16 blk = rq[c4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+      const float4 b = make_float4(blk[4 * q], blk[4 * q + 1], blk[4 * q + 2], blk[4 * q + 3]);  // x0, y0, x1, y1
+      // stored coordinates have their sign bit clear: their bits are their keys
+      if (4 * c4 + q >= d.n_rects || __float_as_int(b.z) <= kx0 || __float_as_int(b.x) >= kx1 ||
+          __float_as_int(b.w) <= ky0 || __float_as_int(b.y) >= ky1)
         continue;
       const float w = b.z - b.x, h = b.w - b.y;
       uint32_t w00 = 0, w10 = 0, w11 = 0, w01 = 0;
@@ -529,6 +539,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       if (inside(b.z, kx0, nx)) edge(px, b.z, w10, w11);  // right
       if (inside(b.w, ky0, ny)) edge(py, b.w, w11, w01);  // top
       if (inside(b.x, kx0, nx)) edge(px, b.x, w01, w00);  // left
+      }
     }
   }
   // C2. other polygons, edge by edge, by wave group 0 (consecutive edges
