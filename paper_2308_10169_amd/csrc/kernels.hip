@@ -301,9 +301,10 @@ __device__ void hsef_step(const Pools& pl, const InstDesc& d, InstCtl* ctl, cons
 // Tbest = argmin over groups; then Auto Truncation, the online outer step
 // and the control-block advance.  One block per instance, after the tile
 // kernels have finished (kernel boundary = visibility, no fences in tiles).
-__global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
+__global__ __launch_bounds__(512) void reduce_kernel(Pools pl, int flags) {
   __shared__ float s_gf[kMaxG];
   __shared__ int s_gn[kMaxG];
+  __shared__ float s_hist[kHist];
   __shared__ int s_tg, s_stop, s_at, s_q;
   const int inst = blockIdx.x;
   const InstDesc d = pl.desc[inst];  // by value: stores cannot make it reload
@@ -320,6 +321,10 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
     }
     return;
   }
+  // the Auto-Truncation history ring, read while the Pbest scan runs (its
+  // LDS copy is written after the scan, so that no wave waits for it first)
+  const bool hist_lane = (flags & STEP_FRAME) && t < kHist;
+  const float hv = hist_lane ? ctl->hist[t] : 0.f;
   // one wave per group (waves take groups in turn): lanes scan the group's
   // Pbest fitness, a shuffle argmin (lowest index on ties) picks Gbest
   const float* Pf = pl.Pf + d.po;
@@ -327,12 +332,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   for (int g = wave; g < G; g += n_waves) {
     float bf = INFINITY;
     int bn = 0x7fffffff;
-    for (int n = lane; n < N; n += 64) {
-      const float f = Pf[g * N + n];
-      if (better(f, n, bf, bn)) {
-        bf = f;
-        bn = n;
-      }
+    for (int n0 = lane; n0 < N; n0 += 4 * 64) {  // four loads in flight per lane
+      float f[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f[u] = n0 + 64 * u < N ? Pf[g * N + n0 + 64 * u] : INFINITY;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (better(f[u], n0 + 64 * u, bf, bn)) {
+          bf = f[u];
+          bn = n0 + 64 * u;
+        }
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) {
@@ -351,6 +360,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
       pl.gbest_f[d.go + g] = bf;
     }
   }
+  if (hist_lane) s_hist[t] = hv;
   __syncthreads();
   if (t == 0) {
     int tg = 0;
@@ -373,8 +383,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(Pools pl, int flags) {
   if (flags & STEP_FRAME) {
     if (t == 0) {
       ctl->hist[(k_new - 1) % kHist] = tf;
+      s_hist[(k_new - 1) % kHist] = tf;
       const int q = pl.PQ[d.po + tg * N + tn];
-      const bool a = at_fires(ctl->hist, k_new, d.at_mode, d.at_window, d.at_delta, q);
+      const bool a = at_fires(s_hist, k_new, d.at_mode, d.at_window, d.at_delta, q);
       s_at = a;
       s_stop = a || k_new >= d.T;
       s_q = q;
@@ -981,7 +992,11 @@ static hipError_t launch_k(const Pools& pl, int n_blocks, int threads, int flags
     hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads),
                        s, pl, flags);
   if (after && e == hipSuccess) e = hipEventRecord(after, s);
-  hipLaunchKernelGGL(reduce_kernel, dim3(pl.n_inst), dim3(256), 0, s, pl, flags);
+  // few instances: eight waves per block, so that each of (typically) eight
+  // groups gets a wave of its own and the launch's latency is one scan;
+  // a full batch keeps four waves per block (more blocks resident)
+  const int red_threads = pl.n_inst < 256 ? 512 : 256;
+  hipLaunchKernelGGL(reduce_kernel, dim3(pl.n_inst), dim3(red_threads), 0, s, pl, flags);
   return e;
 }
 
