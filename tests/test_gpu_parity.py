@@ -136,6 +136,28 @@ def test_many_groups_per_block(sp, K, B):
     assert stats["paths"] == 4 * 64 * 3
 
 
+@pytest.mark.parametrize("tune", [(8, 64), (8, 128), (4, 256)])  # 1, 2, 4 wave groups
+@pytest.mark.parametrize("n_rects", [1, 3, 5, 6, 9])
+def test_ragged_rectangle_quads(sp, tune, n_rects):
+    # Rectangles are read four at a time from a slice padded to whole quads
+    # and dealt over the wave groups quad by quad: counts that are not a
+    # multiple of four, and fewer quads than wave groups, against the oracle.
+    spec = I.dynamic_map(30 + n_rects, S=200.0, n_static=n_rects, n_moving=0, side=(20.0, 50.0))
+    sw = I.dynamic_swarm(spec.scale, seed=n_rects, groups=4, particles=48, waypoints=12)
+    bp = sp.BatchPlanner([spec], [sw], tune=tune)
+    o = orc.Swarm(sw, spec.width, spec.height)
+    m = orc.Map(spec)
+    stats = {}
+    st0 = bp.get_state(0)
+    for _ in range(3):
+        bp.profile_step(1)
+        st1 = bp.get_state(0)
+        check_step(o, m, st0, st1, spec.scale, stats)
+        st0 = st1
+    bp.close()
+    assert stats["paths"] == 3 * 4 * 48
+
+
 def test_adversarial_degenerate_paths(sp):
     # Waypoints placed exactly on obstacle vertices, on edges and along edge
     # lines: many degenerate tests; counts must stay in the oracle bracket.
