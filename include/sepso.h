@@ -205,8 +205,10 @@ sepso_status sepso_batch_profile_step(sepso_batch* b, int32_t n, float* avg_ms);
 sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best);
 /* sepso_autotune with a persistent cache: cache_path is a text file of lines
  * "<key> <K> <block_threads>", the key a 64-bit hash (16 hex digits) of the
- * device architecture name and every instance's groups, particles,
- * waypoints, rectangles and other-polygon edges.  When the file holds this
+ * device architecture name, a fingerprint of the library's device-code
+ * sources (a rebuilt library does not reuse another build's tiles) and every
+ * instance's groups, particles, waypoints, rectangles and other-polygon
+ * edges.  When the file holds this
  * batch's key with a valid tile, that tile is applied without timing
  * (and the batch is reset as after sepso_autotune);
  * otherwise the batch is autotuned and a line is appended.  A missing file is

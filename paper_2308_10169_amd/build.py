@@ -6,6 +6,7 @@ would otherwise emit v_pk_{add,mul,fma}_f32 from ordinary float code.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -30,15 +31,30 @@ def _run(cmd):
     return r
 
 
+DEVICE_SOURCES = ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "rng.h", "common.h", "kernels.h", "mlp.h")
+
+
+def kernels_id() -> str:
+    """First 64 bits of a SHA-256 over the device-code sources (keys the
+    autotuner's tile cache to this build)."""
+    h = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return "0x" + h.hexdigest()[:16] + "ull"
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     objs = []
+    kid = kernels_id()
     for src in ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "api.cpp", "lin.cpp"):
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         cmd = [hipcc] + HIPFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc, "-x", "hip"] + HIPFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [hipcc, "-x", "hip"] + HIPFLAGS + [f"-DSEPSO_KERNELS_ID={kid}", "-c",
+                                                     os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
         _run(cmd)

@@ -1018,6 +1018,12 @@ namespace {
 
 // Key of a batch for the tune cache: FNV-1a over the device architecture name
 // and the shape fields of every instance that decide the tile's cost.
+// Fingerprint of the device-code sources this library was built from
+// (passed in by the build; 0 for a build that does not pass it).
+#ifndef SEPSO_KERNELS_ID
+#define SEPSO_KERNELS_ID 0ull
+#endif
+
 uint64_t tune_key(const sepso_batch* b) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](const void* p, size_t n) {
@@ -1031,6 +1037,9 @@ uint64_t tune_key(const sepso_batch* b) {
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     mix(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+  // a build of other kernel sources may rank the tiles differently
+  const uint64_t src = SEPSO_KERNELS_ID;
+  mix(&src, sizeof(src));
   mix(&b->n, sizeof(b->n));
   for (const InstDesc& d : b->desc) {
     const int32_t f[5] = {d.G, d.N, d.W, d.n_rects, d.n_gedges};
