@@ -45,7 +45,7 @@ typedef enum sepso_status {
   SEPSO_E_NOMEM = 2,       /* workspace too small or host allocation failed */
   SEPSO_E_HIP = 3,         /* HIP runtime error (sticky) */
   SEPSO_E_STATE = 4,       /* handle unusable (earlier HIP error) or wrong call order */
-  SEPSO_E_UNSUPPORTED = 5  /* valid request this build does not support */
+  SEPSO_E_UNSUPPORTED = 5  /* valid request the library does not support */
 } sepso_status;
 
 const char* sepso_last_error(void);

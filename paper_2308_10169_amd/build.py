@@ -36,7 +36,7 @@ DEVICE_SOURCES = ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "rng.h", "co
 
 def kernels_id() -> str:
     """First 64 bits of a SHA-256 over the device-code sources (keys the
-    autotuner's tile cache to this build)."""
+    autotuner's tile cache to these sources)."""
     h = hashlib.sha256()
     for name in DEVICE_SOURCES:
         with open(os.path.join(CSRC, name), "rb") as f:
