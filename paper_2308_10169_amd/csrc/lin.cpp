@@ -136,11 +136,17 @@ void adam(sepso_lin* L, float lr, hipStream_t s) {
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   const float c1 = (float)(1.0 - std::pow(0.9, L->adam_t));
   const float c2 = (float)(1.0 - std::pow(0.999, L->adam_t));
+  // all eight tensors (weights and biases of the four layers) in one launch
+  AdamSets a{};
   for (int l = 0; l < 4; ++l) {
-    launch_adam(L->W32[l], L->gW[l], L->mW[l], L->vW[l], L->W16[l], (int64_t)kOutN[l] * kInPad[l],
-                lr, b1, b2, eps, c1, c2, s);
-    launch_adam(L->b32[l], L->gb[l], L->mb[l], L->vb[l], nullptr, kOutN[l], lr, b1, b2, eps, c1, c2, s);
+    const int w = 2 * l, b = 2 * l + 1;
+    a.p[w] = L->W32[l]; a.g[w] = L->gW[l]; a.m[w] = L->mW[l]; a.v[w] = L->vW[l];
+    a.p16[w] = L->W16[l]; a.count[w] = (int64_t)kOutN[l] * kInPad[l];
+    a.p[b] = L->b32[l]; a.g[b] = L->gb[l]; a.m[b] = L->mb[l]; a.v[b] = L->vb[l];
+    a.p16[b] = nullptr; a.count[b] = kOutN[l];
   }
+  a.n = 8;
+  launch_adam_sets(a, lr, b1, b2, eps, c1, c2, s);
 }
 
 // Upload host FP32 rows (n x kLinIn) as BF16 rows of stride kLinInPad.

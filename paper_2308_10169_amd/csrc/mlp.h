@@ -28,8 +28,20 @@ void launch_loss(const float* y, const float* target, int B, int n, float* dy, u
 void launch_colsum(const float* dz, int B, int n, float* out, hipStream_t s);
 void launch_loss_sum(const float* row_sq, int B, float scale, float* out, hipStream_t s);
 void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t s);
-void launch_adam(float* p, const float* g, float* m, float* v, uint16_t* p16, int64_t count,
-                 float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+// Parameter tensors updated by one Adam launch (p16 may be NULL per set).
+constexpr int kAdamMaxSets = 8;
+struct AdamSets {
+  float* p[kAdamMaxSets];
+  const float* g[kAdamMaxSets];
+  float* m[kAdamMaxSets];
+  float* v[kAdamMaxSets];
+  uint16_t* p16[kAdamMaxSets];
+  int64_t count[kAdamMaxSets];
+  int64_t first_block[kAdamMaxSets];  // filled by launch_adam_sets
+  int n;
+};
+void launch_adam_sets(AdamSets a, float lr, float b1, float b2, float eps, float c1, float c2,
+                      hipStream_t s);
 void launch_cvt_bf16(const float* p, uint16_t* p16, int64_t count, hipStream_t s);
 void launch_proposal(const Pools& pl, int n_inst, const float* Y, int ldy, const int32_t* eligible,
                      hipStream_t s);

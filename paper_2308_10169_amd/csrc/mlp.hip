@@ -237,22 +237,23 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int
   if (w == 0 && j < n) out[j] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
-// Adam on FP32 master weights (rows x cols with `cols` real columns stored
-// at stride `ld`), refreshing the BF16 copy used by the GEMMs.
-__global__ __launch_bounds__(256) void adam_kernel(float* p, const float* g, float* m, float* v,
-                                                   uint16_t* p16, int64_t count, float lr,
-                                                   float b1, float b2, float eps, float c1,
-                                                   float c2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  p[i] = pi;
-  if (p16) p16[i] = to_bf16(pi);
+// Adam on FP32 master weights, refreshing the BF16 copies used by the GEMMs,
+// over up to kAdamMaxSets parameter tensors in one launch: block b belongs
+// to the set whose block range holds it.
+__global__ __launch_bounds__(256) void adam_sets_kernel(AdamSets a, float lr, float b1, float b2,
+                                                        float eps, float c1, float c2) {
+  int k = 0;
+  while (k + 1 < a.n && (int64_t)blockIdx.x >= a.first_block[k + 1]) ++k;
+  const int64_t i = ((int64_t)blockIdx.x - a.first_block[k]) * blockDim.x + threadIdx.x;
+  if (i >= a.count[k]) return;
+  const float gi = a.g[k][i];
+  const float mi = b1 * a.m[k][i] + (1.f - b1) * gi;
+  const float vi = b2 * a.v[k][i] + (1.f - b2) * gi * gi;
+  a.m[k][i] = mi;
+  a.v[k][i] = vi;
+  const float pi = a.p[k][i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  a.p[k][i] = pi;
+  if (a.p16[k]) a.p16[k][i] = to_bf16(pi);
 }
 
 __global__ __launch_bounds__(256) void cvt_bf16_kernel(const float* p, uint16_t* p16, int64_t count) {
@@ -296,7 +297,8 @@ void launch_raster(const Pools& pl, int n_inst, uint16_t* X, int ldx, int32_t* e
 void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_t* B, int ldb,
                  int M, int N, int K, const Epi& ep, float* ws, int64_t ws_floats, hipStream_t s) {
   // Split K while the tile grid leaves most CUs idle, as far as the k-steps
-  // and the workspace allow.
+  // and the workspace allow (measured: even two-step slices pay for their
+  // slice sum at the training shapes).
   const int tiles = ((N + 63) / 64) * ((M + 63) / 64), steps = K / 32;
   int S = 1;
   while (S < 8 && tiles * S * 2 <= 256 && S * 2 <= steps &&
@@ -338,10 +340,16 @@ void launch_colsum(const float* dz, int B, int n, float* out, hipStream_t s) {
   hipLaunchKernelGGL(colsum_kernel, dim3((n + 63) / 64), dim3(256), 0, s, dz, B, n, out);
 }
 
-void launch_adam(float* p, const float* g, float* m, float* v, uint16_t* p16, int64_t count,
-                 float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, g, m, v,
-                     p16, count, lr, b1, b2, eps, c1, c2);
+void launch_adam_sets(AdamSets a, float lr, float b1, float b2, float eps, float c1, float c2,
+                      hipStream_t s) {
+  int64_t blocks = 0;
+  for (int k = 0; k < a.n; ++k) {
+    a.first_block[k] = blocks;
+    blocks += (a.count[k] + 255) / 256;
+  }
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(adam_sets_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, lr, b1, b2, eps,
+                     c1, c2);
 }
 
 void launch_cvt_bf16(const float* p, uint16_t* p16, int64_t count, hipStream_t s) {
