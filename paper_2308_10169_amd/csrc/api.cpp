@@ -190,7 +190,7 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
     L.sumG += G;
     L.sumGD += (int64_t)G * D;
     L.sumD += D;
-    L.initBlocks += (P * D + 255) / 256;
+    L.initBlocks += (P * ((D + 3) / 4) + 255) / 256;  // one init thread per 4 coordinates
   }
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -504,8 +504,8 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
       hyper[6 * d.go + j] = sw[i].hyper[j];
       ohyper[6 * d.go + j] = sw[i].hsef_hyper ? sw[i].hsef_hyper[j] : kHyper8[(j / 6) % 8][j % 6];
     }
-    const int64_t PD = (int64_t)d.G * d.N * 2 * d.W;
-    for (int64_t e = 0; e < PD; e += 256) blki.push_back(make_int2(i, (int)e));
+    const int64_t PQ4 = (int64_t)d.G * d.N * ((2 * d.W + 3) / 4);  // coordinate quads
+    for (int64_t q = 0; q < PQ4; q += 256) blki.push_back(make_int2(i, (int)q));
     b->path_off[i + 1] = b->path_off[i] + 2 * d.W;
   }
   b->h_pptr.assign(pptr.begin(), pptr.begin() + b->desc[0].n_polys + 1);

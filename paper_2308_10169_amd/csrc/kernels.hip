@@ -117,43 +117,53 @@ __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
 // ---------------------------------------------------------------------------
 // Init: X ~ U(box), V ~ U(+-vmax); with a previous plan, the first n_pi
 // particles of every group are drawn within +-radius of it (Priori
-// Initialization).  Counter (particle*ceil(D/4) + d/4, frame, instance, tag).
+// Initialization).  Counter (particle*ceil(D/4) + d/4, frame, instance, tag),
+// output d mod 4: one thread per quad of coordinates d = 4q..4q+3 of a
+// particle makes each of its Philox calls once for all four.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void init_kernel(Pools pl, int frame_override, int use_prev) {
   const int2 bi = pl.blk_init[blockIdx.x];
   const int inst = bi.x;
   const InstDesc d = pl.desc[inst];  // by value: stores cannot make it reload
   InstCtl* ctl = pl.ctl + inst;
-  const int W = d.W, D = 2 * W;
-  const int64_t PD = (int64_t)d.G * d.N * D;
-  const int64_t e = (int64_t)bi.y + threadIdx.x;
+  const int W = d.W, D = 2 * W, DQ = (D + 3) / 4;
+  const int nq = d.G * d.N * DQ;
+  const int q = bi.y + (int)threadIdx.x;
   const int frame = frame_override >= 0 ? frame_override : ctl->frame;
   const bool learned = use_prev && ctl->use_learned;
   const bool pi = !learned && use_prev && d.use_pi && ctl->have_prev;
-  if (e < PD) {
-    const int i = (int)(e / D), dd = (int)(e - (int64_t)i * D);
+  if (q < nq) {
+    const int i = q / DQ, d0 = 4 * (q - i * DQ);
     const int g = i / d.N, n = i - g * d.N;
-    const float hi = dd < W ? d.width : d.height;
     const float vl = pl.hyper[d.go * 6 + g * 6 + 5];
-    const float vmax = vl * hi * 0.5f;
-    const uint32_t c0 = (uint32_t)(i * ((D + 3) / 4) + dd / 4);
+    const uint32_t c0 = (uint32_t)q;  // = i * ceil(D/4) + d0/4
     const U4 rx = philox(c0, (uint32_t)frame, d.instance, TAG_INIT_X, d.seed_lo, d.seed_hi);
     const U4 rv = philox(c0, (uint32_t)frame, d.instance, TAG_INIT_V, d.seed_lo, d.seed_hi);
-    float x = u01(rx.v[dd & 3]) * hi;
-    if ((pi || learned) && n < d.n_pi) {
-      // Priori Initialization around the previous plan, or around this
-      // group's learned proposal when the network supplied one
-      const U4 rp = philox(c0, (uint32_t)frame, d.instance, TAG_PI, d.seed_lo, d.seed_hi);
-      const float r = d.pi_radius;
-      const float c = learned ? pl.proposal[d.gpo + g * D + dd] : pl.prev_path[d.dpo + dd];
-      x = clampf(c + (-r + u01(rp.v[dd & 3]) * (2.f * r)), 0.f, hi);
+    const bool near = (pi || learned) && n < d.n_pi;
+    U4 rp{};
+    if (near) rp = philox(c0, (uint32_t)frame, d.instance, TAG_PI, d.seed_lo, d.seed_hi);
+    const int64_t o = d.xo + (int64_t)i * D + d0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int dd = d0 + u;
+      if (dd < D) {
+        const float hi = dd < W ? d.width : d.height;
+        const float vmax = vl * hi * 0.5f;
+        float x = u01(rx.v[u]) * hi;
+        if (near) {
+          // Priori Initialization around the previous plan, or around this
+          // group's learned proposal when the network supplied one
+          const float r = d.pi_radius;
+          const float c = learned ? pl.proposal[d.gpo + g * D + dd] : pl.prev_path[d.dpo + dd];
+          x = clampf(c + (-r + u01(rp.v[u]) * (2.f * r)), 0.f, hi);
+        }
+        const float v = -vmax + u01(rv.v[u]) * (2.f * vmax);
+        pl.X[o + u] = x;
+        pl.V[o + u] = v;
+        pl.P[o + u] = x;
+      }
     }
-    const float v = -vmax + u01(rv.v[dd & 3]) * (2.f * vmax);
-    const int64_t o = d.xo + e;
-    pl.X[o] = x;
-    pl.V[o] = v;
-    pl.P[o] = x;
-    if (dd == 0) {
+    if (d0 == 0) {
       const int64_t po = d.po + i;
       pl.f[po] = INFINITY;
       pl.L[po] = INFINITY;
