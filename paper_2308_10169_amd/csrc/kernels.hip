@@ -143,25 +143,36 @@ __global__ __launch_bounds__(256) void init_kernel(Pools pl, int frame_override,
     U4 rp{};
     if (near) rp = philox(c0, (uint32_t)frame, d.instance, TAG_PI, d.seed_lo, d.seed_hi);
     const int64_t o = d.xo + (int64_t)i * D + d0;
+    float xq[4], vq[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int dd = d0 + u;
-      if (dd < D) {
-        const float hi = dd < W ? d.width : d.height;
-        const float vmax = vl * hi * 0.5f;
-        float x = u01(rx.v[u]) * hi;
-        if (near) {
-          // Priori Initialization around the previous plan, or around this
-          // group's learned proposal when the network supplied one
-          const float r = d.pi_radius;
-          const float c = learned ? pl.proposal[d.gpo + g * D + dd] : pl.prev_path[d.dpo + dd];
-          x = clampf(c + (-r + u01(rp.v[u]) * (2.f * r)), 0.f, hi);
-        }
-        const float v = -vmax + u01(rv.v[u]) * (2.f * vmax);
-        pl.X[o + u] = x;
-        pl.V[o + u] = v;
-        pl.P[o + u] = x;
+      const int dd = min(d0 + u, D - 1);  // lanes past the particle's end compute, never store
+      const float hi = dd < W ? d.width : d.height;
+      const float vmax = vl * hi * 0.5f;
+      float x = u01(rx.v[u]) * hi;
+      if (near) {
+        // Priori Initialization around the previous plan, or around this
+        // group's learned proposal when the network supplied one
+        const float r = d.pi_radius;
+        const float c = learned ? pl.proposal[d.gpo + g * D + dd] : pl.prev_path[d.dpo + dd];
+        x = clampf(c + (-r + u01(rp.v[u]) * (2.f * r)), 0.f, hi);
       }
+      xq[u] = x;
+      vq[u] = -vmax + u01(rv.v[u]) * (2.f * vmax);
+    }
+    if (d0 + 4 <= D && (o & 3) == 0) {  // a whole quad at a 16-byte boundary (pools are)
+      const float4 x4 = make_float4(xq[0], xq[1], xq[2], xq[3]);
+      *reinterpret_cast<float4*>(pl.X + o) = x4;
+      *reinterpret_cast<float4*>(pl.V + o) = make_float4(vq[0], vq[1], vq[2], vq[3]);
+      *reinterpret_cast<float4*>(pl.P + o) = x4;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (d0 + u < D) {
+          pl.X[o + u] = xq[u];
+          pl.V[o + u] = vq[u];
+          pl.P[o + u] = xq[u];
+        }
     }
     if (d0 == 0) {
       const int64_t po = d.po + i;
@@ -381,6 +392,13 @@ __global__ __launch_bounds__(512) void reduce_kernel(Pools pl, int flags) {
   __syncthreads();
   const int tg = s_tg, tn = s_gn[tg];
   const float tf = s_gf[tg];
+  // Tbest's crossing count and length, read alongside the row copies
+  int tq = 0;
+  float tl = 0.f;
+  if ((flags & STEP_FRAME) && t == 0) {
+    tq = pl.PQ[d.po + tg * N + tn];
+    tl = pl.PL[d.po + tg * N + tn];
+  }
   const float* P = pl.P + d.xo;
   for (int e = t; e < G * D; e += blockDim.x) {
     const int g = e / D, dd = e - g * D;
@@ -394,11 +412,10 @@ __global__ __launch_bounds__(512) void reduce_kernel(Pools pl, int flags) {
     if (t == 0) {
       ctl->hist[(k_new - 1) % kHist] = tf;
       s_hist[(k_new - 1) % kHist] = tf;
-      const int q = pl.PQ[d.po + tg * N + tn];
-      const bool a = at_fires(s_hist, k_new, d.at_mode, d.at_window, d.at_delta, q);
+      const bool a = at_fires(s_hist, k_new, d.at_mode, d.at_window, d.at_delta, tq);
       s_at = a;
       s_stop = a || k_new >= d.T;
-      s_q = q;
+      s_q = tq;
     }
     __syncthreads();
     stop = s_stop;
@@ -419,7 +436,7 @@ __global__ __launch_bounds__(512) void reduce_kernel(Pools pl, int flags) {
       ctl->ctr = ctr_new + 1u;
       ctl->truncated = at;
       ctl->res_cost = tf;
-      ctl->res_len = pl.PL[d.po + tg * N + tn];
+      ctl->res_len = tl;
       ctl->res_q = s_q;
       ctl->res_iters = k_new;
       ctl->res_trunc = at;
