@@ -58,8 +58,10 @@ def test_frame_result_is_consistent(sp):
     pl.close()
 
 
-def test_priori_initialization(sp):
-    spec, sw = _small_dyn(3)
+@pytest.mark.parametrize("waypoints", [10, 9])  # D % 4 == 0 and 2
+def test_priori_initialization(sp, waypoints):
+    spec = I.dynamic_map(3)
+    sw = I.dynamic_swarm(spec.scale, seed=3, particles=48, waypoints=waypoints)
     pl = sp.Planner(spec, sw)
     r = pl.plan_frame()
     pl.reinit(frame=1, use_prev=True)

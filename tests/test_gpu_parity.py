@@ -31,11 +31,12 @@ def _run_injected(sp, spec, sw, steps, stats=None):
     pl.close()
 
 
-def test_init_draws_bit_exact(sp):
+@pytest.mark.parametrize("waypoints", [8, 7, 9])  # D % 4 == 0, and 2: rows off 16-byte boundaries
+def test_init_draws_bit_exact(sp, waypoints):
     # X0 = u * hi with u a 24-bit Philox uniform: the FP32 product is the
     # correctly rounded exact product, so it must equal the oracle's value
     # rounded to FP32 -- any differing random word would show.
-    spec, sw = I.static_map(0), I.static_swarm(seed=12345)
+    spec, sw = I.static_map(0), I.static_swarm(seed=12345, waypoints=waypoints)
     pl = sp.Planner(spec, sw)
     st = pl.get_state()
     o = orc.Swarm(sw, spec.width, spec.height)
