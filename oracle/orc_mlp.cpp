@@ -1,7 +1,8 @@
 // SEPSO oracle, learned initializer: FP64 forward and backward of the
 // path-proposal MLP (Linear-ReLU stack, linear output, mean squared error),
 // with optional rounding to BF16 at the points where the device stores
-// BF16 values.  TEST INFRASTRUCTURE ONLY (see orc.h).  Plain loops.
+// BF16 values, and the Adam step that trains it.  TEST INFRASTRUCTURE ONLY
+// (see orc.h).  Plain loops.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -120,6 +121,26 @@ void orc_raster(double width, double height, int32_t n_polys, const int32_t* pol
       }
       out[r * n + c] = inside;
     }
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// One step of Adam (Kingma and Ba, "Adam: A Method for Stochastic
+// Optimization", ICLR 2015, Algorithm 1) over n parameters, in FP64: the
+// moment estimates m, v are updated in place, t is the 1-based step index
+// used by the bias corrections, and each parameter moves by
+//   -lr * m_hat / (sqrt(v_hat) + eps),  m_hat = m / (1 - b1^t),  v_hat = v / (1 - b2^t).
+void orc_adam_step(int64_t n, double* p, const double* g, double* m, double* v, int32_t t,
+                   double lr, double b1, double b2, double eps) {
+  const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    const double mh = m[i] / c1, vh = v[i] / c2;
+    p[i] -= lr * mh / (std::sqrt(vh) + eps);
+  }
 }
 
 }  // extern "C"

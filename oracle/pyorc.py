@@ -354,6 +354,20 @@ def mlp(sizes, W, b, x, target=None, round=True, grads=True):
                 gW=gW if do_g else None, gb=gb if do_g else None)
 
 
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One FP64 Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) in place on
+    p, m, v (float64 arrays of one shape); t is the 1-based step index."""
+    L = lib()
+    L.orc_adam_step.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_int32, C.c_double, C.c_double,
+                                C.c_double, C.c_double]
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    gc = np.ascontiguousarray(g, dtype=np.float64)
+    assert gc.size == p.size == m.size == v.size
+    L.orc_adam_step(p.size, _p(p), _p(gc), _p(m), _p(v), int(t), float(lr), float(b1), float(b2),
+                    float(eps))
+
+
 def raster(spec, n=64):
     L = lib()
     ptr = np.ascontiguousarray(spec.poly_ptr, dtype=np.int32)
@@ -364,6 +378,20 @@ def raster(spec, n=64):
                  int(n), _p(out))
     return out
 
+
+# Table hyper8 (the paper's DTPSO / H-SEPSO defaults): rows = groups,
+# columns = C1, C2, C3, w_init, w_end, V_limit.  The oracle's own copy of the
+# printed table (tests check it against tests/golden/table_hyper8.txt).
+HYPER8 = np.array([
+    [2, 1, 1, 0.4, 0.2, 0.2],
+    [1, 1, 2, 0.7, 0.3, 0.1],
+    [2, 2, 1, 0.8, 0.1, 0.6],
+    [2, 2, 1, 0.8, 0.6, 0.4],
+    [2, 1, 2, 0.2, 0.1, 0.3],
+    [2, 1, 2, 0.9, 0.5, 0.5],
+    [1, 2, 2, 0.4, 0.1, 0.8],
+    [1, 2, 2, 0.9, 0.3, 0.3],
+], dtype=np.float64)
 
 # Default per-column box of the evolved hyper-parameters (C1, C2, C3, w_init,
 # w_end, V_limit); the paper does not state one.
@@ -383,11 +411,10 @@ class Evolve:
     def __init__(self, spec, lsw, h_groups=8, h_particles=4, evolutions=500, seed=0,
                  h_hyper=None, lo=None, hi=None):
         import dataclasses
-        from paper_2308_10169_amd import inputs as I
         Gl = lsw.groups
         self.Gh, self.Nh, self.Dh = h_groups, h_particles, 6 * Gl
         n = h_groups * h_particles
-        hh = I.HYPER8[np.arange(h_groups) % 8] if h_hyper is None else h_hyper
+        hh = HYPER8[np.arange(h_groups) % 8] if h_hyper is None else h_hyper
         self.h_hyper = np.ascontiguousarray(hh, dtype=np.float64).reshape(h_groups, 6).copy()
         self.lo = np.ascontiguousarray(EVOLVE_LO if lo is None else lo, dtype=np.float64).copy()
         self.hi = np.ascontiguousarray(EVOLVE_HI if hi is None else hi, dtype=np.float64).copy()

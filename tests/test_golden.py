@@ -27,8 +27,9 @@ def test_philox_known_answers(orc):
         assert [int(x) for x in out] == v[6:]
 
 
-def test_hyper_tables_as_printed():
+def test_hyper_tables_as_printed(orc):
     assert np.array_equal(I.HYPER8, np.array(_rows("table_hyper8.txt"), float))
+    assert np.array_equal(orc.HYPER8, np.array(_rows("table_hyper8.txt"), float))
     assert np.array_equal(I.HYPER8PATH, np.array(_rows("table_hyper8path.txt"), float))
     a, b, g, dlt, tw = _rows("table_params_path.txt")[0]
     pp = I.PARAMS_PATH

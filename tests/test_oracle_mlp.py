@@ -88,3 +88,51 @@ def test_raster_of_rectangle_and_u_shape(orc):
     inside = lambda x, y: (20 < x < 80 and 20 < y < 80) and not (40 < x < 60 and y > 40)
     want = np.array([[inside(x, y) for x in c] for y in c])
     assert np.array_equal(r.astype(bool), want)
+
+
+def _adam_run(orc, p0, grads, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    p = np.array(p0, dtype=np.float64)
+    m, v = np.zeros_like(p), np.zeros_like(p)
+    out = []
+    for t, g in enumerate(grads, start=1):
+        orc.adam_step(p, np.asarray(g, np.float64), m, v, t, lr, b1, b2, eps)
+        out.append(p.copy())
+    return out
+
+
+def test_adam_first_step_closed_form(orc):
+    # From zero moments the bias-corrected estimates are g and g^2, so the
+    # first step moves every weight by -lr * g / (|g| + eps).
+    rng = np.random.default_rng(0)
+    p0 = rng.normal(0, 1, 500)
+    g = np.r_[rng.normal(0, 1, 400), rng.normal(0, 1e-9, 50), np.zeros(50)]
+    lr, eps = 3e-3, 1e-8
+    (p1,) = _adam_run(orc, p0, [g], lr=lr, eps=eps)
+    assert np.allclose(p1, p0 - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    assert np.array_equal(p1[-50:], p0[-50:])  # zero gradient: no move
+
+
+def test_adam_constant_gradient(orc):
+    # A constant gradient keeps m_hat = g and v_hat = g^2 at every step (the
+    # bias corrections undo the moments' warm-up exactly), so each step
+    # moves by the same -lr * g / (|g| + eps).
+    rng = np.random.default_rng(1)
+    p0 = rng.normal(0, 1, 300)
+    g = rng.normal(0, 2, 300)
+    steps = _adam_run(orc, p0, [g] * 6, lr=1e-2)
+    d = 1e-2 * g / (np.abs(g) + 1e-8)
+    for t, p in enumerate(steps, start=1):
+        assert np.allclose(p, p0 - t * d, rtol=0, atol=1e-13), t
+
+
+def test_adam_sign_flip(orc):
+    # g then -g: m_2 = -(1 - b1)^2 g and v_2 = (1 - b2)(1 + b2) g^2, so with
+    # the step-2 corrections m_hat = -(1 - b1) g / (1 + b1), v_hat = g^2 and
+    # the second step moves by +lr (1 - b1) / (1 + b1) * g / (|g| + eps).
+    rng = np.random.default_rng(2)
+    p0 = rng.normal(0, 1, 200)
+    g = rng.normal(0, 1, 200)
+    lr, b1, b2 = 5e-3, 0.8, 0.99
+    p1, p2 = _adam_run(orc, p0, [g, -g], lr=lr, b1=b1, b2=b2)
+    step2 = lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p2 - p1, step2, rtol=0, atol=1e-14)
