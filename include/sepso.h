@@ -104,7 +104,8 @@ typedef struct sepso_frame_result {
   int32_t crossings;   /* Q of the returned path */
   int32_t iters;       /* iterations run in this frame */
   int32_t truncated;   /* Auto Truncation fired */
-  int32_t used_learned;/* reserved: 0 */
+  int32_t used_learned;/* 1: the attached learned initializer's proposal seeded this
+                          frame's Priori Initialization; 0: plain PI or uniform */
   float device_ms;     /* device time of the frame (0 when batched) */
 } sepso_frame_result;
 
@@ -135,6 +136,33 @@ typedef struct sepso_tune {
 typedef struct sepso_ctx sepso_ctx;
 typedef struct sepso_batch sepso_batch;
 
+/* ---- path fitness --------------------------------------------------------
+ * Fitness of given paths on a polygonal map (Eq.(11)-(13), Sec. "Map
+ * representation"): path r is [start, w_1..w_W, target] with the waypoints
+ * in the Eq.(10) layout, paths[r*2W + i] = x_{i+1}, paths[r*2W + W + i] =
+ * y_{i+1}; L = sum of the W+1 segment lengths; Q = number of proper
+ * crossings (both pairs of orientations strictly of opposite sign; touching
+ * and collinear contacts do not count) of the segments with every polygon
+ * edge (v_j, v_{j+1}), the last vertex joined to the first; F = L +
+ * alpha * Q^beta.  FP32 throughout.
+ * Device inputs: poly_ptr (n_polys+1 int32 vertex offsets, non-decreasing,
+ * poly_ptr[0] = 0, poly_ptr[n_polys] = n_vert), verts (n_vert (x, y)
+ * pairs), ends (4 floats: start x, y, target x, y), paths (n_paths x 2W).
+ * Device outputs: f, L (n_paths floats), Q (n_paths int32).  The workspace
+ * (size from sepso_fitness_workspace_bytes, 256-byte aligned) holds the
+ * edge records and per-segment partial results; it is free again when the
+ * work has completed.  Asynchronous on stream (NULL = the default stream);
+ * n_paths = 0 launches nothing.  1 <= waypoints <= 64, beta >= 1, alpha
+ * finite, n_paths * (W + 1) < 2^31, else SEPSO_E_ARG; a workspace that is
+ * too small gives SEPSO_E_NOMEM; a launch failure gives SEPSO_E_HIP. */
+sepso_status sepso_fitness_workspace_bytes(int32_t n_vert, int32_t n_paths, int32_t waypoints,
+                                           size_t* bytes);
+sepso_status sepso_fitness(int32_t n_polys, int32_t n_vert, const int32_t* d_poly_ptr,
+                           const float* d_verts, const float* d_ends, const float* d_paths,
+                           int32_t n_paths, int32_t waypoints, float alpha, int32_t beta,
+                           float* d_f, float* d_L, int32_t* d_Q, void* d_workspace,
+                           size_t workspace_bytes, void* stream);
+
 /* ---- single instance ---------------------------------------------------- */
 sepso_status sepso_workspace_bytes(const sepso_map* map, const sepso_swarm* swarm, size_t* bytes);
 
@@ -155,6 +183,27 @@ sepso_status sepso_step(sepso_ctx* ctx, int32_t n);
  * writes *out and the plan's 2W path values to out_path (may be NULL). */
 sepso_status sepso_plan_frame(sepso_ctx* ctx, const sepso_map* next, sepso_frame_result* out,
                               float* out_path);
+
+/* n iterations of the current frame as sepso_plan_frame runs them: bests
+ * with Auto Truncation and, every hsef_every iterations, the online outer
+ * step (Sec. "HSEF"), up to max_iters; once the frame has ended (truncated
+ * or at max_iters) further calls do nothing until sepso_reinit or
+ * sepso_set_state.  The last iteration's update is applied before the call
+ * returns, as in sepso_step.  Asynchronous. */
+sepso_status sepso_step_frame(sepso_ctx* ctx, int32_t n);
+
+/* Online self-evolution state (Sec. "HSEF"): outer particle g is group g's
+ * (w_init, C1, C2); ov, op (G x 3 in that order) are its velocity and best
+ * position, opf (G) its best fitness; otb the outer total best, epoch_in_frame
+ * the outer steps of this frame (inertia schedule position), epoch_ctr the
+ * outer random-stream position.  Any array may be NULL.  Synchronous. */
+typedef struct sepso_outer {
+  float *ov, *op, *opf;
+  int32_t otb, epoch_in_frame;
+  uint32_t epoch_ctr;
+} sepso_outer;
+sepso_status sepso_get_outer(sepso_ctx* ctx, sepso_outer* o);
+sepso_status sepso_set_outer(sepso_ctx* ctx, const sepso_outer* o);
 
 /* Re-initialise the swarm for frame index `frame` (uniform; with
  * use_prev != 0 and PI enabled, Priori Initialization from the last plan).

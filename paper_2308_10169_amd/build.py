@@ -31,7 +31,7 @@ def _run(cmd):
     return r
 
 
-DEVICE_SOURCES = ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "rng.h", "common.h", "kernels.h", "mlp.h")
+DEVICE_SOURCES = ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "fitness.hip", "rng.h", "common.h", "kernels.h", "mlp.h")
 
 
 def kernels_id() -> str:
@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     objs = []
     kid = kernels_id()
-    for src in ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "api.cpp", "lin.cpp"):
+    for src in ("kernels.hip", "mlp.hip", "bf.hip", "philox.hip", "fitness.hip", "api.cpp", "lin.cpp"):
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         cmd = [hipcc] + HIPFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):

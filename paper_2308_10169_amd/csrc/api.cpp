@@ -751,6 +751,70 @@ sepso_status sepso_step(sepso_ctx* ctx, int32_t n) {
   return step_batch(ctx->b, n);
 }
 
+sepso_status sepso_step_frame(sepso_ctx* ctx, int32_t n) {
+  if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < n && e == hipSuccess; ++k)
+    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
+                    STEP_FIT | STEP_FRAME, b->stream);
+  if (n > 0 && e == hipSuccess)  // the pending update (nothing once the frame has ended)
+    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
+                    STEP_FRAME, b->stream);
+  if (e != hipSuccess) return hip_fail(b, e, "step launch");
+  LAUNCHCHK(b, "step launch");
+  return SEPSO_OK;
+}
+
+sepso_status sepso_get_outer(sepso_ctx* ctx, sepso_outer* o) {
+  if (!ctx || !o) return fail(SEPSO_E_ARG, "ctx/outer is NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status s = usable(b);
+  if (s != SEPSO_OK) return s;
+  const InstDesc& d = b->desc[0];
+  auto d2h = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!dst) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, b->stream);
+  };
+  HIPCHK(b, d2h(o->ov, b->pl.ov + 3 * d.go, 12 * (size_t)d.G));
+  HIPCHK(b, d2h(o->op, b->pl.op + 3 * d.go, 12 * (size_t)d.G));
+  HIPCHK(b, d2h(o->opf, b->pl.opf + d.go, 4 * (size_t)d.G));
+  HIPCHK(b, hipMemcpyAsync(b->h_ctl, b->pl.ctl, sizeof(InstCtl), hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  o->otb = b->h_ctl[0].otb;
+  o->epoch_in_frame = b->h_ctl[0].epoch_in_frame;
+  o->epoch_ctr = b->h_ctl[0].epoch_ctr;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_set_outer(sepso_ctx* ctx, const sepso_outer* o) {
+  if (!ctx || !o) return fail(SEPSO_E_ARG, "ctx/outer is NULL");
+  sepso_batch* b = ctx->b;
+  sepso_status s = usable(b);
+  if (s != SEPSO_OK) return s;
+  const InstDesc& d = b->desc[0];
+  if (o->otb < 0 || o->otb >= d.G || o->epoch_in_frame < 0)
+    return fail(SEPSO_E_ARG, "set_outer: otb or epoch_in_frame out of range");
+  auto h2d = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!src) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream);
+  };
+  HIPCHK(b, h2d(b->pl.ov + 3 * d.go, o->ov, 12 * (size_t)d.G));
+  HIPCHK(b, h2d(b->pl.op + 3 * d.go, o->op, 12 * (size_t)d.G));
+  HIPCHK(b, h2d(b->pl.opf + d.go, o->opf, 4 * (size_t)d.G));
+  HIPCHK(b, hipMemcpyAsync(b->h_ctl, b->pl.ctl, sizeof(InstCtl), hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  b->h_ctl[0].otb = o->otb;
+  b->h_ctl[0].epoch_in_frame = o->epoch_in_frame;
+  b->h_ctl[0].epoch_ctr = o->epoch_ctr;
+  HIPCHK(b, hipMemcpyAsync(b->pl.ctl, b->h_ctl, sizeof(InstCtl), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
 sepso_status sepso_reinit(sepso_ctx* ctx, int32_t frame, int32_t use_prev) {
   if (!ctx) return fail(SEPSO_E_ARG, "ctx is NULL");
   sepso_batch* b = ctx->b;

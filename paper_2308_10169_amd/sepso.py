@@ -58,6 +58,11 @@ class CState(C.Structure):
                 ("k", C.c_int32), ("ctr", C.c_uint32), ("frame", C.c_int32)]
 
 
+class COuter(C.Structure):
+    _fields_ = [("ov", fp), ("op", fp), ("opf", fp), ("otb", C.c_int32),
+                ("epoch_in_frame", C.c_int32), ("epoch_ctr", C.c_uint32)]
+
+
 class CTune(C.Structure):
     _fields_ = [("seg_per_thread", C.c_int32), ("block_threads", C.c_int32)]
 
@@ -108,6 +113,9 @@ def _load():
     L.sepso_destroy.argtypes = [vp]
     L.sepso_step.argtypes = [vp, C.c_int32]
     L.sepso_reinit.argtypes = [vp, C.c_int32, C.c_int32]
+    L.sepso_step_frame.argtypes = [vp, C.c_int32]
+    L.sepso_get_outer.argtypes = [vp, C.POINTER(COuter)]
+    L.sepso_set_outer.argtypes = [vp, C.POINTER(COuter)]
     L.sepso_plan_frame.argtypes = [vp, C.POINTER(CMap), C.POINTER(CFrameResult), fp]
     L.sepso_get_state.argtypes = [vp, C.POINTER(CState)]
     L.sepso_set_state.argtypes = [vp, C.POINTER(CState)]
@@ -162,6 +170,9 @@ def _load():
     L.sepso_lin_features.argtypes = [vp, vp, fp]
     L.sepso_lin_attach.argtypes = [vp, vp]
     L.sepso_lin_attach_ctx.argtypes = [vp, vp]
+    L.sepso_fitness_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(sz)]
+    L.sepso_fitness.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_int32, C.c_int32,
+                                C.c_float, C.c_int32, vp, vp, vp, vp, sz, vp]
     _lib, _torch = L, torch
     return L
 
@@ -182,6 +193,34 @@ def philox(first, c1, c2, c3, key, n):
                              C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
     st.synchronize()
     return out[:int(n)].cpu().numpy().view(np.uint32)
+
+
+def fitness(spec, paths, waypoints, alpha, beta):
+    """sepso_fitness on device copies of the map's polygons and endpoints
+    and of paths (n, 2W): returns dict(f, L, Q) as numpy arrays."""
+    _load()
+    torch = _torch
+    W = int(waypoints)
+    dev = "cuda"
+    pp = torch.from_numpy(np.ascontiguousarray(spec.poly_ptr, dtype=np.int32)).to(dev)
+    vv = torch.from_numpy(_f32(spec.verts).reshape(-1)).to(dev)
+    ee = torch.from_numpy(_f32(list(spec.start) + list(spec.target))).to(dev)
+    X = torch.from_numpy(_f32(paths).reshape(-1, 2 * W)).to(dev)
+    n = X.shape[0]
+    n_polys, n_vert = len(spec.poly_ptr) - 1, int(spec.poly_ptr[-1])
+    f = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    Lv = torch.empty_like(f)
+    Q = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream()
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    nbytes = C.c_size_t()
+    _check(_lib.sepso_fitness_workspace_bytes(n_vert, n, W, C.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+    _check(_lib.sepso_fitness(n_polys, n_vert, ptr(pp), ptr(vv), ptr(ee), ptr(X), n, W,
+                              float(alpha), int(beta), ptr(f), ptr(Lv), ptr(Q), ptr(ws),
+                              nbytes.value, C.c_void_p(st.cuda_stream)))
+    st.synchronize()
+    return dict(f=f[:n].cpu().numpy(), L=Lv[:n].cpu().numpy(), Q=Q[:n].cpu().numpy())
 
 
 def _check(st):
@@ -275,6 +314,27 @@ class Planner:
 
     def step(self, n=1):
         _check(_lib.sepso_step(self.h, int(n)))
+
+    def step_frame(self, n=1):
+        """n iterations of the current frame (AT and online HSEF included)."""
+        _check(_lib.sepso_step_frame(self.h, int(n)))
+
+    def get_outer(self):
+        G = self.sw.groups
+        o = dict(ov=np.zeros((G, 3), np.float32), op=np.zeros((G, 3), np.float32),
+                 opf=np.zeros(G, np.float32))
+        c = COuter(o["ov"].ctypes.data_as(fp), o["op"].ctypes.data_as(fp),
+                   o["opf"].ctypes.data_as(fp), 0, 0, 0)
+        _check(_lib.sepso_get_outer(self.h, C.byref(c)))
+        o.update(otb=c.otb, epoch_in_frame=c.epoch_in_frame, epoch_ctr=c.epoch_ctr)
+        return o
+
+    def set_outer(self, o):
+        a = {k: np.ascontiguousarray(o[k], dtype=np.float32) for k in ("ov", "op", "opf")}
+        c = COuter(a["ov"].ctypes.data_as(fp), a["op"].ctypes.data_as(fp),
+                   a["opf"].ctypes.data_as(fp), int(o["otb"]), int(o["epoch_in_frame"]),
+                   int(o["epoch_ctr"]))
+        _check(_lib.sepso_set_outer(self.h, C.byref(c)))
 
     def reinit(self, frame=0, use_prev=False):
         _check(_lib.sepso_reinit(self.h, int(frame), int(bool(use_prev))))

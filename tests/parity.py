@@ -79,3 +79,48 @@ def check_step(o, m, st0, st1, S, stats=None):
     # Pbest positions: those that improved this iteration equal st0's X
     assert np.array_equal(st1["P"], o.P.astype(np.float32)), "Pbest positions"
     assert st1["k"] == o.s.k and st1["ctr"] == o.s.ctr
+
+
+def check_frame_step(o, m, st0, st1, out0, out1, S, sample, hsef):
+    """One iteration of a frame (sepso_step_frame) of a large swarm, from the
+    GPU state st0 (outer-swarm state out0) to st1 / out1: the fitness of the
+    sampled particles against the oracle's; then, for every particle, the
+    oracle's bests on the GPU's FP32 fitness values, its online outer step
+    when one is due (Sec. HSEF: after the bests, before the update) and its
+    FP64 update."""
+    W, D = o.W, o.D
+    sub = lambda st: dict(X=st["X"].reshape(-1, D)[sample][None], Q=st["Q"].reshape(-1)[sample][None],
+                          L=st["L"].reshape(-1)[sample][None], f=st["f"].reshape(-1)[sample][None])
+    check_fitness(m, sub(st0), sub(st1), W, o.sw.alpha, o.sw.beta)
+    load_oracle(o, st0)
+    o.s.k = st0["k"] + 1
+    o.f[...] = st1["f"].astype(np.float64)
+    o.L[...] = st1["L"].astype(np.float64)
+    o.Q[...] = st1["Q"]
+    o.bests()
+    assert np.array_equal(o.Pf.astype(np.float32), st1["Pf"]), "Pbest fitness"
+    assert np.array_equal(o.gbest_n, st1["gbest_n"]), "group best index"
+    assert (o.s.tbest_g, o.s.tbest_n) == tuple(st1["tbest"][:2]), "total best index"
+    if hsef:
+        o.ov[...] = out0["ov"].astype(np.float64)
+        o.op[...] = out0["op"].astype(np.float64)
+        o.opf[...] = out0["opf"].astype(np.float64)
+        o.h.otb, o.h.epoch_in_frame, o.h.epoch_ctr = out0["otb"], out0["epoch_in_frame"], out0["epoch_ctr"]
+        o.hsef_step()
+        assert o.h.otb == out1["otb"] and o.h.epoch_in_frame == out1["epoch_in_frame"]
+        assert o.h.epoch_ctr == out1["epoch_ctr"]
+        assert np.array_equal(o.opf.astype(np.float32), out1["opf"]), "outer Pbest fitness"
+        assert np.array_equal(o.op.astype(np.float32), out1["op"]), "outer Pbest positions"
+        assert np.allclose(out1["ov"], o.ov, rtol=0, atol=1e-5), "outer velocities"
+        assert np.allclose(st1["hyper"], o.hyper, rtol=0, atol=1e-5), "evolved hyper-parameters"
+        assert not np.array_equal(st1["hyper"], st0["hyper"]), "the outer step moved nothing"
+    else:
+        assert np.array_equal(st1["hyper"], st0["hyper"])
+    o.update()
+    o.s.ctr += 1
+    dX = np.abs(st1["X"] - o.X)
+    dV = np.abs(st1["V"] - o.V)
+    assert np.all(dX <= REL * np.maximum(np.abs(o.X), S)), f"positions differ: max {dX.max()}"
+    assert np.all(dV <= REL * np.maximum(np.abs(o.V), S)), f"velocities differ: max {dV.max()}"
+    assert np.array_equal(st1["P"], o.P.astype(np.float32)), "Pbest positions"
+    assert st1["k"] == o.s.k and st1["ctr"] == o.s.ctr

@@ -197,3 +197,97 @@ def test_tune_cache(sp, tmp_path):
     c.close()
     lines = path.read_text().split("\n")[1:-1]
     assert len(lines) == 2 and lines[0].split()[0] != lines[1].split()[0]
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                    "frame_costs_dynamic366.txt")
+
+
+def test_paper_shaped_frames_match_oracle(sp):
+    # The paper-shaped dynamic run at full shape (366 map, 10 static + 20
+    # moving rectangles, 8 x 170 particles, W = 20, PI + AT mode 2 + online
+    # self-evolution every 10 iterations, <= 50 iterations): seeds 0-99, the
+    # first three frames, planned as one batch; the median cost of each frame
+    # over the seeds within 1% of the FP64 oracle's frame loop on the same
+    # seeds (tests/golden/frame_costs_dynamic366.txt, written by
+    # make_frame_costs.py from the oracle alone).
+    ref = np.loadtxt(GOLDEN)
+    seeds = np.unique(ref[:, 0]).astype(int)
+    specs = [I.dynamic_map(int(s)) for s in seeds]
+    sws = [I.dynamic_swarm(specs[0].scale, seed=int(s)) for s in seeds]
+    bp = sp.BatchPlanner(specs, sws)
+    res = bp.plan(3)
+    bp.close()
+    for f in range(3):
+        rows = ref[ref[:, 1] == f]
+        oc = rows[np.argsort(rows[:, 0]), 2]
+        gc = res["cost"][f]
+        mg, mo = np.median(gc), np.median(oc)
+        print(f"frame {f}: median cost gpu {mg:.3f} oracle {mo:.3f}; mean iterations "
+              f"{res['iters'][f].mean():.1f} / {rows[:, 3].mean():.1f}", flush=True)
+        assert abs(mg - mo) <= 0.01 * mo
+    assert abs(np.median(res["cost"]) - np.median(ref[:, 2])) <= 0.01 * np.median(ref[:, 2])
+
+
+def _at_case(sp, mode, window, delta, hist, q):
+    """Drives the planner's Auto Truncation with an injected Tbest history:
+    before iteration j the Pbest fitness of one particle is set to hist[j-1]
+    (every evaluated path costs more, so it stays the total best) with
+    crossing count q; returns the iteration at which the frame stopped (0 =
+    never) and the oracle's decision at every iteration."""
+    spec = I.dynamic_map(3)
+    sw = I.dynamic_swarm(spec.scale, seed=3, particles=16, waypoints=6, iters=63,
+                         at_mode=mode, hsef_every=0)
+    sw.at_window = window
+    sw.at_delta = float(np.float32(delta))
+    pl = sp.Planner(spec, sw)
+    st = pl.get_state()
+    frame0 = st["frame"]
+    fired = 0
+    orc_fire = []
+    for j, h in enumerate(hist, start=1):
+        Pf = np.full((sw.groups, sw.particles), np.inf, np.float32)
+        PQ = np.zeros((sw.groups, sw.particles), np.int32)
+        Pf[1, 2] = h
+        PQ[1, 2] = q
+        st.update(V=np.zeros_like(st["V"]), P=st["X"].copy(), Pf=Pf, PQ=PQ, k=j - 1,
+                  frame=frame0, tbest=(1, 2, float(h)))
+        pl.set_state(st)
+        pl.step_frame(1)
+        st = pl.get_state()
+        assert st["tbest"][:2] == (1, 2) and st["tbest"][2] == np.float32(h)
+        if st["frame"] != frame0 and not fired:
+            fired = j
+        orc_fire.append(bool(orc.at_check(np.asarray(hist[:j], np.float64), j, mode, window,
+                                          sw.at_delta, q)))
+    pl.close()
+    return fired, orc_fire
+
+
+def test_auto_truncation_injected_history(sp):
+    # Sec. Auto Truncation: the GPU's decision on an injected Tbest history
+    # against the oracle's on the same history, iteration by iteration, for
+    # the three criteria, with and without a collision on the best path.
+    u = 2.0 ** -17                       # spacing of FP32 values in [64, 128)
+    d32 = float(np.float32(1e-3))
+    thr = d32 * 64.0                     # the relative threshold at a best of 64 (exact)
+    m_lo = int(np.floor(thr / u))        # gaps just below and just above it
+    cases = [
+        (2, 5, 1e-3, [100, 95, 90, 85, 80, 75, 70, 69, 68.5, 68.4, 68.39, 68.389, 68.3889,
+                      68.3888, 68.3888, 68.3888, 68.3888], 0),
+        (2, 5, 1e-3, [64 + m_lo * u, 64, 64, 64, 64, 64, 64], 0),        # fires at k = 6
+        (2, 5, 1e-3, [64 + (m_lo + 1) * u, 64, 64, 64, 64, 64, 64], 0),  # not before k = 7
+        (2, 5, 1e-3, [50.0] * 12, 3),                                    # collision: never
+        (1, 20, 10.0, list(100.0 - 2.0 * np.minimum(np.arange(40), 24)), 0),
+        (3, 20, 10.0, list(100.0 - 25.0 * np.minimum(np.arange(30), 3)), 0),  # k = 22
+        (1, 20, 10.0, [30.0] * 25, 1),
+    ]
+    for mode, window, delta, hist, q in cases:
+        hist = [float(np.float32(h)) for h in hist]
+        fired, ref = _at_case(sp, mode, window, delta, hist, q)
+        want = ref.index(True) + 1 if True in ref else 0
+        print(f"AT mode {mode} window {window} q {q}: gpu stops at {fired}, oracle at {want}",
+              flush=True)
+        assert fired == want
+    # the designed threshold cases decide on the exact side of the threshold
+    assert _at_case(sp, *cases[1])[0] == 6 and _at_case(sp, *cases[2])[0] == 7

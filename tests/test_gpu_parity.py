@@ -6,7 +6,7 @@ import pytest
 from oracle import pyorc as orc
 from paper_2308_10169_amd import inputs as I
 
-from parity import check_fitness, check_step
+from parity import check_fitness, check_frame_step, check_step
 
 pytestmark = pytest.mark.gpu
 
@@ -273,3 +273,30 @@ def test_philox_stream_bit_exact(sp, first, c1, c2, c3, key):
     ctr[:, 1], ctr[:, 2], ctr[:, 3] = c1, c2, c3
     o = orc.philox_many(ctr, np.array([key & 0xFFFFFFFF, key >> 32], dtype=np.uint32))
     assert np.array_equal(g, o)
+
+
+def test_stress_frame_with_self_evolution(sp):
+    # Stress scene at full size (512 map, 500 rectangles + 100 quads = 2400
+    # edges, 400 of them general-polygon records: two LDS passes; 8 x 4096
+    # particles, W = 64) in a 200-iteration frame with the online outer step
+    # every 10 iterations: iterations 1, 50 and 150 checked by state
+    # injection -- fitness on 2048 sampled particles, bests, the outer step
+    # (due at 50 and 150) and the update of every particle.  By iteration 150
+    # the swarm has converged, so the wave culling is active.
+    spec = I.stress_map(0)
+    sw = I.SwarmSpec(8, 4096, 64, 200, I.HYPER8PATH, alpha=30.0, beta=4, seed=4, hsef_every=10)
+    pl = sp.Planner(spec, sw)
+    o = orc.Swarm(sw, spec.width, spec.height)
+    m = orc.Map(spec)
+    sample = np.sort(np.random.default_rng(2).choice(8 * 4096, 2048, replace=False))
+    done = 0
+    for it in (1, 50, 150):
+        pl.step_frame(it - 1 - done)
+        st0, out0 = pl.get_state(), pl.get_outer()
+        assert st0["k"] == it - 1
+        pl.step_frame(1)
+        st1, out1 = pl.get_state(), pl.get_outer()
+        print(f"stress frame iteration {it}: tbest {st1['tbest'][2]:.2f}", flush=True)
+        check_frame_step(o, m, st0, st1, out0, out1, spec.scale, sample, hsef=it % 10 == 0)
+        done = it
+    pl.close()
