@@ -134,8 +134,9 @@ void backward(sepso_lin* L, const uint16_t* X, const float* T, int B, float* los
 void adam(sepso_lin* L, float lr, hipStream_t s) {
   L->adam_t += 1;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float c1 = (float)(1.0 - std::pow(0.9, L->adam_t));
-  const float c2 = (float)(1.0 - std::pow(0.999, L->adam_t));
+  // bias corrections from the same (FP32) decay rates the moments use
+  const float c1 = (float)(1.0 - std::pow((double)b1, L->adam_t));
+  const float c2 = (float)(1.0 - std::pow((double)b2, L->adam_t));
   // all eight tensors (weights and biases of the four layers) in one launch
   AdamSets a{};
   for (int l = 0; l < 4; ++l) {

@@ -103,3 +103,41 @@ def test_learned_start_beats_plain_planner(sp):
     assert ev["median_iters_learned"] < ev["median_iters_plain"]
     assert ev["first_iter_cost_learned"] < ev["first_iter_cost_plain"]
     lin.close()
+
+
+def test_adam_matches_oracle(sp):
+    # Three Adam steps of the library's training (FP32 master weights,
+    # decay rates 0.9 / 0.999 and eps 1e-8 as FP32 values) against the
+    # oracle's FP64 Adam (Kingma and Ba, Algorithm 1) fed the same
+    # gradients, element by element over all 2.79M parameters.  The
+    # training set is one minibatch of 32 self-generated samples, so each
+    # step's gradient is the library's gradient at the current weights.
+    maps = I.random_static_maps(32, seed=21)
+    sws = [I.learned_swarm(seed=2, instance=i, iters=10) for i in range(32)]
+    bp = sp.BatchPlanner(maps, sws)
+    bp.plan(1)
+    lin = sp.LearnedInit(max_rows=32, max_samples=32, seed=9)
+    lin.collect(bp)
+    x = lin.features(bp)
+    t = np.zeros((32, 320), np.float32)
+    for i, m in enumerate(maps):  # targets: final group bests over the map size
+        st = bp.get_state(i)
+        rows = st["P"][np.arange(8), st["gbest_n"]]  # (8, 40)
+        t[i] = (rows / np.float32(m.width)).astype(np.float32).ravel()  # square maps
+    bp.close()
+    lr = float(np.float32(2e-3))
+    f32 = lambda v: float(np.float32(v))
+    p = lin.get_weights().astype(np.float64)
+    m1, v1 = np.zeros_like(p), np.zeros_like(p)
+    for step in range(1, 4):
+        _, g = lin.grads(x, t)
+        orc.adam_step(p, g, m1, v1, step, lr, b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
+        lin.train(1, batch=32, lr=lr)
+        w = lin.get_weights().astype(np.float64)
+        err = np.abs(w - p)
+        tol = 2.0 ** -22 * np.maximum(np.abs(p), lr) + 1e-5 * lr
+        print(f"adam step {step}: max |w - oracle| {err.max():.3g}, moved {np.mean(w != 0):.3f}",
+              flush=True)
+        assert np.all(err <= tol), (step, int(np.argmax(err - tol)), err.max())
+        p = w.copy()  # next step from the library's FP32 weights
+    lin.close()
