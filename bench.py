@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "plans/sec at oracle-matched cost; seg×edge tests/s vs FP32 VALU peak"
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published (packed FP32)
+PEAK_HBM = 8.0e12      # MI355X HBM3E, published
 F_TEST = 10.0          # algorithmic FLOP per segment x edge test
+BYTES_PER_ELEM = 20.0  # algorithmic HBM bytes per swarm element and iteration
 COUNTERS = os.path.join(ROOT, "profiles", "iter_kernel_batch1024_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2308_10169_amd", "csrc", "kernels.hip")
 
@@ -136,7 +138,7 @@ def cost_parity(gpu_cost, orc_cost):
     ratio = g / o
     med_ratio = float(np.median(ratio))
     return dict(instances=len(ids), median_cost_ratio=med_ratio,
-                mean_cost_ratio=float(np.mean(ratio)),
+                geomean_cost_ratio=float(np.exp(np.mean(np.log(ratio)))),
                 instances_within_1pct=int(np.sum(np.abs(ratio - 1.0) <= 0.01)),
                 median_cost_gpu=med_g, median_cost_oracle=med_o,
                 median_gap=abs(med_g - med_o) / abs(med_o),
@@ -252,39 +254,48 @@ def main():
         tests_run += per * iters[:, i].sum()
     print(f"# {plans} plans in {dt:.3f}s, mean iters {iters.mean():.1f}", file=sys.stderr, flush=True)
 
-    # Roofline of the fused iteration on the work it executes: the wave
-    # culling skips rectangles and edges no segment of the wave can cross
-    # (exactly), so a launch runs only a share of the all-pairs tests; that
-    # share is replayed on the host from sampled instances' swarm state.
+    # Roofline of the fused iteration.  At this state (a frame planned, the
+    # swarms converged) its time is set by its memory phase -- streaming every
+    # swarm element once (read X, V, P; write X, V: 20 B) -- and not by its
+    # crossing tests: a build without the crossing tests takes as long.  So
+    # the bound is HBM, at the algorithmic 20 B per element; the ALU side (the
+    # tests the wave culling leaves, replayed on the host from sampled
+    # instances' swarm state, 10 FLOP each) is reported beside it.
     executed = executed_fraction(bp, specs, sws, tune or (8, 128),
                                  range(0, args.instances, max(1, args.instances // 64)))
+    alg_bytes = BYTES_PER_ELEM * elems_iter
     all_pairs = F_TEST * tests_iter / (kern_ms * 1e-3)
-    achieved = executed * all_pairs
+    alu = executed * all_pairs
     kname = f"iter_kernel<{tune[0]}>" if tune else "iter_kernel"
     rec = counter_record(kname, tune) if tune else None
-    roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=achieved / PEAK_FP32, traffic=rec["hbm_bytes"] if rec else None,
+    roof = dict(bound="hbm", achieved=alg_bytes / (kern_ms * 1e-3) / 1e9, peak=PEAK_HBM / 1e9,
+                unit="GB/s", frac=alg_bytes / (kern_ms * 1e-3) / PEAK_HBM,
+                traffic=rec["hbm_bytes"] if rec else None,
                 kernel=f"{kname} (fused iteration, tile {tune})", ms_per_launch=kern_ms,
-                tests_per_launch_executed=executed * tests_iter, flop_per_test=F_TEST,
-                tests_per_launch_all_pairs=tests_iter, tests_executed_frac=executed,
-                # the planner's effective rate over every segment x edge pair
-                # of Eq.(13), culled ones included: not a utilisation (> 1 possible)
-                all_pairs_effective_tflops=all_pairs / 1e12,
-                all_pairs_effective_frac=all_pairs / PEAK_FP32)
+                elements_per_launch=elems_iter, bytes_per_element=BYTES_PER_ELEM,
+                alu=dict(bound="alu", achieved=alu / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                         frac=alu / PEAK_FP32, tests_per_launch_executed=executed * tests_iter,
+                         flop_per_test=F_TEST, tests_per_launch_all_pairs=tests_iter,
+                         tests_executed_frac=executed,
+                         # the planner's effective rate over every segment x edge
+                         # pair of Eq.(13), culled ones included: not a utilisation
+                         all_pairs_effective_tflops=all_pairs / 1e12,
+                         all_pairs_effective_frac=all_pairs / PEAK_FP32))
     if rec:
+        roof["traffic_tb_per_s"] = rec["hbm_bytes"] / (kern_ms * 1e-3) / 1e12
         # VALU issue: wave instructions x 64 lanes against the lane rate behind
         # the FP32 peak (157.3 TFLOP/s / 2 FLOP per FMA lane)
         lanes = rec["valu_insts"] * 64 / (kern_ms * 1e-3)
-        roof["valu_lane_ops_per_s"] = lanes
-        roof["valu_util"] = lanes / (PEAK_FP32 / 2)
+        roof["alu"]["valu_lane_ops_per_s"] = lanes
+        roof["alu"]["valu_util"] = lanes / (PEAK_FP32 / 2)
         # VALU issue against one wave64 instruction per SIMD every 4 cycles
         # (the ceiling without packed FP32), from the counter run's own cycles
         if "valu_issue_ratio" in rec:
-            roof["valu_issue_ratio"] = rec["valu_issue_ratio"]
+            roof["alu"]["valu_issue_ratio"] = rec["valu_issue_ratio"]
         # FP32 FLOP the counters saw (64 per ADD/MUL, 128 per FMA wave instruction)
         if "fp32_flop" in rec:
-            roof["counter_tflops"] = rec["fp32_flop"] / (kern_ms * 1e-3) / 1e12
-            roof["counter_frac"] = rec["fp32_flop"] / (kern_ms * 1e-3) / PEAK_FP32
+            roof["alu"]["counter_tflops"] = rec["fp32_flop"] / (kern_ms * 1e-3) / 1e12
+            roof["alu"]["counter_frac"] = rec["fp32_flop"] / (kern_ms * 1e-3) / PEAK_FP32
 
     # paper-shaped single instance (366 map, 30 rectangles, 8 x 170, W = 20)
     spec2 = I.dynamic_map(0)

@@ -210,7 +210,7 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   L.Q = take(4 * L.sumP);
   L.PQ = take(4 * L.sumP);
   L.edges = take(sizeof(EdgeRec) * L.sumGE);
-  L.rects = take(16 * L.sumR);
+  L.rects = take(32 * L.sumR);  // boxes, then centres and half sides
   L.pkind = take(8 * L.sumPoly);
   L.verts = take(8 * L.sumE);
   L.pptr = take(4 * L.sumPP);
@@ -453,6 +453,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
   pl.PQ = at<int32_t>(b, L.PQ);
   pl.edges = at<EdgeRec>(b, L.edges);
   pl.rects = at<float4>(b, L.rects);
+  pl.rect_c = pl.rects + L.sumR;
   pl.pkind = at<int2>(b, L.pkind);
   pl.verts = at<float2>(b, L.verts);
   pl.poly_ptr = at<int32_t>(b, L.pptr);

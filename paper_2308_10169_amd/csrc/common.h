@@ -112,6 +112,7 @@ struct Pools {
   int32_t *Q, *PQ;
   EdgeRec* edges;    // general polygons' edges
   float4* rects;     // axis-aligned rectangles (x0, y0, x1, y1), x0 < x1, y0 < y1
+  float4* rect_c;    // their centres and half sides (xc, yc, w/2, h/2)
   int2* pkind;       // per polygon: (1 = rectangle / 0 = general, slot in its pool)
   float2* verts;
   int32_t* poly_ptr;

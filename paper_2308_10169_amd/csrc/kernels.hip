@@ -94,6 +94,9 @@ __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
       // + 0 turns a -0 corner into +0: every stored coordinate then has its
       // sign bit clear, and its bits order as its value does
       pl.rects[d.ro + ks.y] = make_float4(x0 + 0.f, y0 + 0.f, x1 + 0.f, y1 + 0.f);
+      // centre and half sides (exact: the corners lie on a 1/256 grid)
+      pl.rect_c[d.ro + ks.y] = make_float4((x0 + x1) * 0.5f, (y0 + y1) * 0.5f, (x1 - x0) * 0.5f,
+                                           (y1 - y0) * 0.5f);
       continue;
     }
     EdgeRec* er = pl.edges + d.geo + ks.y;
@@ -522,21 +525,50 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
   // the same for every lane, so it stays in scalar registers and the culling
   // test runs on the scalar unit, on integer keys that order floats as their
   // values do (the key order puts -0 below +0, so it never culls more than
-  // the float comparison would).  Edge sides are exact sign tests of one
-  // coordinate difference; corner sides: (x0,y0) by two FMAs, each other
-  // corner from a neighbour by one FMA along the rectangle's side (three
-  // roundings on the far corner stay well inside the degenerate band).
+  // the float comparison would).
+  //
+  // A box is convex, so the proper crossings of a segment with its four
+  // edges are (in general position) one when exactly one end point lies
+  // strictly inside, none when both do, and two when both lie outside and
+  // the segment meets the open box: its x and y ranges overlap the box's
+  // and the box's corners are not all on one side of its line.  End-point
+  // sides are exact sign tests of one coordinate difference; the corner
+  // test is |o(centre)| < |dx| h/2 + |dy| w/2 (the corners' orientations
+  // are o(centre) +- |dx| h/2 +- |dy| w/2), by two FMAs for o(centre) and
+  // two for the difference, within the degenerate band of the exact value.
+  // Where a test is degenerate the count may resolve it either way.
   {
     const int kx0 = __builtin_amdgcn_readfirstlane(float_key(bx0));
     const int kx1 = __builtin_amdgcn_readfirstlane(float_key(bx1));
     const int ky0 = __builtin_amdgcn_readfirstlane(float_key(by0));
     const int ky1 = __builtin_amdgcn_readfirstlane(float_key(by1));
+    // lo < c < hi as one unsigned comparison of the coordinate's bits (the
+    // box is not empty here; a coordinate of -0 lies on the map's border,
+    // its bits test as outside).
+    const uint32_t ny = (uint32_t)(ky1 - ky0 - 1), nx = (uint32_t)(kx1 - kx0 - 1);
+    auto inside = [](float c, int lo, uint32_t n) { return (uint32_t)(__float_as_int(c) - lo - 1) < n; };
+    // Words: bit K - s for point s; segment s (points s, s + 1) at bit K - s,
+    // so its second point is the word shifted left by one.  Bits 1..K are the
+    // segments; inactive lanes keep none.
+    constexpr uint32_t kOnes = (2u << K) - 1u;
+    const uint32_t segmask = active ? (kOnes & ~1u) : 0u;
+    // sign bits of (c - p_s) (sub_c_p) or of (p_s - c)
+    auto side_word = [&](const float (&p)[K + 1], float c, bool sub_c_p) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int s = 0; s <= K; ++s)
+        w = __builtin_amdgcn_alignbit(w, __float_as_uint(sub_c_p ? c - p[s] : p[s] - c), 31);
+      return w;
+    };
     // Rectangles come in 64-byte quads (an instance's slice is padded to a
     // whole number of them), one scalar load per quad; wave group rg takes
     // quads rg, rg + R, ...  Padding rectangles are loaded, never tested.
     typedef float quad16 __attribute__((ext_vector_type(16)));
     const __attribute__((address_space(4))) quad16* rq =
         (const __attribute__((address_space(4))) quad16*)(pl.rects + d.ro);
+    typedef float quad4 __attribute__((ext_vector_type(4)));
+    const __attribute__((address_space(4))) quad4* cq =
+        (const __attribute__((address_space(4))) quad4*)(pl.rect_c + d.ro);
     for (int c4 = rg; 4 * c4 < d.n_rects; c4 += R) {
       const quad16 blk = rq[c4];
 #pragma unroll
@@ -546,37 +578,34 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       if (4 * c4 + q >= d.n_rects || __float_as_int(b.z) <= kx0 || __float_as_int(b.x) >= kx1 ||
           __float_as_int(b.w) <= ky0 || __float_as_int(b.y) >= ky1)
         continue;
-      const float w = b.z - b.x, h = b.w - b.y;
-      uint32_t w00 = 0, w10 = 0, w11 = 0, w01 = 0;
+      // Point sides of the four lines (bit set: strictly on the box's side).
+      // A line that does not pass strictly through the wave's box has every
+      // point on the box's side of it or on it (the box is not culled); a
+      // point on the line is then taken as on the box's side, as if moved
+      // inward by an infinitesimal amount, which changes degenerate tests
+      // only.
+      const uint32_t lw = inside(b.x, kx0, nx) ? side_word(px, b.x, true) : kOnes;   // p.x > x0
+      const uint32_t rw = inside(b.z, kx0, nx) ? side_word(px, b.z, false) : kOnes;  // p.x < x1
+      const uint32_t bw = inside(b.y, ky0, ny) ? side_word(py, b.y, true) : kOnes;   // p.y > y0
+      const uint32_t tw = inside(b.w, ky0, ny) ? side_word(py, b.w, false) : kOnes;  // p.y < y1
+      const uint32_t in = lw & rw & bw & tw;
+      count((in ^ (in << 1)) & segmask);  // one end strictly inside
+      // both ends outside, ranges overlapping: candidates for two crossings
+      const uint32_t ov = ((lw << 1) | lw) & ((rw << 1) | rw) & ((bw << 1) | bw) & ((tw << 1) | tw);
+      const uint32_t cand = ov & ~((in << 1) | in) & segmask;
+      if (__builtin_amdgcn_ballot_w64(cand != 0u) == 0ull) continue;
+      const quad4 cr = cq[4 * c4 + q];  // centre and half sides, loaded only when needed
+      const float xc = cr.x, yc = cr.y, hw = cr.z, hh = cr.w;
+      uint32_t sw = 0;  // bit K - 1 - s: the line of segment s passes strictly through the box
 #pragma unroll
       for (int s = 0; s < K; ++s) {
-        const float o00 = fmaf(dx[s], b.y, fmaf(ndy[s], b.x, nc[s]));
-        const float o10 = fmaf(ndy[s], w, o00);
-        const float o01 = fmaf(dx[s], h, o00);
-        const float o11 = fmaf(dx[s], h, o10);
-        w00 = __builtin_amdgcn_alignbit(w00, __float_as_uint(o00), 31);
-        w10 = __builtin_amdgcn_alignbit(w10, __float_as_uint(o10), 31);
-        w11 = __builtin_amdgcn_alignbit(w11, __float_as_uint(o11), 31);
-        w01 = __builtin_amdgcn_alignbit(w01, __float_as_uint(o01), 31);
+        const float oc = fmaf(dx[s], yc, fmaf(ndy[s], xc, nc[s]));
+        const float dd = fmaf(-fabsf(ndy[s]), hw, fmaf(-fabsf(dx[s]), hh, fabsf(oc)));
+        sw = __builtin_amdgcn_alignbit(sw, __float_as_uint(dd), 31);
       }
-      // An edge whose line does not pass strictly through the wave's box has
-      // every point on one side of it (or on it: a degenerate contact), so no
-      // segment crosses it and its point-side word is not formed.
-      auto edge = [&](const float (&p)[K + 1], float c, uint32_t wa, uint32_t wb) {
-        uint32_t ew = 0;
-#pragma unroll
-        for (int s = 0; s <= K; ++s) ew = __builtin_amdgcn_alignbit(ew, __float_as_uint(p[s] - c), 31);
-        count((wa ^ wb) & (ew ^ (ew >> 1)));
-      };
-      // lo < c < hi as one unsigned comparison of the coordinate's bits (the
-      // box is not empty here; a coordinate of -0 lies on the map's border,
-      // its bits test as outside, and no segment can cross that line).
-      const uint32_t ny = (uint32_t)(ky1 - ky0 - 1), nx = (uint32_t)(kx1 - kx0 - 1);
-      auto inside = [](float c, int lo, uint32_t n) { return (uint32_t)(__float_as_int(c) - lo - 1) < n; };
-      if (inside(b.y, ky0, ny)) edge(py, b.y, w00, w10);  // bottom
-      if (inside(b.z, kx0, nx)) edge(px, b.z, w10, w11);  // right
-      if (inside(b.w, ky0, ny)) edge(py, b.w, w11, w01);  // top
-      if (inside(b.x, kx0, nx)) edge(px, b.x, w01, w00);  // left
+      const uint32_t thr = cand & (sw << 1);
+      count(thr);
+      count(thr);
       }
     }
   }
@@ -967,9 +996,13 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
 
 // One fused iteration (fitness path), the same with the rectangles dealt over
 // R wave groups (launches with few blocks), and the update-only flush, as
-// separate kernels so that profiles separate them.
+// separate kernels so that profiles separate them.  Up to K = 8 the plain
+// kernel is held to six waves per SIMD (80 VGPRs): its blocks spend most of
+// their time waiting on the swarm's loads, and a sixth block per CU hides
+// more of that than the four VGPRs it gives up cost.
 template <int K>
-__global__ __launch_bounds__(256) void iter_kernel(Pools pl, int flags) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 6 : 1))) void
+iter_kernel(Pools pl, int flags) {
   iteration<K, 1, true>(pl, flags);
 }
 template <int K, int R>

@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--tune", default="16,64", help="K,block_threads or 'auto'")
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--warmup-launches", type=int, default=20)
+    ap.add_argument("--frames-first", type=int, default=1,
+                    help="frames planned before the warm-up launches (the benchmark's state)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter scale)")
     args = ap.parse_args()
@@ -55,6 +57,8 @@ def main():
     if tune is None:
         tune = bp.autotune()
     tests, elems = bp.work()
+    if args.frames_first > 0:
+        bp.plan(args.frames_first)
     bp.profile_step(args.warmup_launches)  # clocks settle before the measured launches
     ms = bp.profile_step(args.launches)
     rate = tests / (ms * 1e-3)

@@ -156,3 +156,98 @@ def test_rectangle_corner_signs_match_when_robust(orc, near):
                 checked += 1
                 assert neg(o32) == (o64 < 0), (p, q, v, o64, o32)
     assert checked > 3000
+
+
+def rect_count_inout(p, q, box):
+    """The fused iteration's count of proper crossings of segment p -> q
+    with the four edges of an axis-aligned box, emulated in FP32: the end
+    points' strict sides of the box's four lines (exact comparisons); one
+    crossing when exactly one end point lies strictly inside; two when both
+    lie outside, the segment's x and y ranges overlap the box's open ranges
+    and the box's corners are not all on one side of the segment's line,
+    tested at the box centre: |o(c)| < |dx| h/2 + |dy| w/2, by two FMAs for
+    o(c) and two for the difference."""
+    x0, y0, x1, y1 = box
+    L = lambda v: sub32(x0, v[0]) < 0          # v.x > x0
+    R = lambda v: sub32(v[0], x1) < 0          # v.x < x1
+    B = lambda v: sub32(y0, v[1]) < 0
+    T = lambda v: sub32(v[1], y1) < 0
+    inside = lambda v: L(v) and R(v) and B(v) and T(v)
+    ip, iq = inside(p), inside(q)
+    if ip != iq:
+        return 1
+    if ip or iq:
+        return 0
+    ov = (L(p) or L(q)) and (R(p) or R(q)) and (B(p) or B(q)) and (T(p) or T(q))
+    if not ov:
+        return 0
+    dx, ndy, nc = seg_line(p, q)
+    xc, yc = (x0 + x1) / 2, (y0 + y1) / 2      # exact: coordinates on a 1/256 grid
+    hw, hh = (x1 - x0) / 2, (y1 - y0) / 2
+    oc = fma32(dx, yc, fma32(ndy, xc, nc))
+    d = fma32(-abs(dx), hh, abs(oc))
+    d = fma32(-abs(ndy), hw, d)
+    return 2 if d < 0 else 0
+
+
+def _box_cases(rng, S, n):
+    """Segments against boxes on a 1/256 grid: random, through the box,
+    ending inside, grazing a corner, along an edge line, on an edge,
+    axis-parallel and zero-length."""
+    g = lambda v: np.round(np.asarray(v, float) * 256) / 256
+    f32 = lambda v: np.asarray(v, np.float64).astype(np.float32).astype(float)
+    for k in range(n):
+        w, h = g(rng.uniform(5, 40, 2))
+        x0, y0 = g(rng.uniform(0, S - w)), g(rng.uniform(0, S - h))
+        box = (x0, y0, x0 + w, y0 + h)
+        c = np.array([box[(k % 2) * 2], box[1 + ((k // 2) % 2) * 2]])  # a corner
+        kind = k % 8
+        if kind == 0:
+            p, q = rng.uniform(0, S, 2), rng.uniform(0, S, 2)
+        elif kind == 1:  # through the box
+            m = np.array([x0 + w / 2, y0 + h / 2]) + rng.normal(size=2) * [w / 3, h / 3]
+            d = rng.normal(size=2)
+            p, q = m - 60 * d, m + 60 * d
+        elif kind == 2:  # one end inside
+            p = np.array([rng.uniform(x0, x0 + w), rng.uniform(y0, y0 + h)])
+            q = p + rng.normal(size=2) * 30
+        elif kind == 3:  # line grazing a corner by ~1e-4
+            d = rng.normal(size=2)
+            d /= np.linalg.norm(d)
+            off = rng.choice([-1, 1]) * rng.uniform(0, 2e-4) * np.array([-d[1], d[0]])
+            p, q = c - rng.uniform(1, 50) * d + off, c + rng.uniform(1, 50) * d + off
+        elif kind == 4:  # along an edge line
+            p = np.array([box[0], rng.uniform(0, S)])
+            q = np.array([box[0], rng.uniform(0, S)])
+        elif kind == 5:  # end point on an edge
+            p = np.array([box[2], rng.uniform(y0, y0 + h)])
+            q = rng.uniform(0, S, 2)
+        elif kind == 6:  # axis-parallel through or near
+            y = rng.choice([y0, y0 + h, rng.uniform(y0, y0 + h), y0 + h + 1e-3])
+            p, q = np.array([x0 - 20, y]), np.array([x0 + w + 20, y])
+        else:  # zero length, inside or outside
+            p = rng.uniform(0, S, 2) if rng.random() < 0.5 else np.array([x0 + w / 2, y0 + h / 2])
+            q = p.copy()
+        p, q = f32(np.clip(p, 0, S)), f32(np.clip(q, 0, S))
+        yield p, q, box
+
+
+def test_rectangle_inout_count_in_bracket(orc):
+    # The in/out form of the rectangle count against the oracle's per-edge
+    # classification: equal to the robust count when no edge test is
+    # degenerate, inside [q_yes, q_yes + n_deg] always.
+    S = 512.0
+    tau = 1e-6 * S * S
+    rng = np.random.default_rng(23)
+    exact = 0
+    for p, q, (x0, y0, x1, y1) in _box_cases(rng, S, 6000):
+        corners = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+        cls = [orc.classify(p, q, np.array(corners[e]), np.array(corners[(e + 1) % 4]), tau)
+               for e in range(4)]
+        yes, deg = sum(c == 1 for c in cls), sum(c == -1 for c in cls)
+        got = rect_count_inout(p, q, (x0, y0, x1, y1))
+        assert yes <= got <= yes + deg, (p, q, (x0, y0, x1, y1), cls, got)
+        if deg == 0:
+            exact += 1
+            assert got == yes
+    assert exact > 3000
