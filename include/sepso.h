@@ -163,6 +163,22 @@ sepso_status sepso_fitness(int32_t n_polys, int32_t n_vert, const int32_t* d_pol
                            float* d_f, float* d_L, int32_t* d_Q, void* d_workspace,
                            size_t workspace_bytes, void* stream);
 
+/* sepso_fitness without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the edge records and per-segment partial results live
+ * in a fixed 8 MiB device array that the library holds on each GPU it runs
+ * on until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  Requests whose workspace
+ * (sepso_fitness_workspace_bytes) would exceed 8 MiB give SEPSO_E_ARG.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or threads, work still in flight) race; calls
+ * ordered on one stream do not.  Same arguments, results and errors as
+ * sepso_fitness otherwise. */
+sepso_status sepso_fitness_noalloc(int32_t n_polys, int32_t n_vert, const int32_t* d_poly_ptr,
+                                   const float* d_verts, const float* d_ends, const float* d_paths,
+                                   int32_t n_paths, int32_t waypoints, float alpha, int32_t beta,
+                                   float* d_f, float* d_L, int32_t* d_Q, void* stream);
+
 /* ---- single instance ---------------------------------------------------- */
 sepso_status sepso_workspace_bytes(const sepso_map* map, const sepso_swarm* swarm, size_t* bytes);
 

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "../../include/sepso.h"
 #include "internal.h"
@@ -241,6 +242,70 @@ sepso_status sepso_fitness(int32_t n_polys, int32_t n_vert, const int32_t* d_pol
     return fail(SEPSO_E_NOMEM, "fitness: workspace of %zu bytes, %zu needed", ws_bytes, need);
   return fit_run(n_polys, n_vert, d_poly_ptr, d_verts, d_ends, d_paths, n_paths, waypoints, alpha,
                  beta, d_f, d_L, d_Q, static_cast<char*>(d_ws), static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the workspace is a file-scope device array of
+// kFitScratchBytes, one per GPU, shared by every call on that GPU.  Host code
+// never uses the array's name as an address: its device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and kept.
+// ---------------------------------------------------------------------------
+namespace sepso {
+namespace {
+
+constexpr size_t kFitScratchBytes = size_t(8) << 20;  // 8 MiB per GPU
+constexpr int kFitMaxDevices = 64;
+
+__device__ __align__(256) char scratch[kFitScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kFitMaxDevices] = {};
+
+sepso_status scratch_ptr(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(SEPSO_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kFitMaxDevices)
+    return fail(SEPSO_E_UNSUPPORTED, "fitness: device %d beyond the %d supported", dev, kFitMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SEPSO_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SEPSO_OK;
+}
+
+}  // namespace
+}  // namespace sepso
+
+extern "C" {
+
+sepso_status sepso_fitness_noalloc(int32_t n_polys, int32_t n_vert, const int32_t* d_poly_ptr,
+                                   const float* d_verts, const float* d_ends, const float* d_paths,
+                                   int32_t n_paths, int32_t waypoints, float alpha, int32_t beta,
+                                   float* d_f, float* d_L, int32_t* d_Q, void* stream) {
+  sepso_status st = fit_check(n_polys, n_vert, n_paths, waypoints, alpha, beta);
+  if (st == SEPSO_OK)
+    st = fit_pointers(n_vert, d_poly_ptr, d_verts, d_ends, d_paths, n_paths, d_f, d_L, d_Q);
+  if (st != SEPSO_OK) return st;
+  if (n_paths == 0) return SEPSO_OK;
+  const size_t need = fit_layout(n_vert, n_paths, waypoints).total;
+  if (need > kFitScratchBytes)
+    return fail(SEPSO_E_ARG,
+                "fitness_noalloc: %d paths of %d waypoints on %d vertices need %zu bytes of "
+                "scratch; the allocation-free variant holds %zu (use sepso_fitness with a workspace)",
+                n_paths, waypoints, n_vert, need, kFitScratchBytes);
+  void* ws = nullptr;
+  st = scratch_ptr(&ws);
+  if (st != SEPSO_OK) return st;
+  return fit_run(n_polys, n_vert, d_poly_ptr, d_verts, d_ends, d_paths, n_paths, waypoints, alpha,
+                 beta, d_f, d_L, d_Q, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

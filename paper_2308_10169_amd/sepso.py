@@ -173,6 +173,8 @@ def _load():
     L.sepso_fitness_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(sz)]
     L.sepso_fitness.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_int32, C.c_int32,
                                 C.c_float, C.c_int32, vp, vp, vp, vp, sz, vp]
+    L.sepso_fitness_noalloc.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_int32,
+                                        C.c_int32, C.c_float, C.c_int32, vp, vp, vp, vp]
     _lib, _torch = L, torch
     return L
 
@@ -195,9 +197,10 @@ def philox(first, c1, c2, c3, key, n):
     return out[:int(n)].cpu().numpy().view(np.uint32)
 
 
-def fitness(spec, paths, waypoints, alpha, beta):
-    """sepso_fitness on device copies of the map's polygons and endpoints
-    and of paths (n, 2W): returns dict(f, L, Q) as numpy arrays."""
+def fitness(spec, paths, waypoints, alpha, beta, noalloc=False):
+    """sepso_fitness (or, with noalloc, sepso_fitness_noalloc) on device
+    copies of the map's polygons and endpoints and of paths (n, 2W):
+    returns dict(f, L, Q) as numpy arrays."""
     _load()
     torch = _torch
     W = int(waypoints)
@@ -213,12 +216,17 @@ def fitness(spec, paths, waypoints, alpha, beta):
     Q = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     st = torch.cuda.current_stream()
     ptr = lambda t: C.c_void_p(t.data_ptr())
-    nbytes = C.c_size_t()
-    _check(_lib.sepso_fitness_workspace_bytes(n_vert, n, W, C.byref(nbytes)))
-    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
-    _check(_lib.sepso_fitness(n_polys, n_vert, ptr(pp), ptr(vv), ptr(ee), ptr(X), n, W,
-                              float(alpha), int(beta), ptr(f), ptr(Lv), ptr(Q), ptr(ws),
-                              nbytes.value, C.c_void_p(st.cuda_stream)))
+    if noalloc:
+        _check(_lib.sepso_fitness_noalloc(n_polys, n_vert, ptr(pp), ptr(vv), ptr(ee), ptr(X), n, W,
+                                          float(alpha), int(beta), ptr(f), ptr(Lv), ptr(Q),
+                                          C.c_void_p(st.cuda_stream)))
+    else:
+        nbytes = C.c_size_t()
+        _check(_lib.sepso_fitness_workspace_bytes(n_vert, n, W, C.byref(nbytes)))
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+        _check(_lib.sepso_fitness(n_polys, n_vert, ptr(pp), ptr(vv), ptr(ee), ptr(X), n, W,
+                                  float(alpha), int(beta), ptr(f), ptr(Lv), ptr(Q), ptr(ws),
+                                  nbytes.value, C.c_void_p(st.cuda_stream)))
     st.synchronize()
     return dict(f=f[:n].cpu().numpy(), L=Lv[:n].cpu().numpy(), Q=Q[:n].cpu().numpy())
 
