@@ -62,7 +62,7 @@ def counter_record(kernel, tune):
     return out
 
 
-def executed_fraction(bp, specs, sws, tune, sample):
+def executed_fraction(bp, specs, sws, tile_of, sample):
     """Share of the segment x edge tests the fused iteration actually runs:
     a wave skips a rectangle outside the bounding box of its points, and of a
     rectangle it keeps, every edge whose line does not pass strictly through
@@ -71,9 +71,9 @@ def executed_fraction(bp, specs, sws, tune, sample):
     on chunk t // ppb of K segments of particle t % ppb, 64 threads per wave)
     is replayed on the swarm state left by the timed launches of sampled
     instances."""
-    K, B = tune
     run = tot = 0.0
     for i in sample:
+        K, B = tile_of(i)
         spec, sw = specs[i], sws[i]
         W, S = sw.waypoints, sw.waypoints + 2
         X = bp.get_state(i)["X"].reshape(-1, 2 * W).astype(np.float64)
@@ -221,9 +221,18 @@ def main():
 
     sepso.lib()
     bp = sepso.BatchPlanner(specs, sws)
-    tune = bp.autotune() if not args.no_tune else None
+    tune, tiling = None, None
+    if not args.no_tune:
+        # tiles per bucket of instances (split by waypoint count), or one tile
+        # for all when that plans a frame faster -- the autotuner decides
+        tiles, bucket_of, fms = bp.autotune_buckets(4, frame_ms=True)
+        tune = tiles[0] if len(tiles) == 1 else None
+        tiling = dict(tiles=tiles, bucket_sizes=np.bincount(bucket_of).tolist(),
+                      frame0_ms_buckets=fms[0], frame0_ms_one_tile=fms[1],
+                      frame0_plans_per_s_buckets=args.instances / (fms[0] * 1e-3),
+                      frame0_plans_per_s_one_tile=args.instances / (fms[1] * 1e-3))
     tests_iter, elems_iter = bp.work()
-    print(f"# tune {tune}, tests/iteration {tests_iter:.4g}", file=sys.stderr, flush=True)
+    print(f"# tiling {tiling}, tests/iteration {tests_iter:.4g}", file=sys.stderr, flush=True)
 
     # frame 0 of every instance from the fresh batch (the autotuner leaves it
     # as new): the cost the oracle reached on the same instances and streams
@@ -261,17 +270,19 @@ def main():
     # the bound is HBM, at the algorithmic 20 B per element; the ALU side (the
     # tests the wave culling leaves, replayed on the host from sampled
     # instances' swarm state, 10 FLOP each) is reported beside it.
-    executed = executed_fraction(bp, specs, sws, tune or (8, 128),
+    tile_of = ((lambda i: tune) if tune else
+               (lambda i: tiling["tiles"][bucket_of[i]]) if tiling else (lambda i: (8, 128)))
+    executed = executed_fraction(bp, specs, sws, tile_of,
                                  range(0, args.instances, max(1, args.instances // 64)))
     alg_bytes = BYTES_PER_ELEM * elems_iter
     all_pairs = F_TEST * tests_iter / (kern_ms * 1e-3)
     alu = executed * all_pairs
-    kname = f"iter_kernel<{tune[0]}>" if tune else "iter_kernel"
+    kname = f"iter_kernel<{tune[0]}>" if tune else "iter_kernel (one launch per bucket)"
     rec = counter_record(kname, tune) if tune else None
     roof = dict(bound="hbm", achieved=alg_bytes / (kern_ms * 1e-3) / 1e9, peak=PEAK_HBM / 1e9,
                 unit="GB/s", frac=alg_bytes / (kern_ms * 1e-3) / PEAK_HBM,
                 traffic=rec["hbm_bytes"] if rec else None,
-                kernel=f"{kname} (fused iteration, tile {tune})", ms_per_launch=kern_ms,
+                kernel=f"{kname} (fused iteration, tile {tune or tiling})", ms_per_launch=kern_ms,
                 elements_per_launch=elems_iter, bytes_per_element=BYTES_PER_ELEM,
                 alu=dict(bound="alu", achieved=alu / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
                          frac=alu / PEAK_FP32, tests_per_launch_executed=executed * tests_iter,
@@ -323,7 +334,7 @@ def main():
                                     "instances (W 8-32, 4-100 rectangles, 32-256 particles/group "
                                     "x 8 groups, maps 128-512), AT + PI + online HSEF, <=50 "
                                     "iterations/frame, one hipGraph per frame",
-                           instances=args.instances, tune=tune,
+                           instances=args.instances, tune=tune, tiling=tiling,
                            oracle_matched=parity["matched"] if parity else None),
                cost_parity=parity,
                gpu_frame0=dict(plans_per_s=args.instances / frame0_s,

@@ -265,7 +265,8 @@ sepso_status sepso_batch_profile_step(sepso_batch* b, int32_t n, float* avg_ms);
 /* Choose seg_per_thread / block_threads by timing candidates on this batch;
  * the winner is applied to the batch and written to *best (may be NULL).
  * Afterwards the batch is as new: control blocks (random-stream positions,
- * frame index, previous plans) reset and the frame-0 swarm initialised.
+ * frame index, previous plans) and hyper-parameters reset and the frame-0
+ * swarm initialised.
  * Synchronous. */
 sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best);
 /* sepso_autotune with a persistent cache: cache_path is a text file of lines
@@ -283,6 +284,31 @@ sepso_status sepso_autotune_cached(sepso_batch* b, const char* cache_path, sepso
 /* Apply a tile configuration to every instance (same bounds as sepso_set_tune,
  * with the smallest waypoint count of the batch). */
 sepso_status sepso_batch_set_tune(sepso_batch* b, const sepso_tune* tune);
+/* Tiles per bucket of instances: bucket_of[i] in [0, n_buckets) names
+ * instance i's bucket (every bucket non-empty, n_buckets <= 8) and tiles[j]
+ * bucket j's tile (the sepso_batch_set_tune bounds over its instances).  Each
+ * iteration then launches one fused-iteration kernel per bucket (side by side
+ * in the frame's captured graph), then the per-instance reduce.  Results do
+ * not depend on the bucketing beyond a tile's own summation order of the
+ * path length.  Synchronous. */
+sepso_status sepso_batch_set_tiles(sepso_batch* b, int32_t n_buckets, const int32_t* bucket_of,
+                                   const sepso_tune* tiles);
+/* Per-bucket autotuning: the batch's instances are split by waypoint count
+ * into at most max_buckets (<= 8) buckets of about equal size; each bucket's
+ * tile is the fastest candidate of its own fused-iteration launch (or, with
+ * cache_path, a line of the cache file under the bucket's key: the batch key
+ * of sepso_autotune_cached taken over the bucket's instances; timed buckets
+ * are appended).  One frame from the frame-0 swarm is then planned with the
+ * buckets and one with sepso_autotune's single tile; the faster stays.
+ * tiles (max_buckets entries) receives the tile of each bucket used,
+ * bucket_of (n_inst, may be NULL) each instance's bucket, *n_buckets (may be
+ * NULL) the number of buckets (1: one tile for all), frame_ms (2 floats, may
+ * be NULL) the device time of the compared frames (buckets, one tile; NaN
+ * when the batch has a single waypoint count).  Afterwards the batch is as
+ * new, as after sepso_autotune (hyper-parameters as created).  Synchronous. */
+sepso_status sepso_autotune_buckets(sepso_batch* b, int32_t max_buckets, const char* cache_path,
+                                    sepso_tune* tiles, int32_t* bucket_of, int32_t* n_buckets,
+                                    float* frame_ms);
 /* Work counters of one full iteration of every instance: segment x edge
  * tests and swarm elements (for throughput reporting). */
 sepso_status sepso_batch_work(sepso_batch* b, double* tests_per_iter, double* elems_per_iter);

@@ -328,33 +328,53 @@ sepso_status hip_fail(sepso_batch* b, hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(b, _e, what); \
   } while (0)
 
-// Block geometry for the current tune: each block of the fused iteration
-// takes ppb consecutive particles (tile_ppb); fills the desc fields, the LDS
-// sizing and the block -> (instance, first particle) table, heaviest blocks
-// first (the dispatcher hands blocks out in order).
+// One bucket holding every instance, with one tile shape.
+void set_single(sepso_batch* b, const sepso_tune& t) {
+  b->tune = t;
+  b->buckets.assign(1, TileBucket{});
+  b->buckets[0].tune = t;
+  for (int i = 0; i < b->n; ++i) b->buckets[0].inst.push_back(i);
+}
+
+// Block geometry for the buckets' tiles: each block of the fused iteration
+// takes ppb consecutive particles (tile_ppb) of one instance; fills the desc
+// fields and, per bucket, its LDS sizing, wave groups and slice of the block
+// -> (instance, first particle) table, heaviest blocks first (the dispatcher
+// hands blocks out in order).
 void plan_tiles(sepso_batch* b, std::vector<int2>* blk) {
-  const int K = b->tune.seg_per_thread, B = b->tune.block_threads;
+  if (b->buckets.empty()) set_single(b, b->tune);
   blk->clear();
-  std::vector<std::pair<double, int>> order;
-  const int R = tile_rsplit(b->desc, K, B);
-  b->pl.rsplit = R;
-  for (int i = 0; i < b->n; ++i) {
-    InstDesc& d = b->desc[i];
-    d.ppb = tile_ppb(d.W, K, B, R);
-    d.n_blocks = (d.G * d.N + d.ppb - 1) / d.ppb;
-    order.push_back({(double)d.n_edges * d.ppb * (d.W + 2), i});
-  }
-  const TileLds L = tile_lds(b->desc, K, B);
-  b->pl.pos_floats = L.pos;
-  b->pl.stage_floats = L.stage;
-  b->pl.gb_floats = L.gb;
-  b->pl.ngb_max = L.ngb;
-  b->pl.ppb_max = L.ppb;
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<double, int>& a, const std::pair<double, int>& c) { return a.first > c.first; });
-  for (auto& o : order) {
-    const InstDesc& d = b->desc[o.second];
-    for (int t = 0; t < d.n_blocks; ++t) blk->push_back(make_int2(o.second, t * d.ppb));
+  for (TileBucket& bk : b->buckets) {
+    const int K = bk.tune.seg_per_thread, B = bk.tune.block_threads;
+    std::vector<InstDesc> sub;
+    for (int i : bk.inst) sub.push_back(b->desc[i]);
+    const int R = tile_rsplit(sub, K, B);
+    std::vector<std::pair<double, int>> order;
+    for (int i : bk.inst) {
+      InstDesc& d = b->desc[i];
+      d.ppb = tile_ppb(d.W, K, B, R);
+      d.n_blocks = (d.G * d.N + d.ppb - 1) / d.ppb;
+      order.push_back({(double)d.n_edges * d.ppb * (d.W + 2), i});
+    }
+    const TileLds L = tile_lds(sub, K, B);
+    bk.pl = b->pl;
+    bk.pl.rsplit = R;
+    bk.pl.pos_floats = L.pos;
+    bk.pl.stage_floats = L.stage;
+    bk.pl.gb_floats = L.gb;
+    bk.pl.ngb_max = L.ngb;
+    bk.pl.ppb_max = L.ppb;
+    std::stable_sort(order.begin(), order.end(), [](const std::pair<double, int>& a,
+                                                    const std::pair<double, int>& c) {
+      return a.first > c.first;
+    });
+    bk.first_block = (int)blk->size();
+    for (auto& o : order) {
+      const InstDesc& d = b->desc[o.second];
+      for (int t = 0; t < d.n_blocks; ++t) blk->push_back(make_int2(o.second, t * d.ppb));
+    }
+    bk.n_blocks = (int)blk->size() - bk.first_block;
+    bk.pl.blk_tiles = b->pl.blk_tiles + bk.first_block;
   }
   b->tile_blocks = (int)blk->size();
 }
@@ -381,6 +401,8 @@ void destroy_batch(sepso_batch* b) {
   for (int m = 0; m < 2; ++m)
     if (b->graph[m]) (void)hipGraphExecDestroy(b->graph[m]);
   // teardown is best effort: a failure here leaves nothing to recover
+  for (hipStream_t x : b->bstreams) (void)hipStreamDestroy(x);
+  for (hipEvent_t x : b->bevents) (void)hipEventDestroy(x);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
   if (b->h_ctl) (void)hipHostFree(b->h_ctl);
@@ -420,6 +442,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
     }
     b->tune = *tune;
   }
+  set_single(b, b->tune);
   if (ws_bytes < b->lay.total) {
     const size_t need = b->lay.total;
     delete b;
@@ -510,6 +533,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
     b->path_off[i + 1] = b->path_off[i] + 2 * d.W;
   }
   b->h_pptr.assign(pptr.begin(), pptr.begin() + b->desc[0].n_polys + 1);
+  b->h_hyper0 = hyper;
   std::vector<InstCtl> ctl(n);
   std::memset(ctl.data(), 0, sizeof(InstCtl) * n);
   for (int i = 0; i < n; ++i) ctl[i].tb_f = INFINITY;
@@ -527,7 +551,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
       h2d(L.pvel, pvel.data(), 4 * pvel.size()),
       h2d(L.ends, ends.data(), 4 * ends.size()),
       h2d(L.endv, endv.data(), 4 * endv.size()),
-      h2d(L.hyper, hyper.data(), 4 * hyper.size()),
+      h2d(L.hyper, hyper.data(), 4 * hyper.size()),  // kept in b->h_hyper0 below
       h2d(L.ohyper, ohyper.data(), 4 * ohyper.size()),
       h2d(L.blki, blki.data(), sizeof(int2) * blki.size())};
   for (hipError_t x : errs)
@@ -569,6 +593,34 @@ sepso_status usable(sepso_batch* b) {
 
 int init_blocks(sepso_batch* b) { return (int)b->lay.initBlocks; }
 
+// One iteration of every instance: each bucket's tile kernel, then the
+// per-instance reduce.  With fork (graph capture) the buckets after the
+// first go out on side streams that branch off before them and join before
+// the reduce, so that their launches can run side by side; otherwise they
+// follow one another on s.  Events, when given, bracket the tile kernels.
+hipError_t enqueue_iteration(sepso_batch* b, int flags, bool fork, hipEvent_t before = nullptr,
+                             hipEvent_t after = nullptr) {
+  hipStream_t s = b->stream;
+  hipError_t e = hipSuccess;
+  if (before) e = hipEventRecord(before, s);
+  const int nb = (int)b->buckets.size();
+  const bool par = fork && nb > 1 && (int)b->bstreams.size() >= nb - 1 && (int)b->bevents.size() >= nb;
+  if (par && e == hipSuccess) e = hipEventRecord(b->bevents[0], s);
+  for (int j = 0; j < nb && e == hipSuccess; ++j) {
+    const TileBucket& bk = b->buckets[j];
+    hipStream_t sj = par && j > 0 ? b->bstreams[j - 1] : s;
+    if (sj != s) e = hipStreamWaitEvent(sj, b->bevents[0], 0);
+    if (e == hipSuccess &&
+        !launch_tiles(bk.pl, bk.tune.seg_per_thread, bk.n_blocks, bk.tune.block_threads, flags, sj))
+      e = hipErrorInvalidValue;
+    if (e == hipSuccess && sj != s) e = hipEventRecord(b->bevents[j], sj);
+    if (e == hipSuccess && sj != s) e = hipStreamWaitEvent(s, b->bevents[j], 0);
+  }
+  if (after && e == hipSuccess) e = hipEventRecord(after, s);
+  if (e == hipSuccess) launch_reduce(b->pl, flags, s);
+  return e;
+}
+
 // Enqueue one whole frame of every instance; the first error of the
 // enqueued work (launch errors included).
 hipError_t enqueue_frame(sepso_batch* b, bool move) {
@@ -579,8 +631,7 @@ hipError_t enqueue_frame(sepso_batch* b, bool move) {
   for (auto& d : b->desc) tmax = std::max(tmax, d.T);
   hipError_t e = hipSuccess;
   for (int k = 0; k < tmax && e == hipSuccess; ++k)
-    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
-                    STEP_FIT | STEP_FRAME, b->stream);
+    e = enqueue_iteration(b, STEP_FIT | STEP_FRAME, true);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->h_ctl, b->pl.ctl, sizeof(InstCtl) * b->n, hipMemcpyDeviceToHost,
                        b->stream);
@@ -736,12 +787,8 @@ static sepso_status step_batch(sepso_batch* b, int32_t n) {
   if (st != SEPSO_OK) return st;
   if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
   hipError_t e = hipSuccess;
-  for (int k = 0; k < n && e == hipSuccess; ++k)
-    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, STEP_FIT,
-                    b->stream);
-  if (n > 0 && e == hipSuccess)
-    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0,
-                    b->stream);
+  for (int k = 0; k < n && e == hipSuccess; ++k) e = enqueue_iteration(b, STEP_FIT, false);
+  if (n > 0 && e == hipSuccess) e = enqueue_iteration(b, 0, false);
   if (e != hipSuccess) return hip_fail(b, e, "step launch");
   LAUNCHCHK(b, "step launch");
   return SEPSO_OK;
@@ -759,12 +806,9 @@ sepso_status sepso_step_frame(sepso_ctx* ctx, int32_t n) {
   if (st != SEPSO_OK) return st;
   if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
   hipError_t e = hipSuccess;
-  for (int k = 0; k < n && e == hipSuccess; ++k)
-    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
-                    STEP_FIT | STEP_FRAME, b->stream);
+  for (int k = 0; k < n && e == hipSuccess; ++k) e = enqueue_iteration(b, STEP_FIT | STEP_FRAME, false);
   if (n > 0 && e == hipSuccess)  // the pending update (nothing once the frame has ended)
-    e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
-                    STEP_FRAME, b->stream);
+    e = enqueue_iteration(b, STEP_FRAME, false);
   if (e != hipSuccess) return hip_fail(b, e, "step launch");
   LAUNCHCHK(b, "step launch");
   return SEPSO_OK;
@@ -960,12 +1004,9 @@ static sepso_status profile_batch(sepso_batch* b, int32_t n, float* avg_ms) {
   float total = 0.f;
   if (e == hipSuccess) {
     for (int k = 0; k < n && e == hipSuccess; ++k)
-      e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads,
-                      STEP_FIT, b->stream, ev[2 * k], ev[2 * k + 1]);
+      e = enqueue_iteration(b, STEP_FIT, false, ev[2 * k], ev[2 * k + 1]);
     if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess)
-      e = launch_step(b->pl, b->tune.seg_per_thread, b->tile_blocks, b->tune.block_threads, 0,
-                      b->stream);
+    if (e == hipSuccess) e = enqueue_iteration(b, 0, false);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     for (int k = 0; k < n && e == hipSuccess; ++k) {
       float ms = 0.f;
@@ -1031,14 +1072,17 @@ sepso_status sepso_batch_work(sepso_batch* b, double* tests, double* elems) {
 namespace {
 
 // Back to the state of a new batch: control blocks as created (random-stream
-// counters, frame index, previous plan and learned-start flags zero), then the
-// frame-0 initial swarm.  Synchronous.
+// counters, frame index, previous plan and learned-start flags zero), the
+// hyper-parameters as created (the online outer step moves them during a
+// frame), then the frame-0 initial swarm.  Synchronous.
 sepso_status restart(sepso_batch* b) {
   std::vector<InstCtl> ctl(b->n);
   std::memset(ctl.data(), 0, sizeof(InstCtl) * b->n);
   for (InstCtl& c : ctl) c.tb_f = INFINITY;
   HIPCHK(b, hipMemcpyAsync(b->pl.ctl, ctl.data(), sizeof(InstCtl) * b->n, hipMemcpyHostToDevice,
                            b->stream));
+  HIPCHK(b, hipMemcpyAsync(b->pl.hyper, b->h_hyper0.data(), sizeof(float) * b->h_hyper0.size(),
+                           hipMemcpyHostToDevice, b->stream));
   launch_init(b->pl, init_blocks(b), 0, 0, b->stream);
   LAUNCHCHK(b, "init launch");
   HIPCHK(b, hipStreamSynchronize(b->stream));
@@ -1058,7 +1102,7 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
   for (int K : Ks)
     for (int B : Bs) {
       if (!tune_ok(K, B, b->desc)) continue;
-      b->tune = sepso_tune{K, B};
+      set_single(b, sepso_tune{K, B});
       st = upload_tiles(b);
       if (st != SEPSO_OK) return st;
       float ms = 0.f;
@@ -1071,7 +1115,7 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best) {
         win = b->tune;
       }
     }
-  b->tune = win;
+  set_single(b, win);
   st = upload_tiles(b);
   if (st == SEPSO_OK) st = restart(b);
   if (st != SEPSO_OK) return st;
@@ -1136,7 +1180,7 @@ sepso_status sepso_autotune_cached(sepso_batch* b, const char* cache_path, sepso
     fclose(f);
     if (bad) return fail(SEPSO_E_ARG, "tune cache %s: read error", cache_path);
     if (hit) {
-      b->tune = t;
+      set_single(b, t);
       st = upload_tiles(b);
       if (st == SEPSO_OK) st = restart(b);
       if (st != SEPSO_OK) return st;
@@ -1162,8 +1206,258 @@ sepso_status sepso_batch_set_tune(sepso_batch* b, const sepso_tune* tune) {
   if (st != SEPSO_OK) return st;
   if (!tune_ok(tune->seg_per_thread, tune->block_threads, b->desc))
     return fail(SEPSO_E_ARG, "%s", kTuneRule);
-  b->tune = *tune;
+  set_single(b, *tune);
   return upload_tiles(b);
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxBuckets = 8;
+
+// Side streams (default priority) and fork / join events for the buckets.
+sepso_status ensure_bucket_streams(sepso_batch* b) {
+  const int nb = (int)b->buckets.size();
+  while ((int)b->bstreams.size() < nb - 1) {
+    hipStream_t x = nullptr;
+    HIPCHK(b, hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    b->bstreams.push_back(x);
+  }
+  while ((int)b->bevents.size() < nb) {
+    hipEvent_t x = nullptr;
+    HIPCHK(b, hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    b->bevents.push_back(x);
+  }
+  return SEPSO_OK;
+}
+
+// Mean device time of bucket j's tile kernel alone over n launches (events
+// around it; each launch is followed by the reduce of every instance).
+sepso_status profile_bucket(sepso_batch* b, int j, int n, float* avg_ms) {
+  const TileBucket& bk = b->buckets[j];
+  std::vector<hipEvent_t> ev(2 * (size_t)n, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t q = 0; q < ev.size() && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+  float total = 0.f;
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    e = hipEventRecord(ev[2 * k], b->stream);
+    if (e == hipSuccess && !launch_tiles(bk.pl, bk.tune.seg_per_thread, bk.n_blocks,
+                                         bk.tune.block_threads, STEP_FIT, b->stream))
+      e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], b->stream);
+    if (e == hipSuccess) launch_reduce(b->pl, STEP_FIT, b->stream);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+    total += ms;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(b, e, "profile bucket");
+  *avg_ms = total / (float)n;
+  return SEPSO_OK;
+}
+
+// Tune-cache key of one bucket: as the batch key, over the bucket's instances.
+uint64_t bucket_key(const sepso_batch* b, const TileBucket& bk) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  };
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    mix(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+  const uint64_t src = SEPSO_KERNELS_ID;
+  mix(&src, sizeof(src));
+  const char tag[] = "bucket";
+  mix(tag, sizeof(tag));
+  const int32_t n = (int32_t)bk.inst.size();
+  mix(&n, sizeof(n));
+  for (int i : bk.inst) {
+    const InstDesc& d = b->desc[i];
+    const int32_t f[5] = {d.G, d.N, d.W, d.n_rects, d.n_gedges};
+    mix(f, sizeof(f));
+  }
+  return h;
+}
+
+std::vector<InstDesc> bucket_desc(const sepso_batch* b, const std::vector<int>& inst) {
+  std::vector<InstDesc> sub;
+  for (int i : inst) sub.push_back(b->desc[i]);
+  return sub;
+}
+
+// Instances split by waypoint count (the tile's chunk fit) into at most
+// max_b buckets of about equal size, equal counts kept together.
+std::vector<std::vector<int>> split_by_waypoints(const sepso_batch* b, int max_b) {
+  std::vector<int> idx(b->n);
+  for (int i = 0; i < b->n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return b->desc[x].W < b->desc[y].W; });
+  std::vector<std::vector<int>> out(1);
+  const int target = (b->n + max_b - 1) / max_b;
+  for (size_t k = 0; k < idx.size(); ++k) {
+    if (!out.back().empty() && (int)out.back().size() >= target && (int)out.size() < max_b &&
+        b->desc[idx[k]].W != b->desc[idx[k - 1]].W)
+      out.emplace_back();
+    out.back().push_back(idx[k]);
+  }
+  for (auto& v : out) std::sort(v.begin(), v.end());
+  return out;
+}
+
+void report_tiles(const sepso_batch* b, sepso_tune* tiles, int32_t* bucket_of, int32_t* n_buckets) {
+  for (size_t j = 0; j < b->buckets.size(); ++j) {
+    if (tiles) tiles[j] = b->buckets[j].tune;
+    if (bucket_of)
+      for (int i : b->buckets[j].inst) bucket_of[i] = (int32_t)j;
+  }
+  if (n_buckets) *n_buckets = (int32_t)b->buckets.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+sepso_status sepso_batch_set_tiles(sepso_batch* b, int32_t n_buckets, const int32_t* bucket_of,
+                                   const sepso_tune* tiles) {
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (n_buckets < 1 || n_buckets > kMaxBuckets || !bucket_of || !tiles)
+    return fail(SEPSO_E_ARG, "set_tiles: 1 <= n_buckets <= %d, bucket_of and tiles required", kMaxBuckets);
+  std::vector<TileBucket> bks(n_buckets);
+  for (int i = 0; i < b->n; ++i) {
+    if (bucket_of[i] < 0 || bucket_of[i] >= n_buckets)
+      return fail(SEPSO_E_ARG, "set_tiles: bucket_of[%d] = %d out of range", i, bucket_of[i]);
+    bks[bucket_of[i]].inst.push_back(i);
+  }
+  for (int j = 0; j < n_buckets; ++j) {
+    if (bks[j].inst.empty()) return fail(SEPSO_E_ARG, "set_tiles: bucket %d is empty", j);
+    if (!tune_ok(tiles[j].seg_per_thread, tiles[j].block_threads, bucket_desc(b, bks[j].inst)))
+      return fail(SEPSO_E_ARG, "set_tiles: bucket %d: %s", j, kTuneRule);
+    bks[j].tune = tiles[j];
+  }
+  b->buckets = std::move(bks);
+  b->tune = tiles[0];
+  st = ensure_bucket_streams(b);
+  if (st != SEPSO_OK) return st;
+  return upload_tiles(b);
+}
+
+sepso_status sepso_autotune_buckets(sepso_batch* b, int32_t max_buckets, const char* cache_path,
+                                    sepso_tune* tiles, int32_t* bucket_of, int32_t* n_buckets,
+                                    float* frame_ms) {
+  sepso_status st = usable(b);
+  if (st != SEPSO_OK) return st;
+  if (max_buckets < 1 || max_buckets > kMaxBuckets || !tiles)
+    return fail(SEPSO_E_ARG, "autotune_buckets: 1 <= max_buckets <= %d and tiles required", kMaxBuckets);
+  // the one-tile baseline
+  sepso_tune global{};
+  st = sepso_autotune(b, &global);
+  if (st != SEPSO_OK) return st;
+  const std::vector<std::vector<int>> parts = split_by_waypoints(b, max_buckets);
+  if (parts.size() < 2) {
+    if (frame_ms) frame_ms[0] = frame_ms[1] = NAN;
+    report_tiles(b, tiles, bucket_of, n_buckets);
+    return SEPSO_OK;
+  }
+  // cached tiles of these buckets
+  std::vector<std::pair<unsigned long long, sepso_tune>> cache;
+  if (cache_path)
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[256];
+      while (fgets(line, sizeof line, f)) {
+        unsigned long long k = 0;
+        int K = 0, B = 0;
+        if (sscanf(line, "%llx %d %d", &k, &K, &B) == 3) cache.push_back({k, sepso_tune{K, B}});
+      }
+      const bool bad = ferror(f) != 0;
+      fclose(f);
+      if (bad) return fail(SEPSO_E_ARG, "tune cache %s: read error", cache_path);
+    }
+  std::vector<TileBucket> bks(parts.size());
+  for (size_t j = 0; j < parts.size(); ++j) {
+    bks[j].inst = parts[j];
+    bks[j].tune = default_tune(bucket_desc(b, parts[j]));
+  }
+  b->buckets = bks;
+  st = ensure_bucket_streams(b);
+  if (st != SEPSO_OK) return st;
+  std::vector<std::pair<unsigned long long, sepso_tune>> fresh;
+  const int Ks[] = {4, 8, 12, 16, 24};
+  const int Bs[] = {64, 128, 256};
+  for (size_t j = 0; j < b->buckets.size(); ++j) {
+    const std::vector<InstDesc> sub = bucket_desc(b, b->buckets[j].inst);
+    const unsigned long long key = bucket_key(b, b->buckets[j]);
+    bool hit = false;
+    for (auto& c : cache)
+      if (c.first == key && tune_ok(c.second.seg_per_thread, c.second.block_threads, sub)) {
+        b->buckets[j].tune = c.second;
+        hit = true;
+      }
+    if (hit) continue;
+    sepso_tune win = b->buckets[j].tune;
+    float win_ms = INFINITY;
+    for (int K : Ks)
+      for (int B : Bs) {
+        if (!tune_ok(K, B, sub)) continue;
+        b->buckets[j].tune = sepso_tune{K, B};
+        st = upload_tiles(b);
+        float ms = 0.f;
+        if (st == SEPSO_OK) st = profile_bucket(b, (int)j, 1, &ms);  // warm-up
+        if (st == SEPSO_OK) st = profile_bucket(b, (int)j, 3, &ms);
+        if (st != SEPSO_OK) return st;
+        if (ms < win_ms) {
+          win_ms = ms;
+          win = b->buckets[j].tune;
+        }
+      }
+    b->buckets[j].tune = win;
+    fresh.push_back({key, win});
+  }
+  // one frame from the frame-0 swarm each way; the faster plan stays
+  std::vector<TileBucket> chosen = b->buckets;
+  float ms_buckets = 0.f, ms_global = 0.f;
+  st = upload_tiles(b);
+  if (st == SEPSO_OK) st = restart(b);
+  if (st == SEPSO_OK) st = run_frame(b, false, &ms_buckets);
+  if (st != SEPSO_OK) return st;
+  set_single(b, global);
+  st = upload_tiles(b);
+  if (st == SEPSO_OK) st = restart(b);
+  if (st == SEPSO_OK) st = run_frame(b, false, &ms_global);
+  if (st != SEPSO_OK) return st;
+  if (frame_ms) {
+    frame_ms[0] = ms_buckets;
+    frame_ms[1] = ms_global;
+  }
+  if (ms_buckets < ms_global) {
+    b->buckets = chosen;
+    b->tune = chosen[0].tune;
+    st = upload_tiles(b);
+    if (st != SEPSO_OK) return st;
+  }
+  st = restart(b);
+  if (st != SEPSO_OK) return st;
+  if (cache_path && !fresh.empty()) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return fail(SEPSO_E_ARG, "tune cache %s: cannot open for writing", cache_path);
+    bool ok = true;
+    for (auto& c : fresh)
+      ok = ok && fprintf(f, "%016llx %d %d\n", c.first, c.second.seg_per_thread,
+                         c.second.block_threads) > 0;
+    if (fclose(f) != 0 || !ok) return fail(SEPSO_E_ARG, "tune cache %s: write failed", cache_path);
+  }
+  report_tiles(b, tiles, bucket_of, n_buckets);
+  return SEPSO_OK;
 }
 
 sepso_status sepso_set_tune(sepso_ctx* ctx, const sepso_tune* tune) {

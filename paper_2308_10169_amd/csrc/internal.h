@@ -38,11 +38,23 @@ struct Layout {
 
 struct sepso_lin;
 
+namespace sepso {
+// Instances that share one tile shape of the fused iteration: one launch per
+// bucket and iteration over its slice of the block table.
+struct TileBucket {
+  sepso_tune tune{16, 256};
+  std::vector<int> inst;      // instance indices
+  int first_block = 0, n_blocks = 0;
+  Pools pl{};                 // the batch's pools with this bucket's block slice and LDS sizing
+};
+}  // namespace sepso
+
 struct sepso_batch {
   int n = 0;
   std::vector<sepso::InstDesc> desc;
   std::vector<int> n_vert;
   std::vector<int32_t> h_pptr;  // polygon offsets of instance 0
+  std::vector<float> h_hyper0;  // every instance's hyper-parameters as created
   std::vector<int2> h_kind;     // polygon kinds of instance 0
   std::vector<int64_t> path_off;
   sepso::Layout lay{};
@@ -51,7 +63,10 @@ struct sepso_batch {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool broken = false;
-  sepso_tune tune{16, 256};
+  sepso_tune tune{16, 256};    // the tile of every instance when there is one bucket
+  std::vector<sepso::TileBucket> buckets;  // always >= 1 after creation
+  std::vector<hipStream_t> bstreams;       // side streams for concurrent bucket launches
+  std::vector<hipEvent_t> bevents;         // [0] fork, [1 + j] bucket j done
   int tile_blocks = 0;
   int frames_done = 0;
   int tune_gen = 0;  // bumped whenever the tile plan changes (captured graphs go stale)

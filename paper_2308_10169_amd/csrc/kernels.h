@@ -14,11 +14,11 @@ bool step_supported(int K);
 // 32-bit words of dynamic LDS the fused iteration takes per block.
 size_t iter_lds_words(int pos_floats, int stage_floats, int gb_floats, int ngb_max, int ppb_max,
                       int threads);
-// One iteration: the fused (or update-only) tile kernel, then the per-instance
-// reduce; events, when given, bracket the tile kernel alone.  Returns the
-// event records' status (launch errors are left for hipGetLastError).
-hipError_t launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
-                       hipEvent_t before = nullptr, hipEvent_t after = nullptr);
+// One iteration's tile kernel (fused, or the update alone without
+// STEP_FIT) over n_blocks entries of pl.blk_tiles; false for an unsupported K.
+bool launch_tiles(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s);
+// The per-instance reduce that follows the tile kernels of an iteration.
+void launch_reduce(const Pools& pl, int flags, hipStream_t s);
 void launch_evolve_init(const EvolveDev& ev, const Pools& pl, hipStream_t s);
 void launch_evolve_step(const EvolveDev& ev, const Pools& pl, int injected, hipStream_t s);
 

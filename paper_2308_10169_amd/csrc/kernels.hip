@@ -1037,10 +1037,7 @@ size_t iter_lds_bytes(const Pools& pl, int threads) {
 bool step_supported(int K) { return K == 4 || K == 8 || K == 12 || K == 16 || K == 24; }
 
 template <int K>
-static hipError_t launch_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s,
-                           hipEvent_t before, hipEvent_t after) {
-  hipError_t e = hipSuccess;
-  if (before) e = hipEventRecord(before, s);
+static void launch_tiles_k(const Pools& pl, int n_blocks, int threads, int flags, hipStream_t s) {
   const size_t lds = iter_lds_bytes(pl, threads);
   if ((flags & STEP_FIT) && pl.rsplit == 4)
     hipLaunchKernelGGL((iter_kernel_split<K, 4>), dim3(n_blocks), dim3(threads), lds, s, pl, flags);
@@ -1049,27 +1046,27 @@ static hipError_t launch_k(const Pools& pl, int n_blocks, int threads, int flags
   else if (flags & STEP_FIT)
     hipLaunchKernelGGL(iter_kernel<K>, dim3(n_blocks), dim3(threads), lds, s, pl, flags);
   else
-    hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), iter_lds_bytes(pl, threads),
-                       s, pl, flags);
-  if (after && e == hipSuccess) e = hipEventRecord(after, s);
+    hipLaunchKernelGGL(update_kernel<K>, dim3(n_blocks), dim3(threads), lds, s, pl, flags);
+}
+
+bool launch_tiles(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s) {
+  if (n_blocks <= 0) return true;
+  switch (K) {
+    case 4: launch_tiles_k<4>(pl, n_blocks, threads, flags, s); return true;
+    case 8: launch_tiles_k<8>(pl, n_blocks, threads, flags, s); return true;
+    case 12: launch_tiles_k<12>(pl, n_blocks, threads, flags, s); return true;
+    case 16: launch_tiles_k<16>(pl, n_blocks, threads, flags, s); return true;
+    case 24: launch_tiles_k<24>(pl, n_blocks, threads, flags, s); return true;
+    default: return false;
+  }
+}
+
+void launch_reduce(const Pools& pl, int flags, hipStream_t s) {
   // few instances: eight waves per block, so that each of (typically) eight
   // groups gets a wave of its own and the launch's latency is one scan;
   // a full batch keeps four waves per block (more blocks resident)
   const int red_threads = pl.n_inst < 256 ? 512 : 256;
   hipLaunchKernelGGL(reduce_kernel, dim3(pl.n_inst), dim3(red_threads), 0, s, pl, flags);
-  return e;
-}
-
-hipError_t launch_step(const Pools& pl, int K, int n_blocks, int threads, int flags, hipStream_t s,
-                       hipEvent_t before, hipEvent_t after) {
-  switch (K) {
-    case 4: return launch_k<4>(pl, n_blocks, threads, flags, s, before, after);
-    case 8: return launch_k<8>(pl, n_blocks, threads, flags, s, before, after);
-    case 12: return launch_k<12>(pl, n_blocks, threads, flags, s, before, after);
-    case 16: return launch_k<16>(pl, n_blocks, threads, flags, s, before, after);
-    case 24: return launch_k<24>(pl, n_blocks, threads, flags, s, before, after);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 // ---------------------------------------------------------------------------

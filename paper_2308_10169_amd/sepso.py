@@ -139,6 +139,8 @@ def _load():
     L.sepso_batch_work.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.sepso_batch_history.argtypes = [vp, fp]
     L.sepso_batch_set_tune.argtypes = [vp, C.POINTER(CTune)]
+    L.sepso_batch_set_tiles.argtypes = [vp, C.c_int32, ip, C.POINTER(CTune)]
+    L.sepso_autotune_buckets.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(CTune), ip, ip, fp]
     L.sepso_bf_workspace_bytes.argtypes = [C.POINTER(CBFCfg), C.POINTER(sz)]
     L.sepso_bf_create.argtypes = [C.POINTER(CBFCfg), vp, sz, vp, C.POINTER(vp)]
     L.sepso_bf_destroy.argtypes = [vp]
@@ -464,6 +466,29 @@ class BatchPlanner:
         ms = C.c_float()
         _check(_lib.sepso_batch_profile_step(self.h, int(n), C.byref(ms)))
         return ms.value
+
+    def set_tiles(self, bucket_of, tiles):
+        """Tiles per bucket: bucket_of[i] is instance i's bucket, tiles[j] =
+        (K, block_threads) of bucket j."""
+        bo = np.ascontiguousarray(bucket_of, dtype=np.int32)
+        tl = (CTune * len(tiles))(*[CTune(int(k), int(b)) for k, b in tiles])
+        _check(_lib.sepso_batch_set_tiles(self.h, len(tiles), bo.ctypes.data_as(ip), tl))
+
+    def autotune_buckets(self, max_buckets=4, cache_path=None, frame_ms=False):
+        """Per-bucket tiles by the autotuner: returns (tiles, bucket_of) --
+        one tile in the list when a single tile for all instances planned its
+        frame faster -- and, with frame_ms, the two frames' device times
+        (buckets, one tile)."""
+        tl = (CTune * max_buckets)()
+        bo = np.zeros(self.n, np.int32)
+        nb = C.c_int32()
+        ms = np.zeros(2, np.float32)
+        _check(_lib.sepso_autotune_buckets(self.h, int(max_buckets),
+                                           cache_path.encode() if cache_path else None, tl,
+                                           bo.ctypes.data_as(ip), C.byref(nb),
+                                           ms.ctypes.data_as(fp)))
+        tiles = [(tl[j].seg_per_thread, tl[j].block_threads) for j in range(nb.value)]
+        return (tiles, bo, tuple(float(v) for v in ms)) if frame_ms else (tiles, bo)
 
     def autotune(self, cache_path=None):
         """Time the tile candidates (or take this batch's entry of the tune

@@ -117,3 +117,10 @@ def test_negative_vlimit_rejected(lib):
 def test_tune_cache_and_set_tune_need_a_batch(lib):
     assert lib.sepso_autotune_cached(None, b"/tmp/x", None) == 1
     assert lib.sepso_batch_set_tune(None, None) == 1
+
+
+def test_bucket_calls_reject_null_batch(lib):
+    tl = (C.c_int32 * 2)(8, 256)
+    bo = (C.c_int32 * 1)(0)
+    assert lib.sepso_batch_set_tiles(None, 1, bo, tl) == 1
+    assert lib.sepso_autotune_buckets(None, 2, None, tl, bo, None, None) == 1

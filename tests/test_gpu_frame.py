@@ -156,6 +156,53 @@ def test_batch_equals_solo(sp):
     bp.close()
 
 
+def test_buckets_equal_solo(sp):
+    # Tiles per bucket: a ragged batch in three buckets by waypoint count on
+    # three different tiles (one launch per bucket per iteration, side by side
+    # in the frame graph); every instance plans exactly as it does alone on
+    # its bucket's tile.
+    specs, sws = _ragged(9)
+    order = np.argsort([s.waypoints for s in sws], kind="stable")
+    bucket_of = np.zeros(9, np.int32)
+    bucket_of[order[3:6]] = 1
+    bucket_of[order[6:]] = 2
+    tiles = [(4, 128), (8, 256), (12, 64)]
+    bp = sp.BatchPlanner(specs, sws)
+    bp.set_tiles(bucket_of, tiles)
+    rb = bp.plan(3, want_paths=True)
+    for i in range(9):
+        solo = sp.BatchPlanner([specs[i]], [sws[i]], tune=tiles[bucket_of[i]])
+        rs = solo.plan(3, want_paths=True)
+        assert np.array_equal(rs["cost"][:, 0], rb["cost"][:, i])
+        assert np.array_equal(rs["iters"][:, 0], rb["iters"][:, i])
+        assert np.array_equal(rs["paths"][0], rb["paths"][i])
+        solo.close()
+    bp.close()
+
+
+def test_autotune_buckets(sp, tmp_path):
+    # The per-bucket autotuner leaves the batch as new, under the tiles it
+    # reports; a second run takes every bucket's tile from the cache file.
+    specs, sws = _ragged(12)
+    bp = sp.BatchPlanner(specs, sws)
+    cache = str(tmp_path / "tiles.txt")
+    tiles, bo = bp.autotune_buckets(max_buckets=3, cache_path=cache)
+    print("bucket tiles", tiles, bo.tolist(), flush=True)
+    assert 1 <= len(tiles) <= 3 and set(bo.tolist()) == set(range(len(tiles)))
+    r1 = bp.plan(2, want_paths=True)
+    fresh = sp.BatchPlanner(specs, sws)
+    fresh.set_tiles(bo, tiles)
+    r2 = fresh.plan(2, want_paths=True)
+    assert np.array_equal(r1["cost"], r2["cost"]) and np.array_equal(r1["iters"], r2["iters"])
+    assert all(np.array_equal(a, c) for a, c in zip(r1["paths"], r2["paths"]))
+    lines = open(cache).read().splitlines()
+    assert len(lines) >= 2
+    bp.autotune_buckets(max_buckets=3, cache_path=cache)
+    assert open(cache).read().splitlines() == lines
+    fresh.close()
+    bp.close()
+
+
 def test_batch_paths_score_as_reported(sp):
     specs, sws = _ragged(6)
     bp = sp.BatchPlanner(specs, sws)
