@@ -1,7 +1,9 @@
 """Learned initializer workflow on the GPU: the planner generates its own
 training set (converged group bests on random single-plan maps), the MLP is
 trained by the library's BF16 MFMA kernels, and the trained network is
-compared with the plain planner on held-out maps.
+compared with the plain planner on held-out maps (a uniform first frame) and
+on held-out dynamic sequences (plain Priori Initialization from the previous
+frame's plan).
 
   python -m paper_2308_10169_amd.learned --samples 32768 --steps 2000
 
@@ -77,6 +79,78 @@ def evaluate(lin, n_maps=512, seed=2_000_000, iters=50):
                 first_iter_cost_learned=float(np.median(h_lin[:, 0])))
 
 
+def dynamic_maps(n, seed, vmax=1.0):
+    """Held-out dynamic sequences on the training generator's maps: every
+    rectangle moves by a constant velocity uniform in +-vmax cells per frame
+    (bouncing off the walls), start and target move vertically by half a
+    cell per frame; all on the 1/256 grid."""
+    maps = I.random_static_maps(n, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    for m in maps:
+        m.poly_vel = I.snap(rng.uniform(-vmax, vmax, size=(m.n_polys, 2)))
+        m.endpoint_vel = I.snap(np.array([0.0, rng.choice([-0.5, 0.5]), 0.0, rng.choice([-0.5, 0.5])]))
+    return maps
+
+
+def evaluate_dynamic(lin, n_maps=256, frames=6, seed=3_000_000, iters=50, tune=(12, 256)):
+    """Learned start against plain Priori Initialization on dynamic
+    sequences: both planners run every frame to the iteration cap (no Auto
+    Truncation); the plain one seeds frames after the first from its
+    previous plan, the learned one from the network's proposals for the
+    moved map.  Per frame after the first: iterations each needs to reach
+    the plain planner's final cost of that frame, and the time to get there
+    -- iterations x the measured time per iteration, plus the network's
+    inference per frame for the learned start (the difference of the two
+    planners' measured frame times)."""
+    import torch
+    maps = dynamic_maps(n_maps, seed)
+    runs = {}
+    for tag, use in (("plain", None), ("learned", lin)):
+        sws = [I.learned_swarm(seed=seed, instance=i, iters=iters) for i in range(n_maps)]
+        for sw in sws:
+            sw.use_pi = 1
+        bp = sepso.BatchPlanner(maps, sws, tune=tune)
+        bp.attach(use)
+        bp.plan(1)  # warm-up frame: captures the frame graphs
+        bp.close()
+        bp = sepso.BatchPlanner(maps, sws, tune=tune)
+        bp.attach(use)
+        cost, hist, secs = [], [], []
+        for _ in range(frames):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = bp.plan(1)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            cost.append(r["cost"][0])
+            hist.append(bp.history()[:, :iters])
+        bp.close()
+        runs[tag] = (np.array(cost), np.array(hist), np.array(secs))
+    c_p, h_p, t_p = runs["plain"]
+    c_l, h_l, t_l = runs["learned"]
+    it_p = np.stack([iters_to_reach(h_p[f], c_p[f]) for f in range(1, frames)])
+    it_l = np.stack([iters_to_reach(h_l[f], c_p[f]) for f in range(1, frames)])
+    t_iter = float(np.median(t_p[1:])) / iters          # both run `iters` iterations per frame
+    t_infer = max(0.0, float(np.median(t_l[1:]) - np.median(t_p[1:])))
+    ms_p = 1e3 * t_iter * it_p
+    ms_l = 1e3 * (t_infer + t_iter * it_l)
+    return dict(maps=n_maps, frames=frames,
+                median_iters_plain_pi=float(np.median(it_p)),
+                median_iters_learned=float(np.median(it_l)),
+                mean_iters_plain_pi=float(np.mean(it_p)), mean_iters_learned=float(np.mean(it_l)),
+                frac_learned_fewer_iters=float(np.mean(it_l < it_p)),
+                frac_learned_reaches=float(np.mean(it_l <= iters)),
+                frame_ms_plain=1e3 * float(np.median(t_p[1:])),
+                frame_ms_learned=1e3 * float(np.median(t_l[1:])),
+                batch_ms_per_iter=1e3 * t_iter, inference_ms_per_frame=1e3 * t_infer,
+                median_ms_to_reach_plain_pi=float(np.median(ms_p)),
+                median_ms_to_reach_learned=float(np.median(ms_l)),
+                median_cost_plain_pi=float(np.median(c_p[1:])),
+                median_cost_learned=float(np.median(c_l[1:])),
+                frame0_median_iters_uniform=float(np.median(iters_to_reach(h_p[0], c_p[0]))),
+                frame0_median_iters_learned=float(np.median(iters_to_reach(h_l[0], c_p[0]))))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=32768)
@@ -84,6 +158,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--heldout", type=int, default=512)
+    ap.add_argument("--dynamic", type=int, default=256, help="held-out dynamic sequences")
     ap.add_argument("--out", default=None, help="write trained weights (.npy) here")
     args = ap.parse_args()
     lin = sepso.LearnedInit(max_rows=4096, max_samples=args.samples, seed=0)
@@ -93,6 +168,8 @@ def main():
     loss = lin.train(args.steps, args.batch, args.lr)
     t2 = time.perf_counter()
     ev = evaluate(lin, n_maps=args.heldout)
+    if args.dynamic > 0:
+        ev["dynamic"] = evaluate_dynamic(lin, n_maps=args.dynamic)
     if args.out:
         np.save(args.out, lin.get_weights())
     print(json.dumps(dict(samples=n, gen_s=t1 - t0, train_s=t2 - t1, steps=args.steps,

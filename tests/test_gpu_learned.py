@@ -88,21 +88,43 @@ def test_raster_features_match_oracle(sp):
     bp.close()
 
 
-def test_learned_start_beats_plain_planner(sp):
-    # The planner generates its own training set, the network is trained on
-    # the GPU, and on held-out maps the learned start reaches the plain
-    # planner's final cost in fewer iterations.
+@pytest.fixture(scope="module")
+def trained(sp):
+    # The planner generates its own training set and the network is trained
+    # on the GPU (32768 samples, 2000 Adam steps of 256).
     from paper_2308_10169_amd import learned
-    lin = sp.LearnedInit(max_rows=4096, max_samples=8192, seed=0)
-    n = learned.generate(lin, 8192, seed=7)
-    assert n == 8192
-    loss = lin.train(600, batch=256, lr=1e-3)
+    lin = sp.LearnedInit(max_rows=4096, max_samples=32768, seed=0)
+    n = learned.generate(lin, 32768, seed=7)
+    assert n == 32768
+    loss = lin.train(2000, batch=256, lr=1e-3)
     assert loss[-20:].mean() < 0.5 * loss[:20].mean()
-    ev = learned.evaluate(lin, n_maps=256, seed=3_000_000)
+    yield lin
+    lin.close()
+
+
+def test_learned_start_beats_plain_planner(trained):
+    # On held-out static maps the learned start reaches the plain planner's
+    # final cost (from a uniform swarm) in fewer iterations.
+    from paper_2308_10169_amd import learned
+    ev = learned.evaluate(trained, n_maps=256, seed=3_000_000)
     print("learned vs plain", ev)
     assert ev["median_iters_learned"] < ev["median_iters_plain"]
     assert ev["first_iter_cost_learned"] < ev["first_iter_cost_plain"]
-    lin.close()
+
+
+def test_learned_start_against_priori_initialization(trained):
+    # Held-out dynamic sequences (moving rectangles and endpoints), six frames
+    # to the iteration cap: the learned start against plain Priori
+    # Initialization from the previous frame's plan, on the iterations and
+    # the time (network inference included) to reach plain PI's final cost.
+    from paper_2308_10169_amd import learned
+    ev = learned.evaluate_dynamic(trained, n_maps=256, frames=6)
+    print("learned vs plain PI", ev)
+    assert ev["frame0_median_iters_learned"] < ev["frame0_median_iters_uniform"]
+    assert ev["frac_learned_reaches"] >= 0.3
+    assert ev["mean_iters_learned"] < ev["mean_iters_plain_pi"]
+    assert ev["median_cost_learned"] <= 1.02 * ev["median_cost_plain_pi"]
+    assert ev["inference_ms_per_frame"] < 0.25 * ev["frame_ms_plain"]
 
 
 def test_adam_matches_oracle(sp):
