@@ -20,7 +20,8 @@ const int kInPad[4] = {kLinInPad, kLinHidden, kLinHidden, kLinHidden};
 const int kInReal[4] = {kLinIn, kLinHidden, kLinHidden, kLinHidden};
 const int kOutN[4] = {kLinHidden, kLinHidden, kLinHidden, kLinOut};
 constexpr int kLossHist = 1 << 16;
-constexpr int64_t kSplitWs = 8 * 256 * kLinHidden;  // split-K slices (FP32)
+// split-K slices (FP32): up to four of the layer-1 weight gradient
+constexpr int64_t kSplitWs = 4 * kLinHidden * kLinInPad;
 
 int64_t n_params() {
   int64_t n = 0;
@@ -114,19 +115,19 @@ void backward(sepso_lin* L, const uint16_t* X, const float* T, int B, float* los
               hipStream_t s) {
   launch_loss(L->Y, T, B, kLinOut, L->dY, L->dY16, L->rowsq, s);
   launch_loss_sum(L->rowsq, B, 1.f / ((float)B * kLinOut), loss_slot, s);
-  launch_colsum(L->dY, B, kLinOut, L->gb[3], s);
+  launch_colsum(L->dY, B, kLinOut, L->gb[3], L->splitk, s);
   launch_gemm(true, true, L->dY16, kLinOut, L->A16[2], kLinHidden, kLinOut, kLinHidden, B,
               Epi{EPI_F32, nullptr, L->gW[3], nullptr, nullptr, kLinHidden}, L->splitk, kSplitWs, s);
   launch_gemm(false, true, L->dY16, kLinOut, L->W16[3], kLinHidden, B, kLinHidden, kLinOut,
               Epi{EPI_MASK, nullptr, L->dZ[2], L->dZ16[2], L->A16[2], kLinHidden}, L->splitk, kSplitWs, s);
   for (int l = 2; l >= 1; --l) {
-    launch_colsum(L->dZ[l], B, kLinHidden, L->gb[l], s);
+    launch_colsum(L->dZ[l], B, kLinHidden, L->gb[l], L->splitk, s);
     launch_gemm(true, true, L->dZ16[l], kLinHidden, L->A16[l - 1], kLinHidden, kLinHidden,
                 kLinHidden, B, Epi{EPI_F32, nullptr, L->gW[l], nullptr, nullptr, kLinHidden}, L->splitk, kSplitWs, s);
     launch_gemm(false, true, L->dZ16[l], kLinHidden, L->W16[l], kLinHidden, B, kLinHidden,
                 kLinHidden, Epi{EPI_MASK, nullptr, L->dZ[l - 1], L->dZ16[l - 1], L->A16[l - 1], kLinHidden}, L->splitk, kSplitWs, s);
   }
-  launch_colsum(L->dZ[0], B, kLinHidden, L->gb[0], s);
+  launch_colsum(L->dZ[0], B, kLinHidden, L->gb[0], L->splitk, s);
   launch_gemm(true, true, L->dZ16[0], kLinHidden, X, kLinInPad, kLinHidden, kLinInPad, B,
               Epi{EPI_F32, nullptr, L->gW[0], nullptr, nullptr, kLinInPad}, L->splitk, kSplitWs, s);
 }

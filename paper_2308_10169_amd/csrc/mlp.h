@@ -25,7 +25,8 @@ void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_
                  int M, int N, int K, const Epi& ep, float* ws, int64_t ws_floats, hipStream_t s);
 void launch_loss(const float* y, const float* target, int B, int n, float* dy, uint16_t* dy16,
                  float* row_sq, hipStream_t s);
-void launch_colsum(const float* dz, int B, int n, float* out, hipStream_t s);
+// ws: FP32 scratch of ceil(B / 256) x n (row-chunk partial sums).
+void launch_colsum(const float* dz, int B, int n, float* out, float* ws, hipStream_t s);
 void launch_loss_sum(const float* row_sq, int B, float scale, float* out, hipStream_t s);
 void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t s);
 // Parameter tensors updated by one Adam launch (p16 may be NULL per set).

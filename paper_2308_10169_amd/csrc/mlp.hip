@@ -159,6 +159,146 @@ __global__ __launch_bounds__(256) void gemm_kernel(const uint16_t* __restrict__ 
       }
 }
 
+// The same product on a 128 x 128 block tile for large problems: four waves
+// of 64 x 64 (4 x 4 MFMA 16x16x32 tiles, 64 accumulator registers), k-steps
+// of 32 double-buffered in LDS -- the next step's global loads are in flight
+// in registers while the current step's MFMAs run, one barrier per step.
+// Same contract as gemm_kernel.
+// One 32-wide k half-step of a 128-row operand tile (rows of the output
+// dimension x 32 k) into two registers per thread.  K-contiguous source
+// (KM = false): row t/2, k 16*(t&1) .. +15.  K-major source: k rows 2*(t/16)
+// and +1 at columns 8*(t%16) .. +7.  Rows (columns) past R, and a half-step
+// past the slice's end (valid = false), give zeros.
+template <bool KM>
+__device__ __forceinline__ void fetch128(const uint16_t* __restrict__ P, int ld, int r0, int R,
+                                         int k0, int t, bool valid, uint4& r0v, uint4& r1v) {
+  // an invalid row (column) or half-step reads the tile's first row at the
+  // slice's first k, which exists, and is zeroed: every load is unconditional
+  const uint4 zero = make_uint4(0, 0, 0, 0);
+  if (!KM) {
+    const int row = t >> 1, kc = (t & 1) * 16;
+    const bool ok = valid && r0 + row < R;
+    const uint16_t* src = P + (int64_t)(ok ? r0 + row : r0) * ld + (valid ? k0 : 0) + kc;
+    r0v = *reinterpret_cast<const uint4*>(src);
+    r1v = *reinterpret_cast<const uint4*>(src + 8);
+    if (!ok) r0v = r1v = zero;
+  } else {
+    const int kr = 2 * (t >> 4), mc = (t & 15) * 8;
+    const bool ok = valid && r0 + mc < R;
+    const uint16_t* src = P + (int64_t)((valid ? k0 : 0) + kr) * ld + (ok ? r0 + mc : r0);
+    r0v = *reinterpret_cast<const uint4*>(src);
+    r1v = *reinterpret_cast<const uint4*>(src + ld);
+    if (!ok) r0v = r1v = zero;
+  }
+}
+
+// The registers of fetch128 into an LDS tile of rows of LDS halves (k
+// contiguous) at k offset kh; a K-major operand is transposed two k values at
+// a time (one 32-bit store per row).
+template <bool KM, int LDS>
+__device__ __forceinline__ void stash128(uint16_t* S, int kh, int t, const uint4& r0v,
+                                         const uint4& r1v) {
+  if (!KM) {
+    const int row = t >> 1, kc = kh + (t & 1) * 16;
+    *reinterpret_cast<uint4*>(&S[row * LDS + kc]) = r0v;
+    *reinterpret_cast<uint4*>(&S[row * LDS + kc + 8]) = r1v;
+  } else {
+    const int kr = kh + 2 * (t >> 4), mc = (t & 15) * 8;
+    const uint32_t u0[4] = {r0v.x, r0v.y, r0v.z, r0v.w}, u1[4] = {r1v.x, r1v.y, r1v.z, r1v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {  // columns 2i, 2i+1: (k, k+1) as one 32-bit word each
+      *reinterpret_cast<uint32_t*>(&S[(mc + 2 * i) * LDS + kr]) =
+          __builtin_amdgcn_perm(u1[i], u0[i], 0x05040100u);
+      *reinterpret_cast<uint32_t*>(&S[(mc + 2 * i + 1) * LDS + kr]) =
+          __builtin_amdgcn_perm(u1[i], u0[i], 0x07060302u);
+    }
+  }
+}
+
+// The same product on a 128 x 128 block tile for large problems: four waves
+// of 64 x 64 (4 x 4 MFMA 16x16x32 tiles, 64 accumulator registers), k-steps
+// of 64 (two MFMA k-steps; a slice's last may be 32 wide) double-buffered in
+// LDS -- the next step's global loads are in flight in registers while the
+// current step's MFMAs run, one barrier per step.  Same contract as
+// gemm_kernel.
+template <bool A_KM, bool B_KN>
+__global__ __launch_bounds__(256) void gemm128_kernel(const uint16_t* __restrict__ A, int lda,
+                                                      const uint16_t* __restrict__ B, int ldb,
+                                                      int M, int N, int K, int kper, float* part,
+                                                      Epi ep) {
+  constexpr int T = 128, LDS = 72;  // padded row (k) length
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][T * LDS];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][T * LDS];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kbeg = blockIdx.z * kper * 32, kend = min(K, kbeg + kper * 32);
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  auto fetch = [&](int k0) {
+    const bool hi = k0 + 32 < kend;
+    fetch128<A_KM>(A, lda, m0, M, k0, t, true, ra0, ra1);
+    fetch128<A_KM>(A, lda, m0, M, k0 + 32, t, hi, ra2, ra3);
+    fetch128<B_KN>(B, ldb, n0, N, k0, t, true, rb0, rb1);
+    fetch128<B_KN>(B, ldb, n0, N, k0 + 32, t, hi, rb2, rb3);
+  };
+  auto stash = [&](int bf) {
+    stash128<A_KM, LDS>(As[bf], 0, t, ra0, ra1);
+    stash128<A_KM, LDS>(As[bf], 32, t, ra2, ra3);
+    stash128<B_KN, LDS>(Bs[bf], 0, t, rb0, rb1);
+    stash128<B_KN, LDS>(Bs[bf], 32, t, rb2, rb3);
+  };
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += 64) {
+    const bool more = k0 + 64 < kend;
+    if (more) fetch(k0 + 64);  // in flight during this step's MFMAs
+    const uint16_t* as = As[buf];
+    const uint16_t* bs = Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < 64; kk += 32) {  // the upper half of a short last step is zeros
+      bf16x8 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = *reinterpret_cast<const bf16x8*>(&as[(wm + i * 16 + r16) * LDS + kk + kq]);
+        b[i] = *reinterpret_cast<const bf16x8*>(&bs[(wn + i * 16 + r16) * LDS + kk + kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) stash(buf ^ 1);  // the other buffer: its last readers passed the previous barrier
+    __syncthreads();
+    buf ^= 1;
+  }
+  // D layout: lane holds column (lane % 16), rows 4*(lane/16) .. +3
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row >= M || col >= N) continue;
+        if (part)
+          part[((int64_t)blockIdx.z * M + row) * N + col] = acc[i][j][r];
+        else
+          apply_epi(ep, row, col, acc[i][j][r]);
+      }
+}
+
 // Sum of the S split-K slices of part in slice order, then the epilogue.
 __global__ __launch_bounds__(256) void splitk_epi_kernel(const float* __restrict__ part, int S,
                                                          int M, int N, Epi ep) {
@@ -220,21 +360,32 @@ __global__ __launch_bounds__(256) void targets_kernel(Pools pl, float* T, int ld
   }
 }
 
-// Column sums of a B x n FP32 matrix (bias gradients), in a fixed order: a
-// block takes 64 columns, its wave w sums rows w, w+4, ... (eight loads in
-// flight per lane), and the four partial sums are added in wave order.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int n, float* out) {
-  __shared__ float part[4][64];
+// Column sums of a B x n FP32 matrix (bias gradients), in a fixed order:
+// block (x, y) takes 64 columns of the row chunk [256y, 256y + 256), its
+// wave w sums rows w, w+4, ... of the chunk (eight loads in flight per lane)
+// and the four partial sums are added in wave order into part[y][col];
+// colsum_fin_kernel then adds the chunks in chunk order.
+__global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int n, float* part) {
+  __shared__ float ps[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
+  const int r0 = blockIdx.y * 256, r1 = min(B, r0 + 256);
   float s = 0.f;
   if (j < n) {
 #pragma unroll 8
-    for (int r = w; r < B; r += 4) s += dz[(int64_t)r * n + j];
+    for (int r = r0 + w; r < r1; r += 4) s += dz[(int64_t)r * n + j];
   }
-  part[w][lane] = s;
+  ps[w][lane] = s;
   __syncthreads();
-  if (w == 0 && j < n) out[j] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  if (w == 0 && j < n) part[(int64_t)blockIdx.y * n + j] = ((ps[0][lane] + ps[1][lane]) + ps[2][lane]) + ps[3][lane];
+}
+
+__global__ __launch_bounds__(256) void colsum_fin_kernel(const float* part, int R, int n, float* out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  float s = part[j];
+  for (int y = 1; y < R; ++y) s += part[(int64_t)y * n + j];
+  out[j] = s;
 }
 
 // Adam on FP32 master weights, refreshing the BF16 copies used by the GEMMs,
@@ -296,19 +447,32 @@ void launch_raster(const Pools& pl, int n_inst, uint16_t* X, int ldx, int32_t* e
 
 void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_t* B, int ldb,
                  int M, int N, int K, const Epi& ep, float* ws, int64_t ws_floats, hipStream_t s) {
-  // Split K while the tile grid leaves most CUs idle, as far as the k-steps
-  // and the workspace allow (measured: even two-step slices pay for their
-  // slice sum at the training shapes).
-  const int tiles = ((N + 63) / 64) * ((M + 63) / 64), steps = K / 32;
+  // 128 x 128 tiles once they alone give a quarter of the CUs a tile; then
+  // split K until the grid has two blocks per CU (a 128 x 128 block's LDS
+  // leaves room for two), as far as the k-steps and the workspace allow
+  // (measured: even two-step slices pay for their slice sum at the training
+  // shapes; 512 blocks against 256 took the batch-8192 step from 0.83 to
+  // 0.73 ms).
+  const int tiles128 = ((N + 127) / 128) * ((M + 127) / 128);
+  const int T = tiles128 >= 64 ? 128 : 64;
+  const int tiles = ((N + T - 1) / T) * ((M + T - 1) / T), steps = K / 32;
   int S = 1;
-  while (S < 8 && tiles * S * 2 <= 256 && S * 2 <= steps &&
-         (int64_t)S * 2 * M * N <= ws_floats)
+  while (S < 8 && tiles * S < 512 && S * 2 <= steps && (int64_t)S * 2 * M * N <= ws_floats)
     S *= 2;
   const int kper = steps > 0 ? (steps + S - 1) / S : 1;
   S = steps > 0 ? (steps + kper - 1) / kper : 1;
   float* part = S > 1 ? ws : nullptr;
-  const dim3 grid((N + 63) / 64, (M + 63) / 64, S);
-  if (!a_km && !b_kn)
+  const dim3 grid((N + T - 1) / T, (M + T - 1) / T, S);
+  if (T == 128) {
+    if (!a_km && !b_kn)
+      hipLaunchKernelGGL((gemm128_kernel<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+    else if (!a_km && b_kn)
+      hipLaunchKernelGGL((gemm128_kernel<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+    else if (a_km && b_kn)
+      hipLaunchKernelGGL((gemm128_kernel<true, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+    else
+      hipLaunchKernelGGL((gemm128_kernel<true, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+  } else if (!a_km && !b_kn)
     hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
   else if (!a_km && b_kn)
     hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
@@ -336,8 +500,10 @@ void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t 
   hipLaunchKernelGGL(targets_kernel, dim3(n_inst), dim3(256), 0, s, pl, T, ldt);
 }
 
-void launch_colsum(const float* dz, int B, int n, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((n + 63) / 64), dim3(256), 0, s, dz, B, n, out);
+void launch_colsum(const float* dz, int B, int n, float* out, float* ws, hipStream_t s) {
+  const int R = (B + 255) / 256;
+  hipLaunchKernelGGL(colsum_kernel, dim3((n + 63) / 64, R), dim3(256), 0, s, dz, B, n, ws);
+  hipLaunchKernelGGL(colsum_fin_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ws, R, n, out);
 }
 
 void launch_adam_sets(AdamSets a, float lr, float b1, float b2, float eps, float c1, float c2,

@@ -55,7 +55,10 @@ def test_forward_matches_oracle(sp):
     lin.close()
 
 
-@pytest.mark.parametrize("rows", [64, 256])  # 256: the training batch (split-K GEMMs)
+# 64, 256: the small-batch GEMMs (64 x 64 tiles, split K) and the layer-1
+# weight gradient on 128 x 128 tiles; 2048: every product of the step on
+# 128 x 128 tiles
+@pytest.mark.parametrize("rows", [64, 256, 2048])
 def test_gradients_match_oracle(sp, rows):
     lin = sp.LearnedInit(max_rows=rows, seed=5)
     W, b = sp.split_params(lin.get_weights().astype(np.float64))
