@@ -164,8 +164,8 @@ void orc_evolve_init(orc_evolve* h);
 void orc_evolve_step(orc_evolve* h, const double* lfv);
 
 /* Benchmark-function workload (Table BFs): DTPSO over [lo, hi]^D on one of
- * the four functions.  Random streams: counter (c0, c1, 0, tag), tags
- * BF_INIT_X / BF_INIT_V (c0 = 4-value block of the flat index, c1 = 0) and
+ * the four functions.  Random streams: counter (c0, c1, instance, tag), tags
+ * BF_INIT_X / BF_INIT_V (c0 = 4-value block of the flat index, c1 = run) and
  * BF_UPDATE (c0 = particle, c1 = ctr). */
 enum { ORC_BF_SPHERE = 1, ORC_BF_ROSENBROCK = 2, ORC_BF_RASTRIGIN = 3, ORC_BF_GRIEWANK = 4 };
 double orc_bf_value(int32_t func, int32_t D, const double* x);
@@ -182,6 +182,8 @@ typedef struct orc_bf {
   double tb_f;
   int32_t k;
   uint32_t ctr;
+  uint32_t instance;         /* counter word 2 of every draw: independent swarms */
+  uint32_t run;              /* counter word 1 of the initial draws: independent runs */
 } orc_bf;
 void orc_bf_init(orc_bf* s);
 void orc_bf_eval(orc_bf* s);     /* f = function value of X */

@@ -13,8 +13,8 @@
 static const double kInf = std::numeric_limits<double>::infinity();
 static const double kPi = 3.14159265358979323846;
 
-static void draw4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t tag, double u[4]) {
-  const uint32_t ctr[4] = {c0, c1, 0u, tag};
+static void draw4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag, double u[4]) {
+  const uint32_t ctr[4] = {c0, c1, c2, tag};
   const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
   uint32_t w[4];
   orc_philox4x32_10(ctr, key, w);
@@ -61,8 +61,8 @@ void orc_bf_init(orc_bf* s) {
       for (int32_t d = 0; d < D; ++d) {
         double ux[4], uv[4];
         const uint32_t c0 = (uint32_t)(i * nb + d / 4);
-        draw4(s->seed, c0, 0u, ORC_TAG_BF_INIT_X, ux);
-        draw4(s->seed, c0, 0u, ORC_TAG_BF_INIT_V, uv);
+        draw4(s->seed, c0, s->run, s->instance, ORC_TAG_BF_INIT_X, ux);
+        draw4(s->seed, c0, s->run, s->instance, ORC_TAG_BF_INIT_V, uv);
         const double x = lo + ux[d % 4] * (hi - lo);
         s->X[(size_t)i * D + d] = x;
         s->P[(size_t)i * D + d] = x;
@@ -126,7 +126,7 @@ void orc_bf_advance(orc_bf* s) {
     for (int32_t n = 0; n < N; ++n) {
       const int32_t i = g * N + n;
       double r[4];
-      draw4(s->seed, (uint32_t)i, s->ctr, ORC_TAG_BF_UPDATE, r);
+      draw4(s->seed, (uint32_t)i, s->ctr, s->instance, ORC_TAG_BF_UPDATE, r);
       double* x = s->X + (size_t)i * D;
       double* v = s->V + (size_t)i * D;
       const double* p = s->P + (size_t)i * D;

@@ -85,7 +85,8 @@ class OrcBF(C.Structure):
                 ("T", C.c_int32), ("lo", C.c_double), ("hi", C.c_double), ("hyper", dp),
                 ("seed", C.c_uint64), ("X", dp), ("V", dp), ("P", dp), ("f", dp), ("Pf", dp),
                 ("gbest_n", ip), ("gbest_f", dp), ("tb_g", C.c_int32), ("tb_n", C.c_int32),
-                ("tb_f", C.c_double), ("k", C.c_int32), ("ctr", C.c_uint32)]
+                ("tb_f", C.c_double), ("k", C.c_int32), ("ctr", C.c_uint32),
+                ("instance", C.c_uint32), ("run", C.c_uint32)]
 
 
 def lib():
@@ -326,7 +327,8 @@ def bf16(x):
 
 def mlp(sizes, W, b, x, target=None, round=True, grads=True):
     """FP64 MLP forward (+ backward when target given and grads).  W[l]:
-    (sizes[l+1], sizes[l]); returns dict(y, loss, gW, gb)."""
+    (sizes[l+1], sizes[l]); returns dict(y, loss, gW, gb, gWabs) -- gWabs[l]
+    the sum over the batch of |dz| |a| behind each weight-gradient element."""
     L = lib()
     nl = len(sizes) - 1
     sz = np.ascontiguousarray(sizes, dtype=np.int32)
@@ -344,14 +346,17 @@ def mlp(sizes, W, b, x, target=None, round=True, grads=True):
     gW = [np.zeros_like(w) for w in Wc]
     gb = [np.zeros_like(v) for v in bc]
     do_g = grads and target is not None
+    gWa = [np.zeros_like(w) for w in Wc]
     gWp = (dp * nl)(*[_p(w) for w in gW]) if do_g else None
     gbp = (dp * nl)(*[_p(v) for v in gb]) if do_g else None
+    gWap = (dp * nl)(*[_p(w) for w in gWa]) if do_g else None
     L.orc_mlp.argtypes = [C.c_int32, ip, C.POINTER(dp), C.POINTER(dp), C.c_int32, dp, dp,
-                          C.c_int32, dp, C.POINTER(C.c_double), C.POINTER(dp), C.POINTER(dp)]
+                          C.c_int32, dp, C.POINTER(C.c_double), C.POINTER(dp), C.POINTER(dp),
+                          C.POINTER(dp)]
     L.orc_mlp(nl, _p(sz, ip), Wp, bp, B, _p(x), _p(tg) if tg is not None else None,
-              int(bool(round)), _p(y), C.byref(loss), gWp, gbp)
+              int(bool(round)), _p(y), C.byref(loss), gWp, gbp, gWap)
     return dict(y=y, loss=loss.value if target is not None else None,
-                gW=gW if do_g else None, gb=gb if do_g else None)
+                gW=gW if do_g else None, gb=gb if do_g else None, gWabs=gWa if do_g else None)
 
 
 def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
@@ -399,19 +404,12 @@ EVOLVE_LO = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
 EVOLVE_HI = np.array([3.0, 3.0, 3.0, 1.0, 1.0, 1.0])
 
 
-class Evolve:
-    """Evolution phase (Sec. "Hierarchical Self-evolving Framework", Eq.(9)).
+class _HLevel:
+    """Higher level of the evolution phase (H-SEPSO, Sec. "Hierarchical
+    Self-evolving Framework", Eq.(9)), run by liborc: particle i is a whole
+    (G_L, 6) lower-level hyper matrix, its fitness the LFV handed to step()."""
 
-    The higher level (H-SEPSO) lives in liborc; each H particle's fitness is
-    the lowest fitness value of a full lower-level run (one oracle frame with
-    truncation, priori initialisation and online evolution switched off) of
-    its own persistent lower-level swarm, instance i, with the particle's
-    values as the lower level's (G_L, 6) hyper matrix."""
-
-    def __init__(self, spec, lsw, h_groups=8, h_particles=4, evolutions=500, seed=0,
-                 h_hyper=None, lo=None, hi=None):
-        import dataclasses
-        Gl = lsw.groups
+    def __init__(self, Gl, h_groups, h_particles, evolutions, seed, h_hyper, lo, hi):
         self.Gh, self.Nh, self.Dh = h_groups, h_particles, 6 * Gl
         n = h_groups * h_particles
         hh = HYPER8[np.arange(h_groups) % 8] if h_hyper is None else h_hyper
@@ -428,30 +426,18 @@ class Evolve:
                            _p(self.Pf), _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0,
                            float("inf"), 0, 0)
         lib().orc_evolve_init(C.byref(self.h))
-        self.map = Map(spec)
-        self.lower = []
-        for i in range(n):
-            sw = dataclasses.replace(lsw, instance=i, use_pi=0, at_mode=0, hsef_every=0)
-            self.lower.append(Swarm(sw, spec.width, spec.height))
         self.evolution = 0
 
     k = property(lambda self: self.h.k)
     ctr = property(lambda self: self.h.ctr)
     tbest = property(lambda self: (self.h.tb_g, self.h.tb_n, self.h.tb_f))
 
-    def lfv(self, hyper_rows=None):
-        """Lowest fitness value of every H particle's lower-level run at the
-        current evolution (hyper_rows overrides the H positions)."""
-        src = self.X if hyper_rows is None else hyper_rows
-        out = np.empty(len(self.lower))
-        for i, sw in enumerate(self.lower):
-            sw.hyper[:] = src[i].reshape(sw.G, 6)
-            out[i] = sw.plan_frame(self.map, self.evolution)["cost"]
-        return out
-
     def step(self, lfv):
         v = np.ascontiguousarray(lfv, dtype=np.float64)
         lib().orc_evolve_step(C.byref(self.h), _p(v))
+
+    def lfv(self, hyper_rows=None):
+        raise NotImplementedError
 
     def evolve(self, n=1, hyper_cast=None):
         """n evolutions; hyper_cast maps the positions handed to the lower
@@ -465,6 +451,59 @@ class Evolve:
         return np.array(curve)
 
 
+class Evolve(_HLevel):
+    """Evolution phase for path planning: each H particle's fitness is the
+    lowest fitness value of a full lower-level run (one oracle frame with
+    truncation, priori initialisation and online evolution switched off) of
+    its own persistent lower-level swarm, instance i, with the particle's
+    values as the lower level's (G_L, 6) hyper matrix."""
+
+    def __init__(self, spec, lsw, h_groups=8, h_particles=4, evolutions=500, seed=0,
+                 h_hyper=None, lo=None, hi=None):
+        import dataclasses
+        super().__init__(lsw.groups, h_groups, h_particles, evolutions, seed, h_hyper, lo, hi)
+        self.map = Map(spec)
+        self.lower = []
+        for i in range(h_groups * h_particles):
+            sw = dataclasses.replace(lsw, instance=i, use_pi=0, at_mode=0, hsef_every=0)
+            self.lower.append(Swarm(sw, spec.width, spec.height))
+
+    def lfv(self, hyper_rows=None):
+        """Lowest fitness value of every H particle's lower-level run at the
+        current evolution (hyper_rows overrides the H positions)."""
+        src = self.X if hyper_rows is None else hyper_rows
+        out = np.empty(len(self.lower))
+        for i, sw in enumerate(self.lower):
+            sw.hyper[:] = src[i].reshape(sw.G, 6)
+            out[i] = sw.plan_frame(self.map, self.evolution)["cost"]
+        return out
+
+
+class BFEvolve(_HLevel):
+    """Evolution phase on a benchmark function (Sec. "Evolution Phase on
+    Benchmark Functions"): H particle i's fitness is the lowest fitness value
+    after `iters` evaluated iterations of a fresh DTPSO swarm (instance i,
+    run = evolutions done) with the particle's values as its (G, 6) hyper
+    matrix."""
+
+    def __init__(self, func, groups, particles, dims, iters, h_groups=8, h_particles=4,
+                 evolutions=500, lo=-600.0, hi=600.0, seed=0, h_seed=0, h_hyper=None, h_lo=None,
+                 h_hi=None):
+        super().__init__(groups, h_groups, h_particles, evolutions, h_seed, h_hyper, h_lo, h_hi)
+        self.bf = (func, groups, particles, dims, iters, lo, hi, seed)
+
+    def lower_run(self, i, hyper, run):
+        func, G, N, D, T, lo, hi, seed = self.bf
+        sw = BFSwarm(func, G, N, D, T, hyper, lo=lo, hi=hi, seed=seed, instance=i, run=run)
+        sw.step(T)
+        return sw
+
+    def lfv(self, hyper_rows=None):
+        src = self.X if hyper_rows is None else hyper_rows
+        return np.array([self.lower_run(i, src[i], self.evolution).tbest[2]
+                         for i in range(len(src))])
+
+
 def bf_value(func, x):
     """Benchmark function `func` (1..4, Table BFs) of one point x (D,)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -474,7 +513,8 @@ def bf_value(func, x):
 class BFSwarm:
     """DTPSO on a benchmark function (Table BFs) with numpy-owned state."""
 
-    def __init__(self, func, groups, particles, dims, iters, hyper, lo=-600.0, hi=600.0, seed=0):
+    def __init__(self, func, groups, particles, dims, iters, hyper, lo=-600.0, hi=600.0, seed=0,
+                 instance=0, run=0):
         G, N, D = groups, particles, dims
         self.G, self.N, self.D = G, N, D
         self.hyper = np.ascontiguousarray(hyper, dtype=np.float64).reshape(G, 6).copy()
@@ -485,7 +525,8 @@ class BFSwarm:
         self.gbest_f = z(G)
         self.s = OrcBF(int(func), G, N, D, int(iters), float(lo), float(hi), _p(self.hyper),
                        int(seed), _p(self.X), _p(self.V), _p(self.P), _p(self.f), _p(self.Pf),
-                       _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0, float("inf"), 0, 0)
+                       _p(self.gbest_n, ip), _p(self.gbest_f), 0, 0, float("inf"), 0, 0,
+                       int(instance), int(run))
         lib().orc_bf_init(C.byref(self.s))
 
     k = property(lambda self: self.s.k)

@@ -87,3 +87,62 @@ def test_swarm_descends(orc, func):
     f1 = s.tbest[2]
     s.step(299)
     assert s.tbest[2] < 0.2 * f1
+
+
+def test_instance_and_run_streams(orc):
+    # swarm instance s, run r: initial draws at counter (block, r, s, tag), the
+    # move at (particle, ctr, s, tag); instance 0, run 0 is the default stream
+    G, N, D, lo, hi = 2, 3, 7, -600.0, 600.0
+    base = _swarm(orc, G=G, N=N, D=D)
+    same = orc.BFSwarm(1, G, N, D, 4, I.HYPER8[:G], seed=3, instance=0, run=0)
+    assert np.array_equal(base.X, same.X) and np.array_equal(base.V, same.V)
+    s = orc.BFSwarm(1, G, N, D, 4, I.HYPER8[:G], seed=3, instance=5, run=2)
+    nb = (D + 3) // 4
+    for i in (0, G * N - 1):
+        for d in range(D):
+            w = orc.philox([i * nb + d // 4, 2, 5, 10], [3, 0])
+            assert s.X.reshape(-1, D)[i, d] == lo + orc.u01(int(w[d % 4])) * (hi - lo)
+    assert not np.array_equal(s.X, base.X)
+    r = orc.BFSwarm(1, G, N, D, 4, I.HYPER8[:G], seed=3, instance=0, run=1)
+    assert not np.array_equal(r.X, base.X)
+    # the move of instance 5 draws (r1, r2, r3) from (particle, ctr, 5, 9): with
+    # only C1 and w = 0 the first move is X + r1 (P - X) = X (P = X after the
+    # first evaluation), so compare the second move against the drawn r1
+    h = np.array([[1.0, 0, 0, 0, 0, 1]] * G)
+    t = orc.BFSwarm(1, G, N, D, 4, h, seed=3, instance=5)
+    t.step(1)
+    X1 = t.X.copy()
+    ctr = t.ctr
+    t.step(1)
+    X1, P2, X2 = X1.reshape(-1, D), t.P.reshape(-1, D), t.X.reshape(-1, D)
+    for i in range(G * N):
+        r1 = orc.u01(int(orc.philox([i, ctr, 5, 9], [3, 0])[0]))
+        exp = np.clip(X1[i] + np.clip(r1 * (P2[i] - X1[i]), -600, 600), lo, hi)
+        assert np.allclose(X2[i], exp, rtol=0, atol=1e-9)
+
+
+def test_bf_evolve_one_iteration_lfv(orc):
+    # with one evaluated iteration a lower-level run's LFV is the lowest
+    # function value over its initial swarm, whatever the hyper-parameters
+    ev = orc.BFEvolve(3, 2, 4, 6, 1, h_groups=2, h_particles=3, evolutions=5, seed=7, h_seed=1)
+    for e in range(2):
+        lfv = ev.lfv()
+        for i in range(6):
+            init = orc.BFSwarm(3, 2, 4, 6, 1, I.HYPER8[:2], seed=7, instance=i, run=e)
+            vals = [orc.bf_value(3, x) for x in init.X.reshape(-1, 6)]
+            assert lfv[i] == min(vals)
+        ev.step(lfv)
+        ev.evolution += 1
+    assert ev.k == 2
+
+
+def test_bf_evolve_curve(orc):
+    # the total best LFV never rises, and the H particles move inside the box
+    ev = orc.BFEvolve(1, 2, 5, 10, 30, h_groups=2, h_particles=3, evolutions=6, seed=2, h_seed=4)
+    curve = ev.evolve(6)
+    assert np.all(np.diff(curve) <= 0) and curve[-1] < np.inf
+    lo, hi = np.tile(ev.lo, 2), np.tile(ev.hi, 2)
+    assert np.all(ev.X >= lo) and np.all(ev.X <= hi)
+    # the reported best is the LFV of the total-best H Pbest's own run
+    tg, tn, tf = ev.tbest
+    assert tf == ev.Pf[tg * ev.Nh + tn] == curve[-1]
