@@ -368,22 +368,28 @@ sepso_status sepso_lin_attach_ctx(sepso_ctx* ctx, sepso_lin* lin);
  * with G groups of N particles and per-group hyper-parameters (Table hyper8
  * layout).  FP32 state; particle rows padded to a multiple of 4 floats in
  * the workspace.  Random streams: Philox4x32-10, key = seed, counter (c0, c1,
- * 0, tag): tags 10 / 11 draw the initial positions / velocities (c0 = 4-value
- * block of the flat (particle, dim) index, c1 = 0), tag 9 the move (c0 =
- * particle, c1 = ctr, words 0..2 = r1, r2, r3). */
+ * s, tag): tags 10 / 11 draw the initial positions / velocities (c0 = 4-value
+ * block of the swarm-local flat (particle, dim) index, c1 = 0), tag 9 the move
+ * (c0 = swarm-local particle, c1 = ctr, words 0..2 = r1, r2, r3); s is the
+ * swarm.  With swarms = S > 1 the handle holds S independent swarms of G
+ * groups side by side (group rows s*G .. s*G + G - 1), each with its own
+ * Tbest, stepped together: the batched lower levels of the evolution phase
+ * and the independent trials of the application phase. */
 typedef struct sepso_bf_cfg {
   int32_t func;                  /* 1..4 */
-  int32_t groups, particles, dims; /* G in [1, 64], N >= 1, D >= 1 */
+  int32_t groups, particles, dims; /* G in [1, 64] per swarm, N >= 1, D >= 1 */
   int32_t max_iters;             /* T >= 1: inertia schedule length (Eq.6) */
-  const float* hyper;            /* G x 6 (C1, C2, C3, w_init, w_end, V_limit >= 0) */
+  const float* hyper;            /* S*G x 6 (C1, C2, C3, w_init, w_end, V_limit >= 0) */
   float lo, hi;                  /* search box, lo < hi; V clipped to V_limit (hi - lo) / 2 */
   uint64_t seed;
+  int32_t swarms;                /* S independent swarms; 0 or 1 = one */
 } sepso_bf_cfg;
 
-/* Host views (any pointer may be NULL): X, V, P: G*N*D row-major; f, Pf:
- * G*N; gbest_n, gbest_f: G.  tb_* is derived from gbest_f (lowest group,
- * lowest index on ties).  pending = a move is owed before the next
- * evaluation (0 after every sepso_bf_step call). */
+/* Host views (any pointer may be NULL), with G_all = S*G groups: X, V, P:
+ * G_all*N*D row-major; f, Pf: G_all*N; gbest_n, gbest_f: G_all.  tb_* is
+ * derived from gbest_f over all groups (lowest group, lowest index on ties).
+ * pending = a move is owed before the next evaluation (0 after every
+ * sepso_bf_step call). */
 typedef struct sepso_bf_state {
   float *X, *V, *P;
   float *f, *Pf;
@@ -475,6 +481,35 @@ sepso_status sepso_evolve_get_state(sepso_evolve* ev, sepso_evolve_state* st);
 sepso_status sepso_evolve_best(sepso_evolve* ev, float* hyper, float* lfv);
 /* The lower-level batch (owned by ev): for sepso_batch_get_state and tuning. */
 sepso_status sepso_evolve_lower(sepso_evolve* ev, sepso_batch** b);
+
+/* ---- evolution phase on the benchmark functions ---------------------------
+ * Sec. "Evolution Phase on Benchmark Functions": the same higher level
+ * (sepso_evolve_cfg, H state and random streams as above, Dh = 6 G) over
+ * benchmark-function lower levels.  H particle i's lower level is swarm i of
+ * one sepso_bf handle with S = h_groups * h_particles swarms (lower->swarms
+ * and lower->hyper are ignored); every evolution starts each swarm afresh
+ * (initial draws with c1 = evolutions done), runs lower->max_iters evaluated
+ * iterations with the H particle's values as its (G, 6) hyper matrix, and
+ * takes the swarm's lowest fitness value as the particle's fitness (Eq.(9)). */
+typedef struct sepso_bf_evolve sepso_bf_evolve;
+sepso_status sepso_bf_evolve_workspace_bytes(const sepso_bf_cfg* lower, const sepso_evolve_cfg* cfg,
+                                             size_t* bytes);
+/* Validates, initialises both levels (synchronous); workspace caller-owned,
+ * 256-byte aligned; stream NULL = an internal non-blocking stream. */
+sepso_status sepso_bf_evolve_create(const sepso_bf_cfg* lower, const sepso_evolve_cfg* cfg,
+                                    void* d_workspace, size_t workspace_bytes, void* stream,
+                                    sepso_bf_evolve** out);
+sepso_status sepso_bf_evolve_destroy(sepso_bf_evolve* ev);
+/* n evolutions (one captured graph each: every swarm's run, their bests, the
+ * H step), one synchronisation at the end; curve (n <= evolutions floats, may
+ * be NULL) receives the total-best LFV after each. */
+sepso_status sepso_bf_evolve_run(sepso_bf_evolve* ev, int32_t n, float* curve);
+sepso_status sepso_bf_evolve_get_state(sepso_bf_evolve* ev, sepso_evolve_state* st);
+/* Best hyper matrix (Dh floats) and its LFV; SEPSO_E_STATE before the first
+ * evolution. */
+sepso_status sepso_bf_evolve_best(sepso_bf_evolve* ev, float* hyper, float* lfv);
+/* The lower-level handle (owned by ev): for sepso_bf_get_state. */
+sepso_status sepso_bf_evolve_lower(sepso_bf_evolve* ev, sepso_bf** bf);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,14 @@ time of the whole run, the final total best, and the move+evaluate kernel's
 HBM bandwidth (20 bytes per swarm element per iteration).
 
   python -m paper_2308_10169_amd.bf --case large
+
+With --evolve: the evolution phase of Sec. "Evolution Phase on Benchmark
+Functions" (H-SEPSO with Table hyper8 over the lower level's (8, 6) hyper
+matrix, each H particle's fitness the LFV of a fresh 80-particle, 30-dimension,
+1400-iteration run), then the application phase: the best matrix found
+against Table hyper8 over independent 1400-iteration trials.
+
+  python -m paper_2308_10169_amd.bf --evolve --evolutions 500
 """
 from __future__ import annotations
 
@@ -57,13 +65,59 @@ def run(case="large", funcs=("sphere", "rosenbrock", "rastrigin", "griewank"), i
     return out
 
 
+def evolve(funcs=("sphere", "rosenbrock", "rastrigin", "griewank"), evolutions=500, iters=1400,
+           h_groups=8, h_particles=4, trials=50, seed=0):
+    """Evolution then application phase per function; one JSON row each."""
+    from paper_2308_10169_amd import sepso
+    import torch
+    G, N, D = CASES["standard"]
+    out = []
+    for name in funcs:
+        ev = sepso.BFEvolver(name, G, N, D, iters, h_groups=h_groups, h_particles=h_particles,
+                             evolutions=evolutions, seed=seed, h_seed=seed + 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        curve = ev.run(evolutions)
+        secs = time.perf_counter() - t0
+        hyper, lfv = ev.best()
+        ev.close()
+        # application phase: independent trials (swarms with their own random
+        # streams, a seed apart from the evolution's) of the best matrix and of
+        # Table hyper8
+        finals = {}
+        for tag, h in (("evolved", hyper), ("hyper8", I.HYPER8)):
+            sw = sepso.BFSwarm(name, G, N, D, iters, np.tile(np.asarray(h, np.float32), (trials, 1)),
+                               seed=seed + 1000, swarms=trials)
+            sw.step(iters)
+            finals[tag] = sw.swarm_best().astype(np.float64)
+            sw.close()
+        pick = np.unique(np.round(np.geomspace(1, evolutions, 12)).astype(int)) - 1
+        ev_med, h8_med = float(np.median(finals["evolved"])), float(np.median(finals["hyper8"]))
+        out.append(dict(func=name, particles=G * N, dims=D, iters=iters,
+                        h_particles=h_groups * h_particles, evolutions=evolutions,
+                        evolution_s=secs, ms_per_evolution=1e3 * secs / evolutions,
+                        lfv_curve={int(k + 1): float(curve[k]) for k in pick},
+                        best_lfv=float(lfv), best_hyper=np.round(hyper, 4).tolist(),
+                        trials=trials, median_final_evolved=ev_med, median_final_hyper8=h8_med,
+                        median_gain=h8_med / max(ev_med, 1e-300),
+                        frac_trials_evolved_better=float(np.mean(
+                            np.sort(finals["evolved"]) < np.sort(finals["hyper8"])))))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--case", choices=sorted(CASES), default="large")
     ap.add_argument("--iters", type=int, default=1400)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--evolve", action="store_true", help="evolution + application phase")
+    ap.add_argument("--evolutions", type=int, default=500)
+    ap.add_argument("--funcs", default="sphere,rosenbrock,rastrigin,griewank")
     args = ap.parse_args()
-    for row in run(args.case, iters=args.iters, seed=args.seed):
+    funcs = tuple(args.funcs.split(","))
+    rows = (evolve(funcs, args.evolutions, args.iters, seed=args.seed) if args.evolve
+            else run(args.case, funcs, iters=args.iters, seed=args.seed))
+    for row in rows:
         print(json.dumps(row), flush=True)
 
 

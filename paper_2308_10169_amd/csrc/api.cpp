@@ -1482,21 +1482,15 @@ struct sepso_evolve {
   int graph_gen = -1;              // tile plan the graph was captured with
 };
 
-namespace {
+namespace sepso {
 
+namespace {
 const float kEvolveLo[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 const float kEvolveHi[6] = {3.f, 3.f, 3.f, 1.f, 1.f, 1.f};
+}  // namespace
 
-struct EvolveInputs {
-  std::vector<sepso_map> maps;
-  std::vector<sepso_swarm> swarms;
-  std::vector<float> placeholder;  // lower-level hyper until the H init writes it
-  size_t batch_bytes = 0, h_bytes = 0;
-};
-
-sepso_status evolve_inputs(const sepso_map* map, const sepso_swarm* lower,
-                           const sepso_evolve_cfg* cfg, EvolveInputs* in) {
-  if (!map || !lower || !cfg) return fail(SEPSO_E_ARG, "map/lower/cfg is NULL");
+sepso_status evolve_cfg_check(const sepso_evolve_cfg* cfg) {
+  if (!cfg) return fail(SEPSO_E_ARG, "evolve cfg is NULL");
   if (cfg->h_groups < 1 || cfg->h_groups > kMaxG)
     return fail(SEPSO_E_ARG, "evolve: h_groups in [1,%d]", kMaxG);
   if (cfg->h_particles < 1 || (int64_t)cfg->h_groups * cfg->h_particles > kEvolveMaxH)
@@ -1512,6 +1506,124 @@ sepso_status evolve_inputs(const sepso_map* map, const sepso_swarm* lower,
     for (int j = 0; j < 6 * cfg->h_groups; ++j)
       if (!finite(cfg->h_hyper[j]) || (j % 6 == 5 && cfg->h_hyper[j] < 0.f))
         return fail(SEPSO_E_ARG, "evolve: h_hyper");
+  return SEPSO_OK;
+}
+
+size_t evolve_h_bytes(const sepso_evolve_cfg* cfg, int Dh) {
+  const size_t n = (size_t)cfg->h_groups * cfg->h_particles;
+  return align256(sizeof(EvolveCtl)) + align256(4 * 3 * n * Dh) + align256(4 * 2 * n) +
+         align256(8 * (size_t)cfg->h_groups) + align256(4 * (6 * (size_t)cfg->h_groups + 12)) +
+         align256(4 * n) + align256(4 * (size_t)cfg->evolutions);
+}
+
+void evolve_h_carve(const sepso_evolve_cfg* cfg, int Dh, char* base, EvolveDev* d,
+                    std::vector<float>* consts) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += align256(bytes);
+    return p;
+  };
+  const int n = cfg->h_groups * cfg->h_particles;
+  d->Gh = cfg->h_groups;
+  d->Nh = cfg->h_particles;
+  d->Dh = Dh;
+  d->E = cfg->evolutions;
+  d->seed_lo = (uint32_t)(cfg->seed & 0xffffffffu);
+  d->seed_hi = (uint32_t)(cfg->seed >> 32);
+  const size_t nD = (size_t)n * Dh;
+  d->ctl = reinterpret_cast<EvolveCtl*>(take(sizeof(EvolveCtl)));
+  float* xvp = reinterpret_cast<float*>(take(4 * 3 * nD));
+  d->X = xvp;
+  d->V = xvp + nD;
+  d->P = xvp + 2 * nD;
+  float* pl2 = reinterpret_cast<float*>(take(4 * 2 * (size_t)n));
+  d->Pf = pl2;
+  d->lfv = pl2 + n;
+  char* gb = take(8 * (size_t)d->Gh);
+  d->gbest_n = reinterpret_cast<int32_t*>(gb);
+  d->gbest_f = reinterpret_cast<float*>(gb + 4 * d->Gh);
+  float* cst = reinterpret_cast<float*>(take(4 * (6 * (size_t)d->Gh + 12)));
+  d->h_hyper = cst;
+  d->lo = cst + 6 * d->Gh;
+  d->hi = cst + 6 * d->Gh + 6;
+  d->lfv_in = reinterpret_cast<float*>(take(4 * (size_t)n));
+  d->curve = reinterpret_cast<float*>(take(4 * (size_t)d->E));
+  consts->assign(6 * d->Gh + 12, 0.f);
+  for (int j = 0; j < 6 * d->Gh; ++j)
+    (*consts)[j] = cfg->h_hyper ? cfg->h_hyper[j] : kHyper8[(j / 6) % 8][j % 6];
+  for (int c = 0; c < 6; ++c) {
+    (*consts)[6 * d->Gh + c] = cfg->lo ? cfg->lo[c] : kEvolveLo[c];
+    (*consts)[6 * d->Gh + 6 + c] = cfg->hi ? cfg->hi[c] : kEvolveHi[c];
+  }
+}
+
+hipError_t evolve_h_state(const EvolveDev& d, hipStream_t st, sepso_evolve_state* s) {
+  const size_t n = (size_t)d.Gh * d.Nh, nD = n * d.Dh;
+  hipError_t e = hipSuccess;
+  auto d2h = [&](void* dst, const void* src, size_t bytes) {
+    if (dst && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+  };
+  EvolveCtl c{};
+  d2h(s->X, d.X, 4 * nD);
+  d2h(s->V, d.V, 4 * nD);
+  d2h(s->P, d.P, 4 * nD);
+  d2h(s->Pf, d.Pf, 4 * n);
+  d2h(s->lfv, d.lfv, 4 * n);
+  d2h(s->gbest_n, d.gbest_n, 4 * (size_t)d.Gh);
+  d2h(s->gbest_f, d.gbest_f, 4 * (size_t)d.Gh);
+  d2h(&c, d.ctl, sizeof(EvolveCtl));
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  s->tb_g = c.tb_g;
+  s->tb_n = c.tb_n;
+  s->tb_f = c.tb_f;
+  s->k = c.k;
+  s->ctr = c.ctr;
+  return hipSuccess;
+}
+
+hipError_t evolve_h_best(const EvolveDev& d, hipStream_t st, float* hyper, float* lfv, int* k) {
+  EvolveCtl c{};
+  hipError_t e = hipMemcpyAsync(&c, d.ctl, sizeof(EvolveCtl), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  *k = c.k;
+  if (c.k == 0) return hipSuccess;
+  if (hyper) {
+    const size_t row = (size_t)(c.tb_g * d.Nh + c.tb_n) * d.Dh;
+    e = hipMemcpyAsync(hyper, d.P + row, 4 * (size_t)d.Dh, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  if (lfv) *lfv = c.tb_f;
+  return e;
+}
+
+hipError_t evolve_h_curve(const EvolveDev& d, hipStream_t st, int k0, int n, float* curve) {
+  const int E = d.E, first = k0 % E;
+  const int n1 = std::min(n, E - first);
+  hipError_t e = hipMemcpyAsync(curve, d.curve + first, 4 * (size_t)n1, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && n > n1)
+    e = hipMemcpyAsync(curve + n1, d.curve, 4 * (size_t)(n - n1), hipMemcpyDeviceToHost, st);
+  return e;
+}
+
+}  // namespace sepso
+
+namespace {
+
+struct EvolveInputs {
+  std::vector<sepso_map> maps;
+  std::vector<sepso_swarm> swarms;
+  std::vector<float> placeholder;  // lower-level hyper until the H init writes it
+  size_t batch_bytes = 0, h_bytes = 0;
+};
+
+sepso_status evolve_inputs(const sepso_map* map, const sepso_swarm* lower,
+                           const sepso_evolve_cfg* cfg, EvolveInputs* in) {
+  if (!map || !lower || !cfg) return fail(SEPSO_E_ARG, "map/lower/cfg is NULL");
+  sepso_status st = evolve_cfg_check(cfg);
+  if (st != SEPSO_OK) return st;
   const int n = cfg->h_groups * cfg->h_particles;
   sepso_swarm t = *lower;
   if (t.groups < 1 || t.groups > kMaxG) return fail(SEPSO_E_ARG, "lower: groups in [1,%d]", kMaxG);
@@ -1524,13 +1636,10 @@ sepso_status evolve_inputs(const sepso_map* map, const sepso_swarm* lower,
   in->maps.assign(n, *map);
   in->swarms.assign(n, t);
   for (int i = 0; i < n; ++i) in->swarms[i].instance = (uint32_t)i;
-  sepso_status st = sepso_batch_workspace_bytes(in->maps.data(), in->swarms.data(), n, &in->batch_bytes);
+  st = sepso_batch_workspace_bytes(in->maps.data(), in->swarms.data(), n, &in->batch_bytes);
   if (st != SEPSO_OK) return st;
   in->batch_bytes = align256(in->batch_bytes);
-  const size_t Dh = 6 * (size_t)t.groups;
-  in->h_bytes = align256(sizeof(EvolveCtl)) + align256(4 * 3 * n * Dh) + align256(4 * 2 * (size_t)n) +
-                align256(8 * (size_t)cfg->h_groups) + align256(4 * (6 * (size_t)cfg->h_groups + 12)) +
-                align256(4 * (size_t)n) + align256(4 * (size_t)cfg->evolutions);
+  in->h_bytes = evolve_h_bytes(cfg, 6 * t.groups);
   return SEPSO_OK;
 }
 
@@ -1574,48 +1683,12 @@ sepso_status sepso_evolve_create(const sepso_map* map, const sepso_swarm* lower,
     return st;
   }
   ev->batch_bytes = in.batch_bytes;
-  char* base = static_cast<char*>(d_ws) + in.batch_bytes;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    char* p = base + off;
-    off += align256(bytes);
-    return p;
-  };
   EvolveDev& d = ev->dev;
-  d.Gh = cfg->h_groups;
-  d.Nh = cfg->h_particles;
-  d.Dh = 6 * lower->groups;
-  d.E = cfg->evolutions;
-  d.seed_lo = (uint32_t)(cfg->seed & 0xffffffffu);
-  d.seed_hi = (uint32_t)(cfg->seed >> 32);
-  const size_t nD = (size_t)n * d.Dh;
-  d.ctl = reinterpret_cast<EvolveCtl*>(take(sizeof(EvolveCtl)));
-  float* xvp = reinterpret_cast<float*>(take(4 * 3 * nD));
-  d.X = xvp;
-  d.V = xvp + nD;
-  d.P = xvp + 2 * nD;
-  float* pl2 = reinterpret_cast<float*>(take(4 * 2 * (size_t)n));
-  d.Pf = pl2;
-  d.lfv = pl2 + n;
-  char* gb = take(8 * (size_t)d.Gh);
-  d.gbest_n = reinterpret_cast<int32_t*>(gb);
-  d.gbest_f = reinterpret_cast<float*>(gb + 4 * d.Gh);
-  float* consts = reinterpret_cast<float*>(take(4 * (6 * (size_t)d.Gh + 12)));
-  d.h_hyper = consts;
-  d.lo = consts + 6 * d.Gh;
-  d.hi = consts + 6 * d.Gh + 6;
-  float* lin = reinterpret_cast<float*>(take(4 * (size_t)n));
-  d.lfv_in = lin;
-  d.curve = reinterpret_cast<float*>(take(4 * (size_t)d.E));
-  std::vector<float> hc(6 * d.Gh + 12);
-  for (int j = 0; j < 6 * d.Gh; ++j)
-    hc[j] = cfg->h_hyper ? cfg->h_hyper[j] : kHyper8[(j / 6) % 8][j % 6];
-  for (int c = 0; c < 6; ++c) {
-    hc[6 * d.Gh + c] = cfg->lo ? cfg->lo[c] : kEvolveLo[c];
-    hc[6 * d.Gh + 6 + c] = cfg->hi ? cfg->hi[c] : kEvolveHi[c];
-  }
+  std::vector<float> hc;
+  evolve_h_carve(cfg, 6 * lower->groups, static_cast<char*>(d_ws) + in.batch_bytes, &d, &hc);
   sepso_batch* b = ev->b;
-  hipError_t e = hipMemcpyAsync(consts, hc.data(), 4 * hc.size(), hipMemcpyHostToDevice, b->stream);
+  hipError_t e = hipMemcpyAsync(const_cast<float*>(d.h_hyper), hc.data(), 4 * hc.size(),
+                                hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) {
     launch_evolve_init(d, b->pl, b->stream);
     e = hipGetLastError();
@@ -1673,14 +1746,7 @@ sepso_status sepso_evolve_run(sepso_evolve* ev, int32_t n, float* curve) {
   }
   for (int k = 0; k < n; ++k) HIPCHK(b, hipGraphLaunch(ev->graph, b->stream));
   b->frames_done += n;
-  if (curve && n > 0) {
-    const int E = ev->dev.E, first = c0.k % E;
-    const int n1 = std::min(n, E - first);
-    HIPCHK(b, hipMemcpyAsync(curve, ev->dev.curve + first, 4 * (size_t)n1, hipMemcpyDeviceToHost, b->stream));
-    if (n > n1)
-      HIPCHK(b, hipMemcpyAsync(curve + n1, ev->dev.curve, 4 * (size_t)(n - n1), hipMemcpyDeviceToHost,
-                               b->stream));
-  }
+  if (curve && n > 0) HIPCHK(b, evolve_h_curve(ev->dev, b->stream, c0.k, n, curve));
   HIPCHK(b, hipStreamSynchronize(b->stream));
   return SEPSO_OK;
 }
@@ -1703,46 +1769,16 @@ sepso_status sepso_evolve_get_state(sepso_evolve* ev, sepso_evolve_state* s) {
   sepso_status st = evolve_usable(ev);
   if (st != SEPSO_OK) return st;
   if (!s) return fail(SEPSO_E_ARG, "state is NULL");
-  sepso_batch* b = ev->b;
-  const EvolveDev& d = ev->dev;
-  const size_t n = (size_t)d.Gh * d.Nh, nD = n * d.Dh;
-  auto d2h = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-    if (!dst) return hipSuccess;
-    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, b->stream);
-  };
-  EvolveCtl c{};
-  HIPCHK(b, d2h(s->X, d.X, 4 * nD));
-  HIPCHK(b, d2h(s->V, d.V, 4 * nD));
-  HIPCHK(b, d2h(s->P, d.P, 4 * nD));
-  HIPCHK(b, d2h(s->Pf, d.Pf, 4 * n));
-  HIPCHK(b, d2h(s->lfv, d.lfv, 4 * n));
-  HIPCHK(b, d2h(s->gbest_n, d.gbest_n, 4 * (size_t)d.Gh));
-  HIPCHK(b, d2h(s->gbest_f, d.gbest_f, 4 * (size_t)d.Gh));
-  HIPCHK(b, d2h(&c, d.ctl, sizeof(EvolveCtl)));
-  HIPCHK(b, hipStreamSynchronize(b->stream));
-  s->tb_g = c.tb_g;
-  s->tb_n = c.tb_n;
-  s->tb_f = c.tb_f;
-  s->k = c.k;
-  s->ctr = c.ctr;
+  HIPCHK(ev->b, evolve_h_state(ev->dev, ev->b->stream, s));
   return SEPSO_OK;
 }
 
 sepso_status sepso_evolve_best(sepso_evolve* ev, float* hyper, float* lfv) {
   sepso_status st = evolve_usable(ev);
   if (st != SEPSO_OK) return st;
-  sepso_batch* b = ev->b;
-  const EvolveDev& d = ev->dev;
-  EvolveCtl c{};
-  HIPCHK(b, hipMemcpyAsync(&c, d.ctl, sizeof(EvolveCtl), hipMemcpyDeviceToHost, b->stream));
-  HIPCHK(b, hipStreamSynchronize(b->stream));
-  if (c.k == 0) return fail(SEPSO_E_STATE, "no evolution has run yet");
-  if (hyper) {
-    const size_t row = (size_t)(c.tb_g * d.Nh + c.tb_n) * d.Dh;
-    HIPCHK(b, hipMemcpyAsync(hyper, d.P + row, 4 * (size_t)d.Dh, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(b, hipStreamSynchronize(b->stream));
-  }
-  if (lfv) *lfv = c.tb_f;
+  int k = 0;
+  HIPCHK(ev->b, evolve_h_best(ev->dev, ev->b->stream, hyper, lfv, &k));
+  if (k == 0) return fail(SEPSO_E_STATE, "no evolution has run yet");
   return SEPSO_OK;
 }
 

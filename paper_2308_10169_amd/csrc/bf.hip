@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -27,6 +28,7 @@
 #include "../../include/sepso.h"
 #include "common.h"
 #include "internal.h"
+#include "kernels.h"
 #include "rng.h"
 
 namespace sepso {
@@ -42,7 +44,9 @@ struct BFCtl {
 };
 
 struct BFDev {
-  int32_t func, G, N, D, Dp, T;
+  int32_t func, G, N, D, Dp, T;  // G: groups of all swarms
+  int32_t S, Gs;                 // independent swarms, groups per swarm (G = S * Gs)
+  const int32_t* run;            // counter word 1 of the initial draws (NULL: 0)
   float lo, hi;
   uint32_t seed_lo, seed_hi;
   float *X, *V, *P;  // (G*N) x Dp
@@ -61,9 +65,12 @@ __global__ __launch_bounds__(256) void bf_init_kernel(BFDev s) {
   const int i = (int)(e / s.Dp), d = (int)(e - (int64_t)i * s.Dp), g = i / s.N;
   float x = 0.f, v = 0.f;
   if (d < s.D) {
-    const uint32_t c0 = (uint32_t)i * (uint32_t)(s.Dp / 4) + (uint32_t)(d / 4);
-    const U4 rx = philox(c0, 0u, 0u, TAG_BF_INIT_X, s.seed_lo, s.seed_hi);
-    const U4 rv = philox(c0, 0u, 0u, TAG_BF_INIT_V, s.seed_lo, s.seed_hi);
+    // swarm sw's particle il: counter (il * Dp/4 + d/4, run, sw, tag)
+    const int sw = g / s.Gs, il = i - sw * s.Gs * s.N;
+    const uint32_t run = s.run ? (uint32_t)*s.run : 0u;
+    const uint32_t c0 = (uint32_t)il * (uint32_t)(s.Dp / 4) + (uint32_t)(d / 4);
+    const U4 rx = philox(c0, run, (uint32_t)sw, TAG_BF_INIT_X, s.seed_lo, s.seed_hi);
+    const U4 rv = philox(c0, run, (uint32_t)sw, TAG_BF_INIT_V, s.seed_lo, s.seed_hi);
     const float vmax = s.hyper[6 * g + 5] * (s.hi - s.lo) * 0.5f;
     x = s.lo + u01(rx.v[d & 3]) * (s.hi - s.lo);
     v = -vmax + u01(rv.v[d & 3]) * (2.f * vmax);
@@ -100,6 +107,7 @@ __global__ __launch_bounds__(256) void bf_iter_kernel(BFDev s) {
   if (i >= s.G * s.N) return;                          // whole wave leaves
   const BFCtl c = *s.ctl;
   const int g = i / s.N, D = s.D, Dp = s.Dp;
+  const int sw = g / s.Gs, g0 = sw * s.Gs;  // this particle's swarm and its first group
   float4* X = reinterpret_cast<float4*>(s.X + (int64_t)i * Dp);
   float4* V = reinterpret_cast<float4*>(s.V + (int64_t)i * Dp);
   const float4* Pp = reinterpret_cast<const float4*>(s.P + (int64_t)i * Dp);
@@ -113,12 +121,14 @@ __global__ __launch_bounds__(256) void bf_iter_kernel(BFDev s) {
     const int kk = c.k < s.T ? c.k : s.T;
     w = h[3] - (h[3] - h[4]) / (float)s.T * (float)kk;
     vmax = h[5] * (s.hi - s.lo) * 0.5f;
-    const U4 r = philox((uint32_t)i, c.ctr, 0u, TAG_BF_UPDATE, s.seed_lo, s.seed_hi);
+    const U4 r = philox((uint32_t)(i - g0 * s.N), c.ctr, (uint32_t)sw, TAG_BF_UPDATE, s.seed_lo,
+                        s.seed_hi);
     a1 = h[0] * u01(r.v[0]);
     a2 = h[1] * u01(r.v[1]);
     a3 = h[2] * u01(r.v[2]);
-    float bf = lane < s.G ? s.gbest_f[lane] : INFINITY;
-    int bn = lane < s.G ? lane : 0x7fffffff;
+    // Tbest of this particle's own swarm
+    float bf = lane < s.Gs ? s.gbest_f[g0 + lane] : INFINITY;
+    int bn = lane < s.Gs ? lane : 0x7fffffff;
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) {
       const float of = __shfl_xor(bf, m);
@@ -128,7 +138,7 @@ __global__ __launch_bounds__(256) void bf_iter_kernel(BFDev s) {
         bn = on;
       }
     }
-    const int tg = bn < s.G ? bn : 0;
+    const int tg = g0 + (bn < s.Gs ? bn : 0);
     Gb = reinterpret_cast<const float4*>(s.gbest_pos + (int64_t)g * Dp);
     Tb = reinterpret_cast<const float4*>(s.gbest_pos + (int64_t)tg * Dp);
   }
@@ -264,6 +274,24 @@ __global__ __launch_bounds__(256) void bf_reduce_kernel(BFDev s, int fit) {
   }
 }
 
+// Each swarm's total best fitness (the lowest of its groups' bests; non-finite
+// as +inf), one thread per swarm.
+__global__ __launch_bounds__(256) void bf_best_kernel(BFDev s, float* out) {
+  const int sw = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sw >= s.S) return;
+  float b = INFINITY;
+  for (int g = sw * s.Gs; g < (sw + 1) * s.Gs; ++g) {
+    const float f = s.gbest_f[g];
+    if (f < b) b = f;
+  }
+  out[sw] = b;
+}
+
+void launch_bf_init(const BFDev& s, hipStream_t st) {
+  const int64_t total = (int64_t)s.G * s.N * s.Dp;
+  hipLaunchKernelGGL(bf_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, s);
+}
+
 template <int FUNC>
 void launch_bf_iter(const BFDev& s, bool fit, hipStream_t st) {
   const int blocks = (s.G * s.N + 3) / 4;
@@ -295,6 +323,16 @@ struct sepso_bf {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
+// Evolution phase over benchmark-function lower levels: swarm i of the
+// lower-level handle is H particle i.
+struct sepso_bf_evolve {
+  sepso_bf* bf = nullptr;
+  EvolveDev dev{};
+  size_t bf_bytes = 0;
+  float* lower_best = nullptr;     // n: each lower-level swarm's best after its run
+  hipGraphExec_t graph = nullptr;  // one evolution: lower-level runs, their bests, the H step
+};
+
 namespace {
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -303,28 +341,35 @@ struct BFLayout {
   size_t ctl, xvp, fp, gb, gpos, hyper, total;
 };
 
-sepso_status bf_check(const sepso_bf_cfg* c) {
+int bf_swarms(const sepso_bf_cfg* c) { return c->swarms < 1 ? 1 : c->swarms; }
+
+// Shape checks; the hyper values are checked only when check_hyper is set
+// (the evolution phase writes them itself).
+sepso_status bf_check(const sepso_bf_cfg* c, bool check_hyper = true) {
   if (!c) return fail(SEPSO_E_ARG, "cfg is NULL");
   if (c->func < 1 || c->func > 4) return fail(SEPSO_E_ARG, "bf: func in 1..4");
   if (c->groups < 1 || c->groups > 64) return fail(SEPSO_E_ARG, "bf: groups in [1,64]");
   if (c->particles < 1 || c->dims < 1 || c->max_iters < 1)
     return fail(SEPSO_E_ARG, "bf: particles, dims, max_iters >= 1");
-  const double elems = (double)c->groups * c->particles * ((c->dims + 3) / 4 * 4);
-  if (elems > 4.0e9 || (double)c->groups * c->particles > 2.0e9)
+  const double S = bf_swarms(c);
+  const double elems = S * c->groups * c->particles * ((c->dims + 3) / 4 * 4);
+  if (elems > 4.0e9 || S * c->groups * c->particles > 2.0e9 || S * c->groups > 2.0e9 / 6)
     return fail(SEPSO_E_ARG, "bf: swarm too large");
   if ((double)c->groups * c->particles * ((c->dims + 3) / 4) > 4294967295.0)
     return fail(SEPSO_E_ARG, "bf: swarm too large for the 32-bit random counter");
   if (!(std::isfinite(c->lo) && std::isfinite(c->hi) && c->lo < c->hi))
     return fail(SEPSO_E_ARG, "bf: lo < hi finite");
+  if (!check_hyper) return SEPSO_OK;
   if (!c->hyper) return fail(SEPSO_E_ARG, "bf: hyper is NULL");
-  for (int j = 0; j < 6 * c->groups; ++j)
+  for (int64_t j = 0; j < 6 * (int64_t)S * c->groups; ++j)
     if (!std::isfinite(c->hyper[j]) || (j % 6 == 5 && c->hyper[j] < 0.f))
       return fail(SEPSO_E_ARG, "bf: hyper not finite or V_limit < 0");
   return SEPSO_OK;
 }
 
 BFLayout bf_layout(const sepso_bf_cfg* c) {
-  const size_t n = (size_t)c->groups * c->particles, Dp = (size_t)(c->dims + 3) / 4 * 4;
+  const size_t G = (size_t)bf_swarms(c) * c->groups;
+  const size_t n = G * c->particles, Dp = (size_t)(c->dims + 3) / 4 * 4;
   BFLayout L{};
   size_t o = 0;
   auto take = [&](size_t b) {
@@ -335,9 +380,9 @@ BFLayout bf_layout(const sepso_bf_cfg* c) {
   L.ctl = take(sizeof(BFCtl));
   L.xvp = take(4 * 3 * n * Dp);
   L.fp = take(4 * 2 * n);
-  L.gb = take(8 * (size_t)c->groups);
-  L.gpos = take(4 * (size_t)c->groups * Dp);
-  L.hyper = take(4 * 6 * (size_t)c->groups);
+  L.gb = take(8 * G);
+  L.gpos = take(4 * G * Dp);
+  L.hyper = take(4 * 6 * G);
   L.total = o;
   return L;
 }
@@ -366,6 +411,74 @@ sepso_status bf_run(sepso_bf* b, int32_t n) {
   return SEPSO_OK;
 }
 
+// Creates a handle on a checked cfg.  hyper_dev (device, S*G x 6) replaces
+// the upload of cfg->hyper when given; run (device) is the counter word 1 of
+// the initial draws (NULL: 0).  The swarm is initialised only when
+// hyper_dev is NULL (otherwise its writer initialises it later).
+sepso_status bf_create(const sepso_bf_cfg* cfg, void* d_ws, size_t ws_bytes, void* stream,
+                       float** hyper_dev, const int32_t* run, sepso_bf** out) {
+  const BFLayout L = bf_layout(cfg);
+  if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(SEPSO_E_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(SEPSO_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  sepso_bf* b = new (std::nothrow) sepso_bf();
+  if (!b) return fail(SEPSO_E_NOMEM, "host allocation failed");
+  char* w = static_cast<char*>(d_ws);
+  BFDev& d = b->dev;
+  d.func = cfg->func;
+  d.S = bf_swarms(cfg);
+  d.Gs = cfg->groups;
+  d.G = d.S * d.Gs;
+  d.N = cfg->particles;
+  d.D = cfg->dims;
+  d.Dp = (cfg->dims + 3) / 4 * 4;
+  d.T = cfg->max_iters;
+  d.run = run;
+  d.lo = cfg->lo;
+  d.hi = cfg->hi;
+  d.seed_lo = (uint32_t)(cfg->seed & 0xffffffffu);
+  d.seed_hi = (uint32_t)(cfg->seed >> 32);
+  const size_t n = (size_t)d.G * d.N;
+  d.ctl = reinterpret_cast<BFCtl*>(w + L.ctl);
+  d.X = reinterpret_cast<float*>(w + L.xvp);
+  d.V = d.X + n * d.Dp;
+  d.P = d.V + n * d.Dp;
+  d.f = reinterpret_cast<float*>(w + L.fp);
+  d.Pf = d.f + n;
+  d.gbest_n = reinterpret_cast<int32_t*>(w + L.gb);
+  d.gbest_f = reinterpret_cast<float*>(w + L.gb + 4 * (size_t)d.G);
+  d.gbest_pos = reinterpret_cast<float*>(w + L.gpos);
+  d.hyper = reinterpret_cast<const float*>(w + L.hyper);
+  if (hyper_dev) *hyper_dev = reinterpret_cast<float*>(w + L.hyper);
+  if (stream) {
+    b->stream = static_cast<hipStream_t>(stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete b;
+      return fail(SEPSO_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    b->own_stream = true;
+  }
+  hipError_t e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e == hipSuccess && !hyper_dev) {
+    e = hipMemcpyAsync(w + L.hyper, cfg->hyper, 24 * (size_t)d.G, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) {
+      launch_bf_init(d, b->stream);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    sepso_status st = fail(SEPSO_E_HIP, "bf create: %s", hipGetErrorString(e));
+    sepso_bf_destroy(b);
+    return st;
+  }
+  *out = b;
+  return SEPSO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -384,61 +497,7 @@ sepso_status sepso_bf_create(const sepso_bf_cfg* cfg, void* d_ws, size_t ws_byte
   *out = nullptr;
   sepso_status st = bf_check(cfg);
   if (st != SEPSO_OK) return st;
-  const BFLayout L = bf_layout(cfg);
-  if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(SEPSO_E_ARG, "workspace not 256-byte aligned");
-  if (ws_bytes < L.total) return fail(SEPSO_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
-  sepso_bf* b = new (std::nothrow) sepso_bf();
-  if (!b) return fail(SEPSO_E_NOMEM, "host allocation failed");
-  char* w = static_cast<char*>(d_ws);
-  const size_t n = (size_t)cfg->groups * cfg->particles;
-  BFDev& d = b->dev;
-  d.func = cfg->func;
-  d.G = cfg->groups;
-  d.N = cfg->particles;
-  d.D = cfg->dims;
-  d.Dp = (cfg->dims + 3) / 4 * 4;
-  d.T = cfg->max_iters;
-  d.lo = cfg->lo;
-  d.hi = cfg->hi;
-  d.seed_lo = (uint32_t)(cfg->seed & 0xffffffffu);
-  d.seed_hi = (uint32_t)(cfg->seed >> 32);
-  d.ctl = reinterpret_cast<BFCtl*>(w + L.ctl);
-  d.X = reinterpret_cast<float*>(w + L.xvp);
-  d.V = d.X + n * d.Dp;
-  d.P = d.V + n * d.Dp;
-  d.f = reinterpret_cast<float*>(w + L.fp);
-  d.Pf = d.f + n;
-  d.gbest_n = reinterpret_cast<int32_t*>(w + L.gb);
-  d.gbest_f = reinterpret_cast<float*>(w + L.gb + 4 * (size_t)d.G);
-  d.gbest_pos = reinterpret_cast<float*>(w + L.gpos);
-  d.hyper = reinterpret_cast<const float*>(w + L.hyper);
-  if (stream) {
-    b->stream = static_cast<hipStream_t>(stream);
-  } else {
-    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      delete b;
-      return fail(SEPSO_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
-    }
-    b->own_stream = true;
-  }
-  hipError_t e = hipMemcpyAsync(w + L.hyper, cfg->hyper, 24 * (size_t)d.G, hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
-  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
-  if (e == hipSuccess) {
-    const int64_t total = (int64_t)n * d.Dp;
-    hipLaunchKernelGGL(bf_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, b->stream, d);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) {
-    st = fail(SEPSO_E_HIP, "bf create: %s", hipGetErrorString(e));
-    sepso_bf_destroy(b);
-    return st;
-  }
-  *out = b;
-  return SEPSO_OK;
+  return bf_create(cfg, d_ws, ws_bytes, stream, nullptr, nullptr, out);
 }
 
 sepso_status sepso_bf_destroy(sepso_bf* b) {
@@ -536,6 +595,152 @@ sepso_status sepso_bf_set_state(sepso_bf* b, const sepso_bf_state* s) {
   const BFCtl c{s->k, s->ctr, s->pending, 0};
   BFCHK(b, hipMemcpyAsync(d.ctl, &c, sizeof(BFCtl), hipMemcpyHostToDevice, b->stream));
   BFCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
+// ---- evolution phase on the benchmark functions ---------------------------
+
+static sepso_status bfe_sizes(const sepso_bf_cfg* lower, const sepso_evolve_cfg* cfg, sepso_bf_cfg* lc,
+                              size_t* bf_bytes, size_t* h_bytes) {
+  if (!lower || !cfg) return fail(SEPSO_E_ARG, "lower/cfg is NULL");
+  sepso_status st = evolve_cfg_check(cfg);
+  if (st != SEPSO_OK) return st;
+  *lc = *lower;
+  lc->swarms = cfg->h_groups * cfg->h_particles;
+  lc->hyper = nullptr;
+  st = bf_check(lc, false);
+  if (st != SEPSO_OK) return st;
+  *bf_bytes = a256(bf_layout(lc).total);
+  *h_bytes = evolve_h_bytes(cfg, 6 * lower->groups) + a256(4 * (size_t)lc->swarms);
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_evolve_workspace_bytes(const sepso_bf_cfg* lower, const sepso_evolve_cfg* cfg,
+                                             size_t* bytes) {
+  if (!bytes) return fail(SEPSO_E_ARG, "bytes is NULL");
+  sepso_bf_cfg lc;
+  size_t a = 0, h = 0;
+  sepso_status st = bfe_sizes(lower, cfg, &lc, &a, &h);
+  if (st != SEPSO_OK) return st;
+  *bytes = a + h;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_evolve_create(const sepso_bf_cfg* lower, const sepso_evolve_cfg* cfg, void* d_ws,
+                                    size_t ws_bytes, void* stream, sepso_bf_evolve** out) {
+  if (!out) return fail(SEPSO_E_ARG, "out is NULL");
+  *out = nullptr;
+  sepso_bf_cfg lc;
+  size_t a = 0, h = 0;
+  sepso_status st = bfe_sizes(lower, cfg, &lc, &a, &h);
+  if (st != SEPSO_OK) return st;
+  if (!d_ws) return fail(SEPSO_E_ARG, "workspace is NULL");
+  if (ws_bytes < a + h) return fail(SEPSO_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, a + h);
+  sepso_bf_evolve* ev = new (std::nothrow) sepso_bf_evolve();
+  if (!ev) return fail(SEPSO_E_NOMEM, "host allocation failed");
+  EvolveDev& d = ev->dev;
+  std::vector<float> hc;
+  char* hbase = static_cast<char*>(d_ws) + a;
+  evolve_h_carve(cfg, 6 * lower->groups, hbase, &d, &hc);
+  ev->lower_best = reinterpret_cast<float*>(hbase + evolve_h_bytes(cfg, 6 * lower->groups));
+  ev->bf_bytes = a;
+  // the lower level's initial draws take the evolution counter (EvolveCtl's
+  // first word) as word 1
+  static_assert(offsetof(EvolveCtl, k) == 0, "EvolveCtl::k leads");
+  st = bf_create(&lc, d_ws, a, stream, &d.hyper_out, reinterpret_cast<const int32_t*>(d.ctl), &ev->bf);
+  if (st != SEPSO_OK) {
+    delete ev;
+    return st;
+  }
+  d.lfv_in = ev->lower_best;
+  sepso_bf* b = ev->bf;
+  hipError_t e = hipMemcpyAsync(const_cast<float*>(d.h_hyper), hc.data(), 4 * hc.size(),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) {
+    launch_evolve_init(d, Pools{}, b->stream);
+    launch_bf_init(b->dev, b->stream);  // the lower level's state is valid from here on
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    st = fail(SEPSO_E_HIP, "bf evolve create: %s", hipGetErrorString(e));
+    sepso_bf_destroy(b);
+    delete ev;
+    return st;
+  }
+  *out = ev;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_evolve_destroy(sepso_bf_evolve* ev) {
+  if (!ev) return fail(SEPSO_E_ARG, "evolve handle is NULL");
+  if (ev->graph) (void)hipGraphExecDestroy(ev->graph);  // teardown: best effort
+  sepso_bf_destroy(ev->bf);
+  delete ev;
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_evolve_run(sepso_bf_evolve* ev, int32_t n, float* curve) {
+  if (!ev) return fail(SEPSO_E_ARG, "evolve handle is NULL");
+  sepso_bf* b = ev->bf;
+  sepso_status st = bf_usable(b);
+  if (st != SEPSO_OK) return st;
+  if (n < 0) return fail(SEPSO_E_ARG, "n must be >= 0");
+  if (curve && n > ev->dev.E) return fail(SEPSO_E_ARG, "curve holds at most `evolutions` values");
+  const BFDev& d = b->dev;
+  if (!ev->graph) {
+    // fresh swarms (run = evolutions done), T evaluated iterations, every
+    // swarm's best, the H step that writes the next hyper-parameters
+    hipGraph_t g = nullptr;
+    BFCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    launch_bf_init(d, b->stream);
+    for (int k = 0; k < d.T; ++k) launch_bf_step(d, true, b->stream);
+    hipLaunchKernelGGL(bf_best_kernel, dim3((d.S + 255) / 256), dim3(256), 0, b->stream, d, ev->lower_best);
+    launch_evolve_step(ev->dev, Pools{}, 1, b->stream);
+    hipError_t eq = hipGetLastError();
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (eq != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return bf_hip(b, eq, "bf evolution capture");
+    }
+    if (e != hipSuccess) return bf_hip(b, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&ev->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return bf_hip(b, e, "hipGraphInstantiate");
+  }
+  EvolveCtl c0{};
+  if (curve) {
+    BFCHK(b, hipMemcpyAsync(&c0, ev->dev.ctl, sizeof(EvolveCtl), hipMemcpyDeviceToHost, b->stream));
+    BFCHK(b, hipStreamSynchronize(b->stream));
+  }
+  for (int k = 0; k < n; ++k) BFCHK(b, hipGraphLaunch(ev->graph, b->stream));
+  if (curve && n > 0) BFCHK(b, evolve_h_curve(ev->dev, b->stream, c0.k, n, curve));
+  BFCHK(b, hipStreamSynchronize(b->stream));
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_evolve_get_state(sepso_bf_evolve* ev, sepso_evolve_state* s) {
+  if (!ev) return fail(SEPSO_E_ARG, "evolve handle is NULL");
+  sepso_status st = bf_usable(ev->bf);
+  if (st != SEPSO_OK) return st;
+  if (!s) return fail(SEPSO_E_ARG, "state is NULL");
+  BFCHK(ev->bf, evolve_h_state(ev->dev, ev->bf->stream, s));
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_evolve_best(sepso_bf_evolve* ev, float* hyper, float* lfv) {
+  if (!ev) return fail(SEPSO_E_ARG, "evolve handle is NULL");
+  sepso_status st = bf_usable(ev->bf);
+  if (st != SEPSO_OK) return st;
+  int k = 0;
+  BFCHK(ev->bf, evolve_h_best(ev->dev, ev->bf->stream, hyper, lfv, &k));
+  if (k == 0) return fail(SEPSO_E_STATE, "no evolution has run yet");
+  return SEPSO_OK;
+}
+
+sepso_status sepso_bf_evolve_lower(sepso_bf_evolve* ev, sepso_bf** bf) {
+  if (!ev || !bf) return fail(SEPSO_E_ARG, "evolve/out is NULL");
+  *bf = ev->bf;
   return SEPSO_OK;
 }
 

@@ -160,6 +160,7 @@ struct EvolveDev {
   const float* lfv_in;         // injected fitness (n) or null: lower level's frame result
   float* curve;                // total best after evolution k, at (k-1) mod E
   EvolveCtl* ctl;
+  float* hyper_out;            // lower-level hyper rows (n x Dh), or null: the batch's hyper pool
 };
 
 // Kernel flags of the fused iteration.

@@ -117,6 +117,23 @@ struct sepso_lin {
 };
 
 namespace sepso {
+// Higher level of the evolution phase (H-SEPSO), shared by the path-planning
+// and the benchmark-function lower levels (api.cpp).
+sepso_status evolve_cfg_check(const sepso_evolve_cfg* cfg);
+// Device bytes of the H state for H particles of Dh values each.
+size_t evolve_h_bytes(const sepso_evolve_cfg* cfg, int Dh);
+// Carves the H state out of base (evolve_h_bytes bytes) into d's pointers and
+// sizes; consts receives the host image of d->h_hyper, lo and hi (6 Gh + 12
+// floats, contiguous from d->h_hyper) for the caller to upload.
+void evolve_h_carve(const sepso_evolve_cfg* cfg, int Dh, char* base, EvolveDev* d,
+                    std::vector<float>* consts);
+// Synchronous reads of the H state on stream st.
+hipError_t evolve_h_state(const EvolveDev& d, hipStream_t st, sepso_evolve_state* s);
+// Total-best row and LFV; *k = evolutions done (nothing else is read when 0).
+hipError_t evolve_h_best(const EvolveDev& d, hipStream_t st, float* hyper, float* lfv, int* k);
+// Enqueues the copy of the curve entries of evolutions k0 + 1 .. k0 + n.
+hipError_t evolve_h_curve(const EvolveDev& d, hipStream_t st, int k0, int n, float* curve);
+
 // Learned-initializer hooks used by the frame loop (lin.cpp).
 void lin_enqueue_proposals(sepso_lin* lin, sepso_batch* b);
 }  // namespace sepso

@@ -1076,8 +1076,14 @@ void launch_reduce(const Pools& pl, int flags, hipStream_t s) {
 // lower-level run).  Column c of a row is boxed to [lo[c], hi[c]].
 // ---------------------------------------------------------------------------
 
+// Where H particle i's position goes for the lower level: its own row of an
+// external hyper array, or its batch instance's slice of the hyper pool.
+__device__ __forceinline__ float* evolve_dst(const EvolveDev& ev, const Pools& pl, int i) {
+  return ev.hyper_out ? ev.hyper_out + (int64_t)i * ev.Dh : pl.hyper + 6 * pl.desc[i].go;
+}
+
 // Uniform positions in the box, velocities in +-V_limit * half the column's
-// extent; the lower level's hyper pool receives the positions.
+// extent; the lower level's hyper-parameters receive the positions.
 __global__ __launch_bounds__(256) void evolve_init_kernel(EvolveDev ev, Pools pl) {
   const int n = ev.Gh * ev.Nh, Dh = ev.Dh, nb = (Dh + 3) / 4;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1092,7 +1098,7 @@ __global__ __launch_bounds__(256) void evolve_init_kernel(EvolveDev ev, Pools pl
     ev.X[e] = x;
     ev.P[e] = x;
     ev.V[e] = -vmax + u01(rv.v[d & 3]) * (2.f * vmax);
-    pl.hyper[6 * pl.desc[i].go + d] = x;
+    evolve_dst(ev, pl, i)[d] = x;
   }
   if (e < n) {
     ev.Pf[e] = INFINITY;
@@ -1113,7 +1119,8 @@ __global__ __launch_bounds__(256) void evolve_init_kernel(EvolveDev ev, Pools pl
 // One evolution after the lower-level frame: H bests (Pbest = running
 // minimum, Gbest = lowest Pbest of the group, lowest index on ties; Tbest =
 // lowest Gbest), then the move of Eq.(6)-(8) with one (r1, r2, r3) per H
-// particle; new positions go to the lower level's hyper pool.  One block.
+// particle; new positions go to the lower level's hyper-parameters.  One
+// block.  Without injection the fitness is the batch instance's frame result.
 __global__ __launch_bounds__(1024) void evolve_step_kernel(EvolveDev ev, Pools pl, int injected) {
   __shared__ float s_r[3 * kEvolveMaxH];
   __shared__ int s_imp[kEvolveMaxH];
@@ -1171,7 +1178,7 @@ __global__ __launch_bounds__(1024) void evolve_step_kernel(EvolveDev ev, Pools p
     const float xn = clampf(x + v, lo, hi);
     ev.V[e] = v;
     ev.X[e] = xn;
-    pl.hyper[6 * pl.desc[i].go + d] = xn;
+    evolve_dst(ev, pl, i)[d] = xn;
   }
   if (t == 0) {
     ev.curve[(k - 1) % ev.E] = s_gf[tg];

@@ -70,7 +70,7 @@ class CTune(C.Structure):
 class CBFCfg(C.Structure):
     _fields_ = [("func", C.c_int32), ("groups", C.c_int32), ("particles", C.c_int32),
                 ("dims", C.c_int32), ("max_iters", C.c_int32), ("hyper", fp), ("lo", C.c_float),
-                ("hi", C.c_float), ("seed", C.c_uint64)]
+                ("hi", C.c_float), ("seed", C.c_uint64), ("swarms", C.c_int32)]
 
 
 class CBFState(C.Structure):
@@ -158,6 +158,15 @@ def _load():
     L.sepso_evolve_get_state.argtypes = [vp, C.POINTER(CEvolveState)]
     L.sepso_evolve_best.argtypes = [vp, fp, fp]
     L.sepso_evolve_lower.argtypes = [vp, C.POINTER(vp)]
+    L.sepso_bf_evolve_workspace_bytes.argtypes = [C.POINTER(CBFCfg), C.POINTER(CEvolveCfg),
+                                                  C.POINTER(sz)]
+    L.sepso_bf_evolve_create.argtypes = [C.POINTER(CBFCfg), C.POINTER(CEvolveCfg), vp, sz, vp,
+                                         C.POINTER(vp)]
+    L.sepso_bf_evolve_destroy.argtypes = [vp]
+    L.sepso_bf_evolve_run.argtypes = [vp, C.c_int32, fp]
+    L.sepso_bf_evolve_get_state.argtypes = [vp, C.POINTER(CEvolveState)]
+    L.sepso_bf_evolve_best.argtypes = [vp, fp, fp]
+    L.sepso_bf_evolve_lower.argtypes = [vp, C.POINTER(vp)]
     L.sepso_lin_param_count.restype = C.c_int64
     L.sepso_lin_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.POINTER(sz)]
     L.sepso_lin_create.argtypes = [C.c_int32, C.c_int64, C.c_uint64, vp, sz, vp, C.POINTER(vp)]
@@ -613,17 +622,20 @@ BF_FUNCS = {"sphere": 1, "rosenbrock": 2, "rastrigin": 3, "griewank": 4}
 
 
 class BFSwarm:
-    """DTPSO on a benchmark function of Table BFs (sepso_bf)."""
+    """DTPSO on a benchmark function of Table BFs (sepso_bf); with swarms > 1,
+    that many independent swarms of `groups` groups stepped together."""
 
     def __init__(self, func, groups, particles, dims, iters, hyper, lo=-600.0, hi=600.0, seed=0,
-                 stream=None):
+                 stream=None, swarms=1):
         L = _load()
         torch = _torch
-        self.G, self.N, self.D = groups, particles, dims
+        self.S, self.Gs = swarms, groups
+        self.G, self.N, self.D = swarms * groups, particles, dims
         self._hyper = _f32(hyper).reshape(-1)
         f = BF_FUNCS.get(func, func)
         self._cfg = CBFCfg(int(f), groups, particles, dims, iters,
-                           self._hyper.ctypes.data_as(fp), float(lo), float(hi), int(seed))
+                           self._hyper.ctypes.data_as(fp), float(lo), float(hi), int(seed),
+                           int(swarms))
         nbytes = C.c_size_t()
         _check(L.sepso_bf_workspace_bytes(C.byref(self._cfg), C.byref(nbytes)))
         self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
@@ -632,17 +644,32 @@ class BFSwarm:
         _check(L.sepso_bf_create(C.byref(self._cfg), C.c_void_p(self.ws.data_ptr()), nbytes.value,
                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
+        self._owned = True
+
+    @classmethod
+    def borrowed(cls, h, swarms, groups, particles, dims):
+        """View of a handle owned elsewhere (an evolution's lower level)."""
+        self = cls.__new__(cls)
+        self.S, self.Gs = swarms, groups
+        self.G, self.N, self.D = swarms * groups, particles, dims
+        self.h, self._owned = h, False
+        return self
 
     def close(self):
-        if self.h:
+        if self.h and self._owned:
             _check(_lib.sepso_bf_destroy(self.h))
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+    def swarm_best(self, st=None):
+        """Each swarm's lowest fitness value (from a state dict or read now)."""
+        st = self.get_state(rows=False) if st is None else st
+        return st["gbest_f"].reshape(self.S, self.Gs).min(axis=1)
 
     def step(self, n=1):
         _check(_lib.sepso_bf_step(self.h, int(n)))
@@ -675,6 +702,79 @@ class BFSwarm:
                 setattr(cs, k, keep[k].ctypes.data_as(ip if dt == np.int32 else fp))
         cs.k, cs.ctr, cs.pending = int(st.get("k", 0)), int(st.get("ctr", 0)), int(st.get("pending", 0))
         _check(_lib.sepso_bf_set_state(self.h, C.byref(cs)))
+
+
+class BFEvolver:
+    """Evolution phase on a benchmark function (sepso_bf_evolve): H-SEPSO
+    over (groups, 6) hyper matrices, each H particle's fitness the LFV of a
+    fresh `iters`-iteration run of its own lower-level swarm."""
+
+    def __init__(self, func, groups, particles, dims, iters, h_groups=8, h_particles=4,
+                 evolutions=500, lo=-600.0, hi=600.0, seed=0, h_seed=0, h_hyper=None, h_lo=None,
+                 h_hi=None, stream=None):
+        L = _load()
+        torch = _torch
+        self.n, self.Dh, self.Gh, self.E = h_groups * h_particles, 6 * groups, h_groups, evolutions
+        self.shape = (groups, particles, dims)
+        f = BF_FUNCS.get(func, func)
+        self._lcfg = CBFCfg(int(f), groups, particles, dims, iters, None, float(lo), float(hi),
+                            int(seed), 0)
+        self._keep = [None if a is None else _f32(a).reshape(-1) for a in (h_hyper, h_lo, h_hi)]
+        ptr = lambda a: a.ctypes.data_as(fp) if a is not None else None
+        self._cfg = CEvolveCfg(h_groups, h_particles, evolutions, *[ptr(a) for a in self._keep],
+                               int(h_seed))
+        nbytes = C.c_size_t()
+        _check(L.sepso_bf_evolve_workspace_bytes(C.byref(self._lcfg), C.byref(self._cfg),
+                                                 C.byref(nbytes)))
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = C.c_void_p()
+        _check(L.sepso_bf_evolve_create(C.byref(self._lcfg), C.byref(self._cfg),
+                                        C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        b = C.c_void_p()
+        _check(L.sepso_bf_evolve_lower(h, C.byref(b)))
+        self.lower = BFSwarm.borrowed(b, self.n, groups, particles, dims)
+
+    def close(self):
+        if self.h:
+            self.lower.h = None
+            _check(_lib.sepso_bf_evolve_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, n=1):
+        """n evolutions; returns the total-best LFV after each."""
+        out = np.zeros(max(int(n), 1), np.float32)
+        done = 0
+        while done < n:
+            m = min(n - done, self.E)
+            _check(_lib.sepso_bf_evolve_run(self.h, int(m), out[done:].ctypes.data_as(fp)))
+            done += m
+        return out[:n]
+
+    def get_state(self):
+        z = lambda *sh: np.zeros(sh, np.float32)
+        b = dict(X=z(self.n, self.Dh), V=z(self.n, self.Dh), P=z(self.n, self.Dh), Pf=z(self.n),
+                 lfv=z(self.n), gbest_n=np.zeros(self.Gh, np.int32), gbest_f=z(self.Gh))
+        cs = CEvolveState()
+        for k, v in b.items():
+            setattr(cs, k, v.ctypes.data_as(ip if v.dtype == np.int32 else fp))
+        _check(_lib.sepso_bf_evolve_get_state(self.h, C.byref(cs)))
+        b.update(tbest=(cs.tb_g, cs.tb_n, cs.tb_f), k=cs.k, ctr=cs.ctr)
+        return b
+
+    def best(self):
+        hyper = np.zeros(self.Dh, np.float32)
+        f = C.c_float()
+        _check(_lib.sepso_bf_evolve_best(self.h, hyper.ctypes.data_as(fp), C.byref(f)))
+        return hyper.reshape(-1, 6), f.value
 
 
 LIN_IN, LIN_OUT, LIN_HIDDEN = 4100, 320, 512

@@ -93,3 +93,50 @@ def test_descent_matches_oracle(sp, func):
         assert o.tbest[2] < f0.tbest[2]
     print(func, np.median(lg), np.median(lo))
     assert abs(np.median(lg) - np.median(lo)) <= 0.5
+
+
+def test_multi_swarm_init_matches_oracle(sp):
+    # S independent swarms side by side: swarm s draws as the oracle's
+    # instance s
+    S, G, N, D = 3, 2, 5, 30
+    hy = np.tile(_hyper(G), (S, 1))
+    g = sp.BFSwarm(4, G, N, D, 50, hy, seed=8, swarms=S)
+    st = g.get_state()
+    for s in range(S):
+        o = orc.BFSwarm(4, G, N, D, 50, _hyper(G), seed=8, instance=s)
+        sl = slice(s * G, (s + 1) * G)
+        assert np.max(np.abs(st["X"][sl] - o.X)) <= 1200 * 2 ** -23
+        assert np.max(np.abs(st["V"][sl] - o.V)) <= 1200 * 2 ** -23
+    g.close()
+
+
+@pytest.mark.parametrize("func", [2, 3])
+def test_multi_swarm_injected_step(sp, func):
+    # one iteration of every swarm from the GPU's state: fitness, bests, and
+    # each swarm's move toward its own Tbest
+    S, G, N, D = 4, 3, 6, 40
+    hy = np.concatenate([_hyper(8)[(np.arange(G) + s) % 8] for s in range(S)])
+    g = sp.BFSwarm(func, G, N, D, 50, hy, seed=2, swarms=S)
+    g.step(3)
+    st0 = g.get_state()
+    g.step(1)
+    st1 = g.get_state()
+    for s in range(S):
+        sl = slice(s * G, (s + 1) * G)
+        o = orc.BFSwarm(func, G, N, D, 50, hy[sl], seed=2, instance=s)
+        for k in ("X", "V", "P", "Pf", "gbest_f"):
+            getattr(o, k)[...] = st0[k][sl].astype(np.float64)
+        o.gbest_n[...] = st0["gbest_n"][sl]
+        o.set_scalars(k=st0["k"] + 1, ctr=st0["ctr"])
+        o.eval()
+        fg = st1["f"][sl].astype(np.float64)
+        scale = np.maximum(np.abs(o.f), 1.0) + 1e-6 * D
+        assert np.all(np.abs(fg - o.f) <= 1e-5 * scale)
+        o.f[...] = fg
+        o.advance()
+        assert np.array_equal(st1["Pf"][sl], o.Pf.astype(np.float32))
+        assert np.array_equal(st1["gbest_n"][sl], o.gbest_n)
+        for k in ("X", "V", "P"):
+            assert np.max(np.abs(st1[k][sl] - getattr(o, k))) <= 2e-4, (s, k)
+    assert np.array_equal(g.swarm_best(st1), st1["gbest_f"].reshape(S, G).min(1))
+    g.close()
