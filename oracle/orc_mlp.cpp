@@ -33,9 +33,17 @@ double orc_bf16(double x) {
 //   y     : B x sizes[L] outputs
 //   loss  : mean over B * sizes[L] of (y - target)^2
 //   gW,gb : gradients of loss (may be NULL to skip the backward pass)
+//   gWmag : (may be NULL) per weight-gradient element a magnitude that bounds
+//           how far BF16 storage of intermediate values can move it: the same
+//           chain of products run on absolute values, |x| forward through
+//           |W| and |b| (Mag(a)), 2 (Mag(y) + |t|) / (B n) backward through
+//           |W| with every unit kept (Mag(dz), so ReLU decisions that flip
+//           are covered), and gWmag[l] = sum over the batch of
+//           Mag(dz) Mag(a).  Each rounding moves a value by at most 2^-8 of
+//           its Mag, and the roundings add up along the chain.
 void orc_mlp(int32_t L, const int32_t* sizes, const double* const* W, const double* const* b,
              int32_t B, const double* x, const double* target, int32_t round, double* y,
-             double* loss, double* const* gW, double* const* gb) {
+             double* loss, double* const* gW, double* const* gb, double* const* gWmag) {
   auto R = [&](double v) { return round ? orc_bf16(v) : v; };
   std::vector<std::vector<double>> a(L + 1), z(L + 1);
   a[0].resize((size_t)B * sizes[0]);
@@ -61,6 +69,22 @@ void orc_mlp(int32_t L, const int32_t* sizes, const double* const* W, const doub
           a[l + 1][(size_t)r * no + o] = s;
       }
   }
+  // magnitude forward pass (only for gWmag)
+  std::vector<std::vector<double>> m(gWmag ? L + 1 : 0);
+  if (gWmag) {
+    m[0].resize(a[0].size());
+    for (size_t i = 0; i < a[0].size(); ++i) m[0][i] = std::fabs(a[0][i]);
+    for (int l = 0; l < L; ++l) {
+      const int ni = sizes[l], no = sizes[l + 1];
+      m[l + 1].assign((size_t)B * no, 0.0);
+      for (int r = 0; r < B; ++r)
+        for (int o = 0; o < no; ++o) {
+          double s = std::fabs(b[l][o]);
+          for (int i = 0; i < ni; ++i) s += std::fabs(Wr[l][(size_t)o * ni + i]) * m[l][(size_t)r * ni + i];
+          m[l + 1][(size_t)r * no + o] = s;
+        }
+    }
+  }
   const int no = sizes[L];
   double acc = 0.0;
   for (size_t i = 0; i < (size_t)B * no; ++i) {
@@ -70,8 +94,12 @@ void orc_mlp(int32_t L, const int32_t* sizes, const double* const* W, const doub
   if (loss) *loss = acc / ((double)B * no);
   if (!gW || !target) return;
   // d loss / d z_L
-  std::vector<double> dz((size_t)B * no);
+  std::vector<double> dz((size_t)B * no), mdz;
   for (size_t i = 0; i < dz.size(); ++i) dz[i] = 2.0 * (a[L][i] - target[i]) / ((double)B * no);
+  if (gWmag) {
+    mdz.resize(dz.size());
+    for (size_t i = 0; i < dz.size(); ++i) mdz[i] = 2.0 * (m[L][i] + std::fabs(target[i])) / ((double)B * no);
+  }
   for (int l = L - 1; l >= 0; --l) {
     const int ni = sizes[l], nO = sizes[l + 1];
     std::vector<double> dzr(dz.size());
@@ -84,9 +112,24 @@ void orc_mlp(int32_t L, const int32_t* sizes, const double* const* W, const doub
         double s = 0.0;
         for (int r = 0; r < B; ++r) s += dzr[(size_t)r * nO + o] * a[l][(size_t)r * ni + i];
         gW[l][(size_t)o * ni + i] = s;
+        if (gWmag) {
+          double sm = 0.0;
+          for (int r = 0; r < B; ++r) sm += mdz[(size_t)r * nO + o] * m[l][(size_t)r * ni + i];
+          gWmag[l][(size_t)o * ni + i] = sm;
+        }
       }
     }
     if (l == 0) break;
+    if (gWmag) {
+      std::vector<double> mprev((size_t)B * ni, 0.0);
+      for (int r = 0; r < B; ++r)
+        for (int i = 0; i < ni; ++i) {
+          double s = 0.0;
+          for (int o = 0; o < nO; ++o) s += mdz[(size_t)r * nO + o] * std::fabs(Wr[l][(size_t)o * ni + i]);
+          mprev[(size_t)r * ni + i] = s;
+        }
+      mdz.swap(mprev);
+    }
     std::vector<double> dprev((size_t)B * ni, 0.0);
     for (int r = 0; r < B; ++r)
       for (int i = 0; i < ni; ++i) {

@@ -327,8 +327,10 @@ def bf16(x):
 
 def mlp(sizes, W, b, x, target=None, round=True, grads=True):
     """FP64 MLP forward (+ backward when target given and grads).  W[l]:
-    (sizes[l+1], sizes[l]); returns dict(y, loss, gW, gb, gWabs) -- gWabs[l]
-    the sum over the batch of |dz| |a| behind each weight-gradient element."""
+    (sizes[l+1], sizes[l]); returns dict(y, loss, gW, gb, gWmag) -- gWmag[l]
+    per weight-gradient element the same products run on magnitudes (|x|,
+    |W|, |b| forward, 2 (Mag(y) + |t|) / (B n) backward through |W| with every
+    unit kept), which bounds how far BF16 storage can move the element."""
     L = lib()
     nl = len(sizes) - 1
     sz = np.ascontiguousarray(sizes, dtype=np.int32)
@@ -356,7 +358,7 @@ def mlp(sizes, W, b, x, target=None, round=True, grads=True):
     L.orc_mlp(nl, _p(sz, ip), Wp, bp, B, _p(x), _p(tg) if tg is not None else None,
               int(bool(round)), _p(y), C.byref(loss), gWp, gbp, gWap)
     return dict(y=y, loss=loss.value if target is not None else None,
-                gW=gW if do_g else None, gb=gb if do_g else None, gWabs=gWa if do_g else None)
+                gW=gW if do_g else None, gb=gb if do_g else None, gWmag=gWa if do_g else None)
 
 
 def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -136,3 +136,36 @@ def test_adam_sign_flip(orc):
     p1, p2 = _adam_run(orc, p0, [g, -g], lr=lr, b1=b1, b2=b2)
     step2 = lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + 1e-8)
     assert np.allclose(p2 - p1, step2, rtol=0, atol=1e-14)
+
+
+def test_gradient_magnitudes(orc):
+    # gWmag[l] runs the gradient's chain of products on magnitudes.  With
+    # non-negative inputs, weights and biases every unit is active and every
+    # term has one sign; with targets below the outputs the output gradient
+    # is positive too, so the magnitude chain is the gradient itself, layer by
+    # layer.  With mixed signs it dominates |gW| and exceeds it somewhere.
+    rng = np.random.default_rng(4)
+    sizes = [3, 4, 5, 2]
+    W = [rng.uniform(0.1, 1.0, (sizes[l + 1], sizes[l])) for l in range(3)]
+    b = [rng.uniform(0.1, 1.0, sizes[l + 1]) for l in range(3)]
+    x = rng.uniform(0.0, 1.0, (6, 3))
+    r = orc.mlp(sizes, W, b, x, target=np.full((6, 2), -10.0), round=False)
+    for l in range(3):
+        assert np.allclose(r["gWmag"][l], r["gW"][l], rtol=1e-12, atol=0)
+    Wm = [rng.normal(0, 1, w.shape) for w in W]
+    bm = [rng.normal(0, 1, v.shape) for v in b]
+    xm = rng.normal(0, 1, x.shape)
+    y = orc.mlp(sizes, Wm, bm, xm, round=False)["y"]
+    for rnd in (False, True):
+        r2 = orc.mlp(sizes, Wm, bm, xm, target=y + rng.choice([-1.0, 1.0], y.shape), round=rnd)
+        for l in range(3):
+            assert np.all(r2["gWmag"][l] >= np.abs(r2["gW"][l]) * (1 - 1e-2))
+            assert np.any(r2["gWmag"][l] > np.abs(r2["gW"][l]) * (1 + 1e-6))
+    # by hand: x = 1, W0 = (1, 1)^T, W1 = (1, -1), zero biases, t = -1, so
+    # y = 0 (a cancellation), dY = 2, Mag(y) = 2, Mag(dY) = 2 (2 + 1) = 6;
+    # gW1 = dY a1 = (2, 2) against 6 (1, 1); gW0 = dY W1^T x = (2, -2)
+    # against Mag(dY) |W1|^T |x| = (6, 6)
+    r3 = orc.mlp([1, 2, 1], [np.ones((2, 1)), np.array([[1.0, -1.0]])], [np.zeros(2), np.zeros(1)],
+                 np.ones((1, 1)), target=-np.ones((1, 1)), round=False)
+    assert np.array_equal(r3["gW"][1], [[2.0, 2.0]]) and np.array_equal(r3["gWmag"][1], [[6.0, 6.0]])
+    assert np.array_equal(r3["gW"][0], [[2.0], [-2.0]]) and np.array_equal(r3["gWmag"][0], [[6.0], [6.0]])
