@@ -383,6 +383,10 @@ typedef struct sepso_bf_cfg {
   float lo, hi;                  /* search box, lo < hi; V clipped to V_limit (hi - lo) / 2 */
   uint64_t seed;
   int32_t swarms;                /* S independent swarms; 0 or 1 = one */
+  int32_t path;                  /* 0: a swarm whose rows (D <= 256) and state fit in 64 KiB of
+                                    LDS runs each call's iterations in one launch, one
+                                    workgroup per swarm; 1: always two launches per
+                                    iteration.  Both give bit-identical results. */
 } sepso_bf_cfg;
 
 /* Host views (any pointer may be NULL), with G_all = S*G groups: X, V, P:

@@ -120,12 +120,28 @@ def main():
     ap.add_argument("--evolve", action="store_true", help="evolution + application phase")
     ap.add_argument("--evolutions", type=int, default=500)
     ap.add_argument("--funcs", default="sphere,rosenbrock,rastrigin,griewank")
+    ap.add_argument("--seeds", type=int, default=1, help="--evolve: independent evolutions per function")
     args = ap.parse_args()
     funcs = tuple(args.funcs.split(","))
-    rows = (evolve(funcs, args.evolutions, args.iters, seed=args.seed) if args.evolve
-            else run(args.case, funcs, iters=args.iters, seed=args.seed))
-    for row in rows:
-        print(json.dumps(row), flush=True)
+    if not args.evolve:
+        for row in run(args.case, funcs, iters=args.iters, seed=args.seed):
+            print(json.dumps(row), flush=True)
+        return
+    per = {f: [] for f in funcs}
+    for sd in range(args.seed, args.seed + args.seeds):
+        for row in evolve(funcs, args.evolutions, args.iters, seed=sd):
+            row["seed"] = sd
+            per[row["func"]].append(row)
+            print(json.dumps(row), flush=True)
+    if args.seeds > 1:
+        for f, rows in per.items():
+            p = [r["p_evolved_lower"] for r in rows]
+            print(json.dumps(dict(func=f, seeds=len(rows), p_evolved_lower_per_seed=p,
+                                  median_p_evolved_lower=float(np.median(p)),
+                                  seeds_evolved_better=int(sum(v > 0.5 for v in p)),
+                                  median_final_evolved_per_seed=[r["median_final_evolved"] for r in rows],
+                                  median_final_hyper8_per_seed=[r["median_final_hyper8"] for r in rows])),
+                  flush=True)
 
 
 if __name__ == "__main__":

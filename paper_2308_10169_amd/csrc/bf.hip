@@ -100,6 +100,49 @@ __device__ __forceinline__ float wave_prod(float x) {
   return x;
 }
 
+// One coordinate's move (Eq.(7)-(8)) and one lane's four function terms:
+// shared by the stepwise and the whole-run kernels, so that both compute the
+// same FP32 operations in the same order.
+__device__ __forceinline__ float bf_move(float x, float& v, float p, float gb, float tb, float w, float a1,
+                                         float a2, float a3, float vmax, float lo, float hi) {
+  float nv = w * v + a1 * (p - x) + a2 * (gb - x) + a3 * (tb - x);
+  nv = clampf(nv, -vmax, vmax);
+  v = nv;
+  return clampf(x + nv, lo, hi);
+}
+
+// Terms of elements e .. e+3 (those below D) into acc (and prod for
+// Griewank); prev = the element before e (Rosenbrock's pair).
+template <int FUNC>
+__device__ __forceinline__ void bf_terms(const float (&xv)[4], float prev, int e, int D, float& acc,
+                                         float& prod) {
+  if (FUNC == BF_ROSENBROCK) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = e + j;
+      const float xm = j == 0 ? prev : xv[j - 1];
+      if (d >= 1 && d < D) {
+        const float a = xv[j] - xm * xm, b = 1.f - xm;
+        acc += 100.f * a * a + b * b;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = e + j;
+      if (d < D) {
+        const float x = xv[j];
+        if (FUNC == BF_SPHERE) acc += x * x;
+        if (FUNC == BF_RASTRIGIN) acc += x * x + 10.f * (1.f - cospif(2.f * x));
+        if (FUNC == BF_GRIEWANK) {
+          acc += x * x * (1.f / 4000.f);
+          prod *= cosf(x / sqrtf((float)(d + 1)));
+        }
+      }
+    }
+  }
+}
+
 template <int FUNC, bool FIT>
 __global__ __launch_bounds__(256) void bf_iter_kernel(BFDev s) {
   const int lane = threadIdx.x & 63;
@@ -158,15 +201,8 @@ __global__ __launch_bounds__(256) void bf_iter_kernel(BFDev s) {
         const float* gs = &g4.x;
         const float* ts = &t4.x;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (e + j < D) {
-            const float x = xs[j];
-            float v = w * vs[j] + a1 * (ps[j] - x) + a2 * (gs[j] - x) + a3 * (ts[j] - x);
-            v = clampf(v, -vmax, vmax);
-            vs[j] = v;
-            xs[j] = clampf(x + v, s.lo, s.hi);
-          }
-        }
+        for (int j = 0; j < 4; ++j)
+          if (e + j < D) xs[j] = bf_move(xs[j], vs[j], ps[j], gs[j], ts[j], w, a1, a2, a3, vmax, s.lo, s.hi);
         X[q] = x4;
         V[q] = v4;
       }
@@ -176,36 +212,16 @@ __global__ __launch_bounds__(256) void bf_iter_kernel(BFDev s) {
       xv[3] = x4.w;
     }
     if (FIT) {
+      // Rosenbrock pairs (x[j-1], x[j]): the element before this lane's
+      // first comes from the previous lane, or for lane 0 from the previous
+      // chunk
+      float prev = 0.f;
       if (FUNC == BF_ROSENBROCK) {
-        // pairs (x[j-1], x[j]): the element before this lane's first comes
-        // from the previous lane, or for lane 0 from the previous chunk
-        float prev = __shfl_up(xv[3], 1);
+        prev = __shfl_up(xv[3], 1);
         if (lane == 0) prev = carry;
         carry = __shfl(xv[3], 63);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int d = e + j;
-          const float xm = j == 0 ? prev : xv[j - 1];
-          if (d >= 1 && d < D) {
-            const float a = xv[j] - xm * xm, b = 1.f - xm;
-            acc += 100.f * a * a + b * b;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int d = e + j;
-          if (d < D) {
-            const float x = xv[j];
-            if (FUNC == BF_SPHERE) acc += x * x;
-            if (FUNC == BF_RASTRIGIN) acc += x * x + 10.f * (1.f - cospif(2.f * x));
-            if (FUNC == BF_GRIEWANK) {
-              acc += x * x * (1.f / 4000.f);
-              prod *= cosf(x / sqrtf((float)(d + 1)));
-            }
-          }
-        }
       }
+      bf_terms<FUNC>(xv, prev, e, D, acc, prod);
     }
   }
   if (!FIT) return;
@@ -287,6 +303,246 @@ __global__ __launch_bounds__(256) void bf_best_kernel(BFDev s, float* out) {
   out[sw] = b;
 }
 
+// ---- whole run of a small swarm in one workgroup ----------------------------
+// A swarm whose state fits in LDS (rows of at most 256 floats) runs all its
+// iterations in one launch, one workgroup per swarm: the stepwise kernels'
+// move, evaluation, Pbest and bests in the same order and arithmetic
+// (bf_move, bf_terms, the same wave butterflies), with barriers instead of
+// kernel boundaries, so the results are bit-identical.  The control word is
+// read here and advanced by bf_ctl_kernel afterwards (every workgroup reads
+// it unchanged).
+constexpr int kBFRunThreads = 1024;
+
+struct BFRunLds {
+  int Q, L;      // float4 groups per row, lanes per particle (power of two >= Q)
+  size_t bytes;  // dynamic LDS
+};
+
+inline BFRunLds bf_run_lds(int Gs, int N, int Dp) {
+  BFRunLds r{};
+  r.Q = Dp / 4;
+  r.L = 1;
+  while (r.L < r.Q) r.L *= 2;
+  const size_t nS = (size_t)Gs * N;
+  r.bytes = 16 * (3 * nS * r.Q + (size_t)Gs * r.Q) + 4 * (nS * 7 + 10 * (size_t)Gs);
+  return r;
+}
+
+template <int FUNC>
+__global__ __launch_bounds__(kBFRunThreads) void bf_run_kernel(BFDev s, int n_fit, int flush, int L) {
+  extern __shared__ float4 s_dyn4[];
+  __shared__ int s_tg;
+  const int sw = blockIdx.x, t = threadIdx.x, B = blockDim.x;
+  const int Gs = s.Gs, N = s.N, D = s.D, Q = s.Dp / 4, nS = Gs * N, g0 = sw * Gs;
+  const int64_t r0 = (int64_t)g0 * N * Q;  // first float4 of the swarm's rows
+  float4* sX = s_dyn4;
+  float4* sV = sX + nS * Q;
+  float4* sP = sV + nS * Q;
+  float4* sG = sP + nS * Q;  // Gbest rows
+  float* sPf = reinterpret_cast<float*>(sG + Gs * Q);
+  float* sF = sPf + nS;
+  float* sC = sF + nS;                            // per particle a1, a2, a3, (unused)
+  int* sImp = reinterpret_cast<int*>(sC + 4 * nS);
+  float* sGf = reinterpret_cast<float*>(sImp + nS);
+  int* sGn = reinterpret_cast<int*>(sGf + Gs);
+  float* sH = reinterpret_cast<float*>(sGn + Gs);  // per group C1, C2, C3, w_init, w_end, V_limit
+  float* sW = sH + 6 * Gs;                         // per group inertia of the current move
+  float* sVm = sW + Gs;                            // per group velocity bound
+
+  const float4* X4 = reinterpret_cast<const float4*>(s.X) + r0;
+  const float4* V4 = reinterpret_cast<const float4*>(s.V) + r0;
+  const float4* P4 = reinterpret_cast<const float4*>(s.P) + r0;
+  const float4* G4 = reinterpret_cast<const float4*>(s.gbest_pos) + (int64_t)g0 * Q;
+  for (int q = t; q < nS * Q; q += B) {
+    sX[q] = X4[q];
+    sV[q] = V4[q];
+    sP[q] = P4[q];
+  }
+  for (int q = t; q < Gs * Q; q += B) sG[q] = G4[q];
+  for (int i = t; i < nS; i += B) {
+    sPf[i] = s.Pf[(int64_t)g0 * N + i];
+    sF[i] = s.f[(int64_t)g0 * N + i];
+  }
+  for (int g = t; g < Gs; g += B) {
+    sGf[g] = s.gbest_f[g0 + g];
+    sGn[g] = s.gbest_n[g0 + g];
+    const float* h = s.hyper + 6 * (g0 + g);
+    for (int j = 0; j < 6; ++j) sH[6 * g + j] = h[j];
+    sVm[g] = h[5] * (s.hi - s.lo) * 0.5f;
+  }
+  const BFCtl c0 = *s.ctl;
+  int k = c0.k, pending = c0.pending;
+  uint32_t ctr = c0.ctr;
+  __syncthreads();
+
+  const int lane = t & 63, wave = t >> 6, n_waves = B >> 6;
+  const int per_wave = 64 / L, seg = lane / L, ls = lane - seg * L;
+  for (int step = 0; step < n_fit + flush; ++step) {
+    const bool fit = step < n_fit;
+    if (pending) {
+      // Tbest of the swarm (lowest group best, lowest group on ties) and each
+      // particle's r1, r2, r3 scaled by its group's C1, C2, C3
+      if (t == 0) {
+        int tg = 0;
+        for (int g = 1; g < Gs; ++g)
+          if (sGf[g] < sGf[tg]) tg = g;
+        s_tg = tg;
+      }
+      const int kk = k < s.T ? k : s.T;
+      for (int g = t; g < Gs; g += B) {
+        const float* h = sH + 6 * g;
+        sW[g] = h[3] - (h[3] - h[4]) / (float)s.T * (float)kk;
+      }
+      for (int i = t; i < nS; i += B) {
+        const float* h = sH + 6 * (i / N);
+        const U4 r = philox((uint32_t)i, ctr, (uint32_t)sw, TAG_BF_UPDATE, s.seed_lo, s.seed_hi);
+        sC[4 * i + 0] = h[0] * u01(r.v[0]);
+        sC[4 * i + 1] = h[1] * u01(r.v[1]);
+        sC[4 * i + 2] = h[2] * u01(r.v[2]);
+      }
+      __syncthreads();
+      const int tg = s_tg;
+      for (int q = t; q < nS * Q; q += B) {
+        const int i = q / Q, qq = q - i * Q, g = i / N, e = 4 * qq;
+        const float w = sW[g], vmax = sVm[g];
+        const float a1 = sC[4 * i], a2 = sC[4 * i + 1], a3 = sC[4 * i + 2];
+        float4 x4 = sX[q], v4 = sV[q];
+        const float4 p4 = sP[q], gb4 = sG[g * Q + qq], tb4 = sG[tg * Q + qq];
+        float* xs = &x4.x;
+        float* vs = &v4.x;
+        const float* ps = &p4.x;
+        const float* gs = &gb4.x;
+        const float* ts = &tb4.x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (e + j < D) xs[j] = bf_move(xs[j], vs[j], ps[j], gs[j], ts[j], w, a1, a2, a3, vmax, s.lo, s.hi);
+        sX[q] = x4;
+        sV[q] = v4;
+      }
+      __syncthreads();
+    }
+    if (fit) {
+      // evaluation: L lanes per particle, lane ls holding elements 4 ls ..
+      // 4 ls + 3 as the stepwise kernel's lane ls does; the butterfly's
+      // steps below L add the exact zeros (ones) of the empty lanes there
+      for (int base = wave * per_wave; base < nS; base += n_waves * per_wave) {
+        const int i = base + seg;
+        const bool ok = i < nS && ls < Q;
+        float xv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (ok) {
+          const float4 x4 = sX[i * Q + ls];
+          xv[0] = x4.x;
+          xv[1] = x4.y;
+          xv[2] = x4.z;
+          xv[3] = x4.w;
+        }
+        float prev = 0.f;
+        if (FUNC == BF_ROSENBROCK) {
+          prev = __shfl_up(xv[3], 1);
+          if (ls == 0) prev = 0.f;
+        }
+        float acc = 0.f, prod = 1.f;
+        bf_terms<FUNC>(xv, prev, ok ? 4 * ls : D, D, acc, prod);
+        for (int m = L / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+        if (FUNC == BF_GRIEWANK) {
+          for (int m = L / 2; m > 0; m >>= 1) prod *= __shfl_xor(prod, m);
+        }
+        float fv = acc;
+        if (FUNC == BF_GRIEWANK) fv = 1.f + fv - prod;
+        if (!(fabsf(fv) <= 3.402823466e38f)) fv = INFINITY;
+        if (i < nS && ls == 0) {
+          const int imp = fv < sPf[i];
+          sF[i] = fv;
+          if (imp) sPf[i] = fv;
+          sImp[i] = imp;
+        }
+      }
+      __syncthreads();
+      for (int q = t; q < nS * Q; q += B)
+        if (sImp[q / Q]) sP[q] = sX[q];
+      // Gbest of every group: lowest Pbest, lowest index on ties
+      for (int g = t; g < Gs; g += B) {
+        float bf = INFINITY;
+        int bn = 0;
+        for (int n = 0; n < N; ++n) {
+          const float f = sPf[g * N + n];
+          if (f < bf) {
+            bf = f;
+            bn = n;
+          }
+        }
+        sGf[g] = bf;
+        sGn[g] = bn;
+      }
+      __syncthreads();
+      for (int q = t; q < Gs * Q; q += B) {
+        const int g = q / Q;
+        sG[q] = sP[(g * N + sGn[g]) * Q + (q - g * Q)];
+      }
+      __syncthreads();
+      k += 1;
+    }
+    ctr += pending ? 1u : 0u;
+    pending = fit ? 1 : 0;
+  }
+
+  float4* Xo = reinterpret_cast<float4*>(s.X) + r0;
+  float4* Vo = reinterpret_cast<float4*>(s.V) + r0;
+  float4* Po = reinterpret_cast<float4*>(s.P) + r0;
+  float4* Go = reinterpret_cast<float4*>(s.gbest_pos) + (int64_t)g0 * Q;
+  for (int q = t; q < nS * Q; q += B) {
+    Xo[q] = sX[q];
+    Vo[q] = sV[q];
+    Po[q] = sP[q];
+  }
+  for (int q = t; q < Gs * Q; q += B) Go[q] = sG[q];
+  for (int i = t; i < nS; i += B) {
+    s.Pf[(int64_t)g0 * N + i] = sPf[i];
+    s.f[(int64_t)g0 * N + i] = sF[i];
+  }
+  for (int g = t; g < Gs; g += B) {
+    s.gbest_f[g0 + g] = sGf[g];
+    s.gbest_n[g0 + g] = sGn[g];
+  }
+}
+
+// The control word after n_fit evaluated iterations and an optional flush
+// (the stepwise reduce's bookkeeping, step by step).
+__global__ void bf_ctl_kernel(BFDev s, int n_fit, int flush) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  BFCtl c = *s.ctl;
+  for (int step = 0; step < n_fit + flush; ++step) {
+    const bool fit = step < n_fit;
+    c.ctr += c.pending ? 1u : 0u;
+    if (fit) c.k += 1;
+    c.pending = fit ? 1 : 0;
+  }
+  *s.ctl = c;
+}
+
+bool bf_run_fits(const BFDev& s) {
+  return s.Dp <= 256 && bf_run_lds(s.Gs, s.N, s.Dp).bytes <= 64 * 1024;
+}
+
+template <int FUNC>
+void launch_bf_run_f(const BFDev& s, int n_fit, int flush, hipStream_t st) {
+  const BFRunLds r = bf_run_lds(s.Gs, s.N, s.Dp);
+  hipLaunchKernelGGL((bf_run_kernel<FUNC>), dim3(s.S), dim3(kBFRunThreads), r.bytes, st, s, n_fit, flush,
+                     r.L);
+}
+
+// n_fit evaluated iterations (then a flush move when flush) of every swarm,
+// in one launch plus the control-word update.
+void launch_bf_run(const BFDev& s, int n_fit, int flush, hipStream_t st) {
+  switch (s.func) {
+    case BF_SPHERE: launch_bf_run_f<BF_SPHERE>(s, n_fit, flush, st); break;
+    case BF_ROSENBROCK: launch_bf_run_f<BF_ROSENBROCK>(s, n_fit, flush, st); break;
+    case BF_RASTRIGIN: launch_bf_run_f<BF_RASTRIGIN>(s, n_fit, flush, st); break;
+    default: launch_bf_run_f<BF_GRIEWANK>(s, n_fit, flush, st); break;
+  }
+  hipLaunchKernelGGL(bf_ctl_kernel, dim3(1), dim3(64), 0, st, s, n_fit, flush);
+}
+
 void launch_bf_init(const BFDev& s, hipStream_t st) {
   const int64_t total = (int64_t)s.G * s.N * s.Dp;
   hipLaunchKernelGGL(bf_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, s);
@@ -320,6 +576,7 @@ struct sepso_bf {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool broken = false;
+  bool whole_run = false;  // small swarms: all iterations of a call in one launch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -351,6 +608,7 @@ sepso_status bf_check(const sepso_bf_cfg* c, bool check_hyper = true) {
   if (c->groups < 1 || c->groups > 64) return fail(SEPSO_E_ARG, "bf: groups in [1,64]");
   if (c->particles < 1 || c->dims < 1 || c->max_iters < 1)
     return fail(SEPSO_E_ARG, "bf: particles, dims, max_iters >= 1");
+  if (c->path < 0 || c->path > 1) return fail(SEPSO_E_ARG, "bf: path in {0, 1}");
   const double S = bf_swarms(c);
   const double elems = S * c->groups * c->particles * ((c->dims + 3) / 4 * 4);
   if (elems > 4.0e9 || S * c->groups * c->particles > 2.0e9 || S * c->groups > 2.0e9 / 6)
@@ -405,8 +663,12 @@ sepso_status bf_usable(sepso_bf* b) {
 }
 
 sepso_status bf_run(sepso_bf* b, int32_t n) {
-  for (int k = 0; k < n; ++k) launch_bf_step(b->dev, true, b->stream);
-  if (n > 0) launch_bf_step(b->dev, false, b->stream);
+  if (b->whole_run && n > 0) {
+    launch_bf_run(b->dev, n, 1, b->stream);
+  } else {
+    for (int k = 0; k < n; ++k) launch_bf_step(b->dev, true, b->stream);
+    if (n > 0) launch_bf_step(b->dev, false, b->stream);
+  }
   BFCHK(b, hipGetLastError());
   return SEPSO_OK;
 }
@@ -450,6 +712,7 @@ sepso_status bf_create(const sepso_bf_cfg* cfg, void* d_ws, size_t ws_bytes, voi
   d.gbest_pos = reinterpret_cast<float*>(w + L.gpos);
   d.hyper = reinterpret_cast<const float*>(w + L.hyper);
   if (hyper_dev) *hyper_dev = reinterpret_cast<float*>(w + L.hyper);
+  b->whole_run = cfg->path == 0 && bf_run_fits(d);
   if (stream) {
     b->stream = static_cast<hipStream_t>(stream);
   } else {
@@ -694,7 +957,11 @@ sepso_status sepso_bf_evolve_run(sepso_bf_evolve* ev, int32_t n, float* curve) {
     hipGraph_t g = nullptr;
     BFCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     launch_bf_init(d, b->stream);
-    for (int k = 0; k < d.T; ++k) launch_bf_step(d, true, b->stream);
+    if (b->whole_run) {
+      launch_bf_run(d, d.T, 0, b->stream);
+    } else {
+      for (int k = 0; k < d.T; ++k) launch_bf_step(d, true, b->stream);
+    }
     hipLaunchKernelGGL(bf_best_kernel, dim3((d.S + 255) / 256), dim3(256), 0, b->stream, d, ev->lower_best);
     launch_evolve_step(ev->dev, Pools{}, 1, b->stream);
     hipError_t eq = hipGetLastError();

@@ -70,7 +70,7 @@ class CTune(C.Structure):
 class CBFCfg(C.Structure):
     _fields_ = [("func", C.c_int32), ("groups", C.c_int32), ("particles", C.c_int32),
                 ("dims", C.c_int32), ("max_iters", C.c_int32), ("hyper", fp), ("lo", C.c_float),
-                ("hi", C.c_float), ("seed", C.c_uint64), ("swarms", C.c_int32)]
+                ("hi", C.c_float), ("seed", C.c_uint64), ("swarms", C.c_int32), ("path", C.c_int32)]
 
 
 class CBFState(C.Structure):
@@ -626,7 +626,7 @@ class BFSwarm:
     that many independent swarms of `groups` groups stepped together."""
 
     def __init__(self, func, groups, particles, dims, iters, hyper, lo=-600.0, hi=600.0, seed=0,
-                 stream=None, swarms=1):
+                 stream=None, swarms=1, stepwise=False):
         L = _load()
         torch = _torch
         self.S, self.Gs = swarms, groups
@@ -635,7 +635,7 @@ class BFSwarm:
         f = BF_FUNCS.get(func, func)
         self._cfg = CBFCfg(int(f), groups, particles, dims, iters,
                            self._hyper.ctypes.data_as(fp), float(lo), float(hi), int(seed),
-                           int(swarms))
+                           int(swarms), int(bool(stepwise)))
         nbytes = C.c_size_t()
         _check(L.sepso_bf_workspace_bytes(C.byref(self._cfg), C.byref(nbytes)))
         self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device="cuda")
@@ -711,14 +711,14 @@ class BFEvolver:
 
     def __init__(self, func, groups, particles, dims, iters, h_groups=8, h_particles=4,
                  evolutions=500, lo=-600.0, hi=600.0, seed=0, h_seed=0, h_hyper=None, h_lo=None,
-                 h_hi=None, stream=None):
+                 h_hi=None, stream=None, stepwise=False):
         L = _load()
         torch = _torch
         self.n, self.Dh, self.Gh, self.E = h_groups * h_particles, 6 * groups, h_groups, evolutions
         self.shape = (groups, particles, dims)
         f = BF_FUNCS.get(func, func)
         self._lcfg = CBFCfg(int(f), groups, particles, dims, iters, None, float(lo), float(hi),
-                            int(seed), 0)
+                            int(seed), 0, int(bool(stepwise)))
         self._keep = [None if a is None else _f32(a).reshape(-1) for a in (h_hyper, h_lo, h_hi)]
         ptr = lambda a: a.ctypes.data_as(fp) if a is not None else None
         self._cfg = CEvolveCfg(h_groups, h_particles, evolutions, *[ptr(a) for a in self._keep],

@@ -140,3 +140,43 @@ def test_multi_swarm_injected_step(sp, func):
             assert np.max(np.abs(st1[k][sl] - getattr(o, k))) <= 2e-4, (s, k)
     assert np.array_equal(g.swarm_best(st1), st1["gbest_f"].reshape(S, G).min(1))
     g.close()
+
+
+def _same_state(a, b):
+    for k in ("X", "V", "P", "f", "Pf", "gbest_n", "gbest_f"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["tbest"] == b["tbest"] and a["k"] == b["k"] and a["ctr"] == b["ctr"]
+    assert a["pending"] == b["pending"]
+
+
+@pytest.mark.parametrize("func", FUNCS)
+@pytest.mark.parametrize("shape", [(8, 10, 30), (3, 7, 37), (2, 5, 1), (2, 3, 256)])
+def test_whole_run_equals_stepwise(sp, func, shape):
+    # one workgroup per swarm for a whole call against two launches per
+    # iteration: bit-identical state after calls of 60, 1 and 39 iterations
+    # (ragged rows: 37 -> 10 float4 groups on 16 lanes; 1; the 256 limit)
+    G, N, D = shape
+    S = 3
+    hy = np.concatenate([_hyper(8)[(np.arange(G) + s) % 8] for s in range(S)])
+    a = sp.BFSwarm(func, G, N, D, 100, hy, seed=4, swarms=S)
+    b = sp.BFSwarm(func, G, N, D, 100, hy, seed=4, swarms=S, stepwise=True)
+    for n in (60, 1, 39):
+        a.step(n)
+        b.step(n)
+        _same_state(a.get_state(), b.get_state())
+    a.close()
+    b.close()
+
+
+def test_whole_run_evolution_equals_stepwise(sp):
+    ea = sp.BFEvolver(2, 8, 10, 30, 50, h_groups=2, h_particles=3, evolutions=4, seed=1, h_seed=3)
+    eb = sp.BFEvolver(2, 8, 10, 30, 50, h_groups=2, h_particles=3, evolutions=4, seed=1, h_seed=3,
+                      stepwise=True)
+    ca, cb = ea.run(3), eb.run(3)
+    assert np.array_equal(ca, cb)
+    sa, sb = ea.get_state(), eb.get_state()
+    for k in ("X", "V", "P", "Pf", "lfv"):
+        assert np.array_equal(sa[k], sb[k]), k
+    _same_state(ea.lower.get_state(), eb.lower.get_state())
+    ea.close()
+    eb.close()
