@@ -511,12 +511,13 @@ __global__ __launch_bounds__(kBFRunThreads) void bf_run_kernel(BFDev s, int n_fi
 __global__ void bf_ctl_kernel(BFDev s, int n_fit, int flush) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   BFCtl c = *s.ctl;
-  for (int step = 0; step < n_fit + flush; ++step) {
-    const bool fit = step < n_fit;
-    c.ctr += c.pending ? 1u : 0u;
-    if (fit) c.k += 1;
-    c.pending = fit ? 1 : 0;
-  }
+  // every step advances the counter by the move it owes: the first by the
+  // pending flag it starts with, every later one by 1 (a fit step leaves a
+  // move owed)
+  const int steps = n_fit + flush;
+  if (steps > 0) c.ctr += (c.pending ? 1u : 0u) + (uint32_t)(steps - 1);
+  c.k += n_fit;
+  if (steps > 0) c.pending = flush ? 0 : 1;
   *s.ctl = c;
 }
 

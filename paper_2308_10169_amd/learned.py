@@ -6,6 +6,7 @@ on held-out dynamic sequences (plain Priori Initialization from the previous
 frame's plan).
 
   python -m paper_2308_10169_amd.learned --samples 32768 --steps 2000
+  python -m paper_2308_10169_amd.learned --samples 16384 --train-only 5 --steps 20 --batch 8192
 
 Every step runs in libsepso; this module only drives it.
 """
@@ -151,6 +152,23 @@ def evaluate_dynamic(lin, n_maps=256, frames=6, seed=3_000_000, iters=50, tune=(
                 frame0_median_iters_learned=float(np.median(iters_to_reach(h_l[0], c_p[0]))))
 
 
+def train_only(args):
+    """Training steps alone (the MLP kernels' workload for profiling): fill the
+    training set, take warm-up steps, then time `args.steps` steps."""
+    import torch
+    lin = sepso.LearnedInit(max_rows=max(4096, args.batch), max_samples=args.samples, seed=0)
+    n = generate(lin, args.samples, seed=7)
+    lin.train(args.train_only, args.batch, args.lr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = lin.train(args.steps, args.batch, args.lr)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps(dict(samples=n, batch=args.batch, steps=args.steps, ms_per_step=1e3 * dt / args.steps,
+                          loss_last=float(loss[-1]))), flush=True)
+    lin.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=32768)
@@ -160,7 +178,12 @@ def main():
     ap.add_argument("--heldout", type=int, default=512)
     ap.add_argument("--dynamic", type=int, default=256, help="held-out dynamic sequences")
     ap.add_argument("--out", default=None, help="write trained weights (.npy) here")
+    ap.add_argument("--train-only", type=int, default=0, metavar="W",
+                    help="generate, take W warm-up steps, then time --steps training steps only")
     args = ap.parse_args()
+    if args.train_only:
+        train_only(args)
+        return
     lin = sepso.LearnedInit(max_rows=4096, max_samples=args.samples, seed=0)
     t0 = time.perf_counter()
     n = generate(lin, args.samples)
