@@ -59,7 +59,8 @@ def main():
     tests, elems = bp.work()
     if args.frames_first > 0:
         bp.plan(args.frames_first)
-    bp.profile_step(args.warmup_launches)  # clocks settle before the measured launches
+    if args.warmup_launches > 0:
+        bp.profile_step(args.warmup_launches)  # clocks settle before the measured launches
     ms = bp.profile_step(args.launches)
     rate = tests / (ms * 1e-3)
     print(json.dumps(dict(workload=args.workload, instances=len(specs), tune=tune,
