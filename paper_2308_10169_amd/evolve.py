@@ -8,6 +8,7 @@ Table hyper8path and Table hyper8 are each scored by many independent
 lower-level runs.
 
   python -m paper_2308_10169_amd.evolve --evolutions 100 --h-particles 8
+  python -m paper_2308_10169_amd.evolve --scene paper --waypoints 20 --iters 10 --evolutions 500
 """
 from __future__ import annotations
 
@@ -45,11 +46,17 @@ def score(hyper, spec, runs=256, particles=170, waypoints=8, iters=30, seed=1000
                 collision_free=float(np.mean(r["crossings"][0] == 0)))
 
 
+def scene(name, seed):
+    """'ablation': the 8-rectangle scene of the Table ppresult runs; 'paper':
+    the paper-shaped dynamic map (10 static + 20 moving rectangles)."""
+    return ablation.scene(seed) if name == "ablation" else I.dynamic_map(seed)
+
+
 def run(evolutions=100, h_groups=8, h_particles=8, particles=170, waypoints=8, iters=30,
-        seed=0, runs=256, tune=None):
+        seed=0, runs=256, tune=None, scene_name="ablation"):
     from paper_2308_10169_amd import sepso
     import torch
-    spec = ablation.scene(seed)
+    spec = scene(scene_name, seed)
     ev = sepso.Evolver(spec, lower_swarm(None, particles, waypoints, iters, seed), h_groups,
                        h_particles, evolutions, seed=seed)
     if tune is not None:
@@ -61,7 +68,7 @@ def run(evolutions=100, h_groups=8, h_particles=8, particles=170, waypoints=8, i
     dt = time.perf_counter() - t0
     best, lfv = ev.best()
     ev.close()
-    out = dict(evolutions=evolutions, h_particles=h_groups * h_particles,
+    out = dict(scene=scene_name, evolutions=evolutions, h_particles=h_groups * h_particles,
                lower=dict(groups=8, particles=particles, waypoints=waypoints, iters=iters),
                s_per_evolution=dt / max(evolutions - 1, 1),
                curve=[float(x) for x in curve[:: max(1, len(curve) // 20)]],
@@ -78,11 +85,15 @@ def main():
     ap.add_argument("--h-groups", type=int, default=8)
     ap.add_argument("--h-particles", type=int, default=8)
     ap.add_argument("--particles", type=int, default=170)
+    ap.add_argument("--waypoints", type=int, default=8)
+    ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--runs", type=int, default=256)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--scene", choices=["ablation", "paper"], default="ablation")
     args = ap.parse_args()
     print(json.dumps(run(args.evolutions, args.h_groups, args.h_particles, args.particles,
-                         runs=args.runs, seed=args.seed)), flush=True)
+                         args.waypoints, args.iters, runs=args.runs, seed=args.seed,
+                         scene_name=args.scene)), flush=True)
 
 
 if __name__ == "__main__":
