@@ -192,24 +192,35 @@ __device__ __forceinline__ void fetch128(const uint16_t* __restrict__ P, int ld,
   }
 }
 
+// LDS position (in halves) of k offset k of tile row `row`: the row's eight
+// 16-byte chunks of k are permuted by the row's bits 4..6, so that the
+// transposing stores below (lanes 0..15 of a wave write rows 8 apart at one
+// k) land in sixteen different banks, while the MFMA operand reads (sixteen
+// consecutive rows from a multiple of 16, one chunk) keep one permutation
+// per instruction and stay conflict-free on the padded rows.
+template <int LDS>
+__device__ __forceinline__ int swz128(int row, int k) {
+  return row * LDS + ((((k >> 3) ^ (row >> 4)) & 7) << 3) + (k & 7);
+}
+
 // The registers of fetch128 into an LDS tile of rows of LDS halves (k
-// contiguous) at k offset kh; a K-major operand is transposed two k values at
-// a time (one 32-bit store per row).
+// contiguous, chunks permuted by swz128) at k offset kh; a K-major operand is
+// transposed two k values at a time (one 32-bit store per row).
 template <bool KM, int LDS>
 __device__ __forceinline__ void stash128(uint16_t* S, int kh, int t, const uint4& r0v,
                                          const uint4& r1v) {
   if (!KM) {
     const int row = t >> 1, kc = kh + (t & 1) * 16;
-    *reinterpret_cast<uint4*>(&S[row * LDS + kc]) = r0v;
-    *reinterpret_cast<uint4*>(&S[row * LDS + kc + 8]) = r1v;
+    *reinterpret_cast<uint4*>(&S[swz128<LDS>(row, kc)]) = r0v;
+    *reinterpret_cast<uint4*>(&S[swz128<LDS>(row, kc + 8)]) = r1v;
   } else {
     const int kr = kh + 2 * (t >> 4), mc = (t & 15) * 8;
     const uint32_t u0[4] = {r0v.x, r0v.y, r0v.z, r0v.w}, u1[4] = {r1v.x, r1v.y, r1v.z, r1v.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {  // columns 2i, 2i+1: (k, k+1) as one 32-bit word each
-      *reinterpret_cast<uint32_t*>(&S[(mc + 2 * i) * LDS + kr]) =
+      *reinterpret_cast<uint32_t*>(&S[swz128<LDS>(mc + 2 * i, kr)]) =
           __builtin_amdgcn_perm(u1[i], u0[i], 0x05040100u);
-      *reinterpret_cast<uint32_t*>(&S[(mc + 2 * i + 1) * LDS + kr]) =
+      *reinterpret_cast<uint32_t*>(&S[swz128<LDS>(mc + 2 * i + 1, kr)]) =
           __builtin_amdgcn_perm(u1[i], u0[i], 0x07060302u);
     }
   }
@@ -269,8 +280,8 @@ __global__ __launch_bounds__(256) void gemm128_kernel(const uint16_t* __restrict
       bf16x8 a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        a[i] = *reinterpret_cast<const bf16x8*>(&as[(wm + i * 16 + r16) * LDS + kk + kq]);
-        b[i] = *reinterpret_cast<const bf16x8*>(&bs[(wn + i * 16 + r16) * LDS + kk + kq]);
+        a[i] = *reinterpret_cast<const bf16x8*>(&as[swz128<LDS>(wm + i * 16 + r16, kk + kq)]);
+        b[i] = *reinterpret_cast<const bf16x8*>(&bs[swz128<LDS>(wn + i * 16 + r16, kk + kq)]);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -453,11 +464,16 @@ void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_
   // (measured: even two-step slices pay for their slice sum at the training
   // shapes; 512 blocks against 256 took the batch-8192 step from 0.83 to
   // 0.73 ms).
+  // A long reduction over a transposed operand (the weight gradients of the
+  // 512-wide layers, K = the batch) also takes the 128 tiles, split up to 16
+  // ways: their transposed stash is the conflict-free one.
   const int tiles128 = ((N + 127) / 128) * ((M + 127) / 128);
-  const int T = tiles128 >= 64 ? 128 : 64;
+  const bool long_k = K >= 2048 && (a_km || b_kn);
+  const int T = tiles128 >= 64 || long_k ? 128 : 64;
+  const int smax = T == 128 && tiles128 < 64 ? 16 : 8;
   const int tiles = ((N + T - 1) / T) * ((M + T - 1) / T), steps = K / 32;
   int S = 1;
-  while (S < 8 && tiles * S < 512 && S * 2 <= steps && (int64_t)S * 2 * M * N <= ws_floats)
+  while (S < smax && tiles * S < 512 && S * 2 <= steps && (int64_t)S * 2 * M * N <= ws_floats)
     S *= 2;
   const int kper = steps > 0 ? (steps + S - 1) / S : 1;
   S = steps > 0 ? (steps + kper - 1) / kper : 1;
