@@ -473,7 +473,11 @@ void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_
   const int smax = T == 128 && tiles128 < 64 ? 16 : 8;
   const int tiles = ((N + T - 1) / T) * ((M + T - 1) / T), steps = K / 32;
   int S = 1;
-  while (S < smax && tiles * S < 512 && S * 2 <= steps && (int64_t)S * 2 * M * N <= ws_floats)
+  // a short reduction on a grid that already gives every CU a block keeps
+  // its epilogue in the product kernel (the slice sum would cost more)
+  const bool whole = T == 128 && tiles >= 256 && K <= 1024;
+  while (!whole && S < smax && tiles * S < 512 && S * 2 <= steps &&
+         (int64_t)S * 2 * M * N <= ws_floats)
     S *= 2;
   const int kper = steps > 0 ? (steps + S - 1) / S : 1;
   S = steps > 0 ? (steps + kper - 1) / kper : 1;
