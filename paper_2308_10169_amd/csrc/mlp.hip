@@ -228,18 +228,21 @@ __device__ __forceinline__ void stash128(uint16_t* S, int kh, int t, const uint4
 
 // The same product on a 128 x 128 block tile for large problems: four waves
 // of 64 x 64 (4 x 4 MFMA 16x16x32 tiles, 64 accumulator registers), k-steps
-// of 64 (two MFMA k-steps; a slice's last may be 32 wide) double-buffered in
-// LDS -- the next step's global loads are in flight in registers while the
-// current step's MFMAs run, one barrier per step.  Same contract as
-// gemm_kernel.
+// of 64 (two MFMA k-steps; a slice's last may be 32 wide) through one LDS
+// buffer -- the next step's global loads are in flight in registers while
+// the current step's MFMAs run, two barriers per step.  One buffer (37 KB)
+// lets four blocks share a CU where two buffers allowed two; the waves spend
+// most of their time waiting, and the extra blocks hide more of it (layer-1
+// weight gradient at 8192 rows: 102 -> 84 us).  Same contract as gemm_kernel.
 template <bool A_KM, bool B_KN>
 __global__ __launch_bounds__(256) void gemm128_kernel(const uint16_t* __restrict__ A, int lda,
                                                       const uint16_t* __restrict__ B, int ldb,
                                                       int M, int N, int K, int kper, float* part,
                                                       Epi ep) {
   constexpr int T = 128, LDS = 72;  // padded row (k) length
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][T * LDS];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][T * LDS];
+  constexpr int NB = 1;              // LDS buffers (2: one barrier per step, two blocks per CU)
+  __shared__ __attribute__((aligned(16))) uint16_t As[NB][T * LDS];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[NB][T * LDS];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
@@ -289,9 +292,15 @@ __global__ __launch_bounds__(256) void gemm128_kernel(const uint16_t* __restrict
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (more) stash(buf ^ 1);  // the other buffer: its last readers passed the previous barrier
-    __syncthreads();
-    buf ^= 1;
+    if (NB == 2) {
+      if (more) stash(buf ^ 1);  // the other buffer: its last readers passed the previous barrier
+      __syncthreads();
+      buf ^= 1;
+    } else {
+      __syncthreads();  // every wave has read this step's tiles
+      if (more) stash(0);
+      __syncthreads();
+    }
   }
   // D layout: lane holds column (lane % 16), rows 4*(lane/16) .. +3
 #pragma unroll
@@ -459,8 +468,8 @@ void launch_raster(const Pools& pl, int n_inst, uint16_t* X, int ldx, int32_t* e
 void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_t* B, int ldb,
                  int M, int N, int K, const Epi& ep, float* ws, int64_t ws_floats, hipStream_t s) {
   // 128 x 128 tiles once they alone give a quarter of the CUs a tile; then
-  // split K until the grid has two blocks per CU (a 128 x 128 block's LDS
-  // leaves room for two), as far as the k-steps and the workspace allow
+  // split K until the grid has two blocks per CU, as far as the k-steps and
+  // the workspace allow
   // (measured: even two-step slices pay for their slice sum at the training
   // shapes; 512 blocks against 256 took the batch-8192 step from 0.83 to
   // 0.73 ms).
