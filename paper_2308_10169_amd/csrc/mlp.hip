@@ -159,11 +159,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(const uint16_t* __restrict__ 
       }
 }
 
-// The same product on a 128 x 128 block tile for large problems: four waves
-// of 64 x 64 (4 x 4 MFMA 16x16x32 tiles, 64 accumulator registers), k-steps
-// of 32 double-buffered in LDS -- the next step's global loads are in flight
-// in registers while the current step's MFMAs run, one barrier per step.
-// Same contract as gemm_kernel.
 // One 32-wide k half-step of a 128-row operand tile (rows of the output
 // dimension x 32 k) into two registers per thread.  K-contiguous source
 // (KM = false): row t/2, k 16*(t&1) .. +15.  K-major source: k rows 2*(t/16)
@@ -227,86 +222,100 @@ __device__ __forceinline__ void stash128(uint16_t* S, int kh, int t, const uint4
 }
 
 // The same product on a 128 x 128 block tile for large problems: four waves
-// of 64 x 64 (4 x 4 MFMA 16x16x32 tiles, 64 accumulator registers), k-steps
-// of 64 (two MFMA k-steps; a slice's last may be 32 wide) through one LDS
-// buffer -- the next step's global loads are in flight in registers while
+// of 64 x 64 (4 x 4 MFMA 16x16x32 tiles, 64 accumulator registers) or eight
+// of 64 x 32 (4 x 2 tiles; waves 0-3 load the A tile, waves 4-7 the B tile),
+// k-steps of 64 (two MFMA k-steps; a slice's last may be 32 wide) through one
+// LDS buffer -- the next step's global loads are in flight in registers while
 // the current step's MFMAs run, two barriers per step.  One buffer (37 KB)
 // lets four blocks share a CU where two buffers allowed two; the waves spend
 // most of their time waiting, and the extra blocks hide more of it (layer-1
 // weight gradient at 8192 rows: 102 -> 84 us).  Same contract as gemm_kernel.
-template <bool A_KM, bool B_KN>
-__global__ __launch_bounds__(256) void gemm128_kernel(const uint16_t* __restrict__ A, int lda,
-                                                      const uint16_t* __restrict__ B, int ldb,
-                                                      int M, int N, int K, int kper, float* part,
-                                                      Epi ep) {
+template <bool A_KM, bool B_KN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void gemm128_kernel(const uint16_t* __restrict__ A, int lda,
+                                                             const uint16_t* __restrict__ B, int ldb,
+                                                             int M, int N, int K, int kper, float* part,
+                                                             Epi ep) {
   constexpr int T = 128, LDS = 72;  // padded row (k) length
-  constexpr int NB = 1;              // LDS buffers (2: one barrier per step, two blocks per CU)
-  __shared__ __attribute__((aligned(16))) uint16_t As[NB][T * LDS];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[NB][T * LDS];
+  constexpr int NJ = WAVES == 8 ? 2 : 4;  // 16-column MFMA tiles per wave
+  __shared__ __attribute__((aligned(16))) uint16_t As[T * LDS];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[T * LDS];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
-  f32x4 acc[4][4];
+  // four waves: 2 x 2 of 64 x 64; eight waves: 2 x 4 of 64 x 32
+  const int wm = WAVES == 8 ? (w >> 2) * 64 : (w >> 1) * 64;
+  const int wn = WAVES == 8 ? (w & 3) * 32 : (w & 1) * 64;
+  f32x4 acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int kbeg = blockIdx.z * kper * 32, kend = min(K, kbeg + kper * 32);
+  // with eight waves, waves 0-3 carry A and waves 4-7 carry B (in ra*)
+  const int tt = t & 255;
+  const bool carry_a = WAVES == 4 || t < 256;
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
   auto fetch = [&](int k0) {
     const bool hi = k0 + 32 < kend;
-    fetch128<A_KM>(A, lda, m0, M, k0, t, true, ra0, ra1);
-    fetch128<A_KM>(A, lda, m0, M, k0 + 32, t, hi, ra2, ra3);
-    fetch128<B_KN>(B, ldb, n0, N, k0, t, true, rb0, rb1);
-    fetch128<B_KN>(B, ldb, n0, N, k0 + 32, t, hi, rb2, rb3);
+    if (WAVES == 4) {
+      fetch128<A_KM>(A, lda, m0, M, k0, t, true, ra0, ra1);
+      fetch128<A_KM>(A, lda, m0, M, k0 + 32, t, hi, ra2, ra3);
+      fetch128<B_KN>(B, ldb, n0, N, k0, t, true, rb0, rb1);
+      fetch128<B_KN>(B, ldb, n0, N, k0 + 32, t, hi, rb2, rb3);
+    } else if (carry_a) {
+      fetch128<A_KM>(A, lda, m0, M, k0, tt, true, ra0, ra1);
+      fetch128<A_KM>(A, lda, m0, M, k0 + 32, tt, hi, ra2, ra3);
+    } else {
+      fetch128<B_KN>(B, ldb, n0, N, k0, tt, true, ra0, ra1);
+      fetch128<B_KN>(B, ldb, n0, N, k0 + 32, tt, hi, ra2, ra3);
+    }
   };
-  auto stash = [&](int bf) {
-    stash128<A_KM, LDS>(As[bf], 0, t, ra0, ra1);
-    stash128<A_KM, LDS>(As[bf], 32, t, ra2, ra3);
-    stash128<B_KN, LDS>(Bs[bf], 0, t, rb0, rb1);
-    stash128<B_KN, LDS>(Bs[bf], 32, t, rb2, rb3);
+  auto stash = [&]() {
+    if (WAVES == 4) {
+      stash128<A_KM, LDS>(As, 0, t, ra0, ra1);
+      stash128<A_KM, LDS>(As, 32, t, ra2, ra3);
+      stash128<B_KN, LDS>(Bs, 0, t, rb0, rb1);
+      stash128<B_KN, LDS>(Bs, 32, t, rb2, rb3);
+    } else if (carry_a) {
+      stash128<A_KM, LDS>(As, 0, tt, ra0, ra1);
+      stash128<A_KM, LDS>(As, 32, tt, ra2, ra3);
+    } else {
+      stash128<B_KN, LDS>(Bs, 0, tt, ra0, ra1);
+      stash128<B_KN, LDS>(Bs, 32, tt, ra2, ra3);
+    }
   };
   if (kbeg < kend) {
     fetch(kbeg);
-    stash(0);
+    stash();
   }
   __syncthreads();
   const int r16 = lane & 15, kq = (lane >> 4) * 8;
-  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += 64) {
     const bool more = k0 + 64 < kend;
     if (more) fetch(k0 + 64);  // in flight during this step's MFMAs
-    const uint16_t* as = As[buf];
-    const uint16_t* bs = Bs[buf];
 #pragma unroll
     for (int kk = 0; kk < 64; kk += 32) {  // the upper half of a short last step is zeros
-      bf16x8 a[4], b[4];
+      bf16x8 a[4], b[NJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = *reinterpret_cast<const bf16x8*>(&as[swz128<LDS>(wm + i * 16 + r16, kk + kq)]);
-        b[i] = *reinterpret_cast<const bf16x8*>(&bs[swz128<LDS>(wn + i * 16 + r16, kk + kq)]);
-      }
+      for (int i = 0; i < 4; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[swz128<LDS>(wm + i * 16 + r16, kk + kq)]);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(&Bs[swz128<LDS>(wn + j * 16 + r16, kk + kq)]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (NB == 2) {
-      if (more) stash(buf ^ 1);  // the other buffer: its last readers passed the previous barrier
-      __syncthreads();
-      buf ^= 1;
-    } else {
-      __syncthreads();  // every wave has read this step's tiles
-      if (more) stash(0);
-      __syncthreads();
-    }
+    __syncthreads();  // every wave has read this step's tiles
+    if (more) stash();
+    __syncthreads();
   }
   // D layout: lane holds column (lane % 16), rows 4*(lane/16) .. +3
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
@@ -492,15 +501,29 @@ void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_
   S = steps > 0 ? (steps + kper - 1) / kper : 1;
   float* part = S > 1 ? ws : nullptr;
   const dim3 grid((N + T - 1) / T, (M + T - 1) / T, S);
-  if (T == 128) {
+  if (T == 128 && K >= 2048 && tiles128 >= 64) {
+    // large products (the first layer's): four waves of 64 x 64 (fewer LDS
+    // reads per MFMA; the grid alone fills the CUs)
+    const dim3 blk(256);
     if (!a_km && !b_kn)
-      hipLaunchKernelGGL((gemm128_kernel<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+      hipLaunchKernelGGL((gemm128_kernel<false, false, 4>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
     else if (!a_km && b_kn)
-      hipLaunchKernelGGL((gemm128_kernel<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+      hipLaunchKernelGGL((gemm128_kernel<false, true, 4>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
     else if (a_km && b_kn)
-      hipLaunchKernelGGL((gemm128_kernel<true, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+      hipLaunchKernelGGL((gemm128_kernel<true, true, 4>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
     else
-      hipLaunchKernelGGL((gemm128_kernel<true, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+      hipLaunchKernelGGL((gemm128_kernel<true, false, 4>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+  } else if (T == 128) {
+    // the rest: eight waves of 64 x 32 (more waves to cover the loads' latency)
+    const dim3 blk(512);
+    if (!a_km && !b_kn)
+      hipLaunchKernelGGL((gemm128_kernel<false, false, 8>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+    else if (!a_km && b_kn)
+      hipLaunchKernelGGL((gemm128_kernel<false, true, 8>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+    else if (a_km && b_kn)
+      hipLaunchKernelGGL((gemm128_kernel<true, true, 8>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
+    else
+      hipLaunchKernelGGL((gemm128_kernel<true, false, 8>), grid, blk, 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
   } else if (!a_km && !b_kn)
     hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kper, part, ep);
   else if (!a_km && b_kn)
