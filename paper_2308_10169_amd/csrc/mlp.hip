@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void targets_kernel(Pools pl, float* T, int ld
 // block (x, y) takes 64 columns of the row chunk [256y, 256y + 256), its
 // wave w sums rows w, w+4, ... of the chunk (eight loads in flight per lane)
 // and the four partial sums are added in wave order into part[y][col];
-// colsum_fin_kernel then adds the chunks in chunk order.
+// colsum_fin_kernel then adds the chunks in a fixed order.
 __global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int n, float* part) {
   __shared__ float ps[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -409,12 +409,22 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int
   if (w == 0 && j < n) part[(int64_t)blockIdx.y * n + j] = ((ps[0][lane] + ps[1][lane]) + ps[2][lane]) + ps[3][lane];
 }
 
+// 32 columns per block, eight threads per column: thread `sub` adds chunks
+// sub, sub + 8, ... in order, then the eight sums are added pairwise in a
+// fixed tree (the same order on every call).
 __global__ __launch_bounds__(256) void colsum_fin_kernel(const float* part, int R, int n, float* out) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  float s = part[j];
-  for (int y = 1; y < R; ++y) s += part[(int64_t)y * n + j];
-  out[j] = s;
+  __shared__ float ps[8][32];
+  const int c = threadIdx.x & 31, sub = threadIdx.x >> 5;
+  const int j = blockIdx.x * 32 + c;
+  float s = 0.f;
+  if (j < n) {
+#pragma unroll 4
+    for (int y = sub; y < R; y += 8) s += part[(int64_t)y * n + j];
+  }
+  ps[sub][c] = s;
+  __syncthreads();
+  if (sub == 0 && j < n)
+    out[j] = ((ps[0][c] + ps[1][c]) + (ps[2][c] + ps[3][c])) + ((ps[4][c] + ps[5][c]) + (ps[6][c] + ps[7][c]));
 }
 
 // Adam on FP32 master weights, refreshing the BF16 copies used by the GEMMs,
@@ -555,7 +565,7 @@ void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t 
 void launch_colsum(const float* dz, int B, int n, float* out, float* ws, hipStream_t s) {
   const int R = (B + 255) / 256;
   hipLaunchKernelGGL(colsum_kernel, dim3((n + 63) / 64, R), dim3(256), 0, s, dz, B, n, ws);
-  hipLaunchKernelGGL(colsum_fin_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ws, R, n, out);
+  hipLaunchKernelGGL(colsum_fin_kernel, dim3((n + 31) / 32), dim3(256), 0, s, ws, R, n, out);
 }
 
 void launch_adam_sets(AdamSets a, float lr, float b1, float b2, float eps, float c1, float c2,
