@@ -150,11 +150,13 @@ def _same_state(a, b):
 
 
 @pytest.mark.parametrize("func", FUNCS)
-@pytest.mark.parametrize("shape", [(8, 10, 30), (3, 7, 37), (2, 5, 1), (2, 3, 256)])
+@pytest.mark.parametrize("shape", [(8, 10, 30), (3, 7, 37), (2, 5, 1), (2, 3, 256), (5, 25, 40)])
 def test_whole_run_equals_stepwise(sp, func, shape):
     # one workgroup per swarm for a whole call against two launches per
     # iteration: bit-identical state after calls of 60, 1 and 39 iterations
-    # (ragged rows: 37 -> 10 float4 groups on 16 lanes; 1; the 256 limit)
+    # (ragged rows: 37 -> 10 float4 groups on 16 lanes; 1; the 256-float row
+    # limit; 125 particles of 40 floats: 64 500 bytes of LDS, just under the
+    # 64 KiB limit)
     G, N, D = shape
     S = 3
     hy = np.concatenate([_hyper(8)[(np.arange(G) + s) % 8] for s in range(S)])
