@@ -338,43 +338,66 @@ __global__ __launch_bounds__(256) void splitk_epi_kernel(const float* __restrict
   apply_epi(ep, (int)(i / N), (int)(i % N), v);
 }
 
-// dy = 2 (y - target) / (B * n) (FP32 and BF16) and per-row squared-error sums.
+// dy = 2 (y - target) / (B * n) (FP32 and BF16) and per-row squared-error
+// sums: one wave per row (four rows per block), each lane summing columns
+// lane, lane + 64, ... in order, then a butterfly over the wave.  A lane's
+// loads (up to eight) are all issued before its first store.
 __global__ __launch_bounds__(256) void loss_kernel(const float* y, const float* target, int B,
                                                    int n, float* dy, uint16_t* dy16,
                                                    float* row_sq) {
-  const int r = blockIdx.x;
-  __shared__ float s[256];
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= B) return;  // whole waves
   float acc = 0.f;
   const float scale = 2.f / ((float)B * (float)n);
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const int64_t o = (int64_t)r * n + j;
-    const float e = y[o] - target[o];
-    acc += e * e;
-    dy[o] = scale * e;
-    dy16[o] = to_bf16(scale * e);
+  const float* yr = y + (int64_t)r * n;
+  const float* tr = target + (int64_t)r * n;
+  for (int j0 = lane; j0 < n; j0 += 8 * 64) {  // every load of the pass in flight at once
+    float e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + 64 * u;
+      e[u] = j < n ? yr[j] - tr[j] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + 64 * u;
+      if (j < n) {
+        acc += e[u] * e[u];
+        dy[(int64_t)r * n + j] = scale * e[u];
+        dy16[(int64_t)r * n + j] = to_bf16(scale * e[u]);
+      }
+    }
   }
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (unsigned m = blockDim.x / 2; m > 0; m >>= 1) {
-    if (threadIdx.x < m) s[threadIdx.x] += s[threadIdx.x + m];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) row_sq[r] = s[0];
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+  if (lane == 0) row_sq[r] = acc;
 }
 
-// Mean of the per-row squared errors (one block, fixed order).
-__global__ __launch_bounds__(256) void loss_sum_kernel(const float* row_sq, int B, float scale,
-                                                       float* out) {
-  __shared__ float s[256];
+// Mean of the per-row squared errors (one block of 1024 threads, fixed order:
+// thread t sums rows t, t + 1024, ... eight loads at a time, then a butterfly
+// per wave and the sixteen wave sums in wave order).
+__global__ __launch_bounds__(1024) void loss_sum_kernel(const float* row_sq, int B, float scale,
+                                                        float* out) {
+  __shared__ float s[16];
+  const int t = threadIdx.x, lane = t & 63;
   float acc = 0.f;
-  for (int r = threadIdx.x; r < B; r += blockDim.x) acc += row_sq[r];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (unsigned m = blockDim.x / 2; m > 0; m >>= 1) {
-    if (threadIdx.x < m) s[threadIdx.x] += s[threadIdx.x + m];
-    __syncthreads();
+  for (int r0 = t; r0 < B; r0 += 8 * 1024) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = r0 + u * 1024 < B ? row_sq[r0 + u * 1024] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
   }
-  if (threadIdx.x == 0) out[0] = s[0] * scale;
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+  if (lane == 0) s[t >> 6] = acc;
+  __syncthreads();
+  if (t == 0) {
+    float tot = 0.f;
+    for (int w = 0; w < 16; ++w) tot += s[w];
+    out[0] = tot * scale;
+  }
 }
 
 // Training targets of instance i: its final group bests, normalised by the
@@ -390,15 +413,18 @@ __global__ __launch_bounds__(256) void targets_kernel(Pools pl, float* T, int ld
 }
 
 // Column sums of a B x n FP32 matrix (bias gradients), in a fixed order:
-// block (x, y) takes 64 columns of the row chunk [256y, 256y + 256), its
+// block (x, y) takes 64 columns of the row chunk [cr y, cr y + cr), its
 // wave w sums rows w, w+4, ... of the chunk (eight loads in flight per lane)
 // and the four partial sums are added in wave order into part[y][col];
-// colsum_fin_kernel then adds the chunks in a fixed order.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int n, float* part) {
+// colsum_fin_kernel then adds the chunks in a fixed order.  Chunks are 256
+// rows when that still gives 128 blocks or more, else 32 (a small batch: more
+// blocks, one round of loads per wave).
+__global__ __launch_bounds__(256) void colsum_kernel(const float* dz, int B, int n, int cr,
+                                                     float* part) {
   __shared__ float ps[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
-  const int r0 = blockIdx.y * 256, r1 = min(B, r0 + 256);
+  const int r0 = blockIdx.y * cr, r1 = min(B, r0 + cr);
   float s = 0.f;
   if (j < n) {
 #pragma unroll 8
@@ -551,11 +577,11 @@ void launch_gemm(bool a_km, bool b_kn, const uint16_t* A, int lda, const uint16_
 
 void launch_loss(const float* y, const float* target, int B, int n, float* dy, uint16_t* dy16,
                  float* row_sq, hipStream_t s) {
-  hipLaunchKernelGGL(loss_kernel, dim3(B), dim3(256), 0, s, y, target, B, n, dy, dy16, row_sq);
+  hipLaunchKernelGGL(loss_kernel, dim3((B + 3) / 4), dim3(256), 0, s, y, target, B, n, dy, dy16, row_sq);
 }
 
 void launch_loss_sum(const float* row_sq, int B, float scale, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, row_sq, B, scale, out);
+  hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(1024), 0, s, row_sq, B, scale, out);
 }
 
 void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t s) {
@@ -563,8 +589,10 @@ void launch_targets(const Pools& pl, int n_inst, float* T, int ldt, hipStream_t 
 }
 
 void launch_colsum(const float* dz, int B, int n, float* out, float* ws, hipStream_t s) {
-  const int R = (B + 255) / 256;
-  hipLaunchKernelGGL(colsum_kernel, dim3((n + 63) / 64, R), dim3(256), 0, s, dz, B, n, ws);
+  const int nb = (n + 63) / 64;
+  const int cr = (int64_t)nb * ((B + 255) / 256) >= 128 ? 256 : 32;
+  const int R = (B + cr - 1) / cr;
+  hipLaunchKernelGGL(colsum_kernel, dim3(nb, R), dim3(256), 0, s, dz, B, n, cr, ws);
   hipLaunchKernelGGL(colsum_fin_kernel, dim3((n + 31) / 32), dim3(256), 0, s, ws, R, n, out);
 }
 
