@@ -92,6 +92,35 @@ def test_gradients_match_oracle(sp, rows):
     lin.close()
 
 
+def test_full_grid_products(sp):
+    # 8192 rows: the products whose 128 x 128 tile grid already fills the GPU
+    # run without a split of K, their epilogue in the product kernel.
+    # Forward rows are independent: sampled rows against the oracle.  The
+    # gradients are checked against the mean of the four 2048-row quarters'
+    # gradients (each checked against the oracle at that size above): the
+    # loss scale 2 / (B n) changes by an exact power of two, so both sides
+    # round the same values to BF16, and only FP32 summation order (and a
+    # rare activation on the other side of a BF16 rounding boundary) differs.
+    rows, q = 8192, 2048
+    lin = sp.LearnedInit(max_rows=rows, seed=5)
+    W, b = sp.split_params(lin.get_weights().astype(np.float64))
+    x, t = _inputs(rows, 4)
+    y = lin.forward(x)
+    idx = np.sort(np.random.default_rng(9).choice(rows, 48, replace=False))
+    ref = orc.mlp(SIZES, W, b, x[idx].astype(np.float64), round=True, grads=False)["y"]
+    assert _rel(y[idx], ref) <= 1e-2 and _cos(y[idx], ref) >= 0.999
+    _, g = lin.grads(x, t)
+    gq = sum(lin.grads(x[i:i + q], t[i:i + q])[1].astype(np.float64) for i in range(0, rows, q))
+    gq /= rows // q
+    gW, gb = sp.split_params(g.astype(np.float64))
+    qW, qb = sp.split_params(gq)
+    for l in range(4):
+        for got, want in ((gW[l], qW[l]), (gb[l], qb[l])):
+            assert _rel(got, want) <= 1e-3, (l, _rel(got, want))
+            assert _cos(got, want) >= 0.99999, (l, _cos(got, want))
+    lin.close()
+
+
 def test_raster_features_match_oracle(sp):
     maps = I.random_static_maps(24, seed=11)
     sws = [I.learned_swarm(seed=1, instance=i) for i in range(24)]
