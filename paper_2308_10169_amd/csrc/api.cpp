@@ -112,15 +112,44 @@ bool is_axis_rect(const float* v, int m) {
   return true;
 }
 
-// Per polygon of a map: (1, slot among rectangles) or (0, first slot among
-// the other polygons' edges).
-void classify_polys(const sepso_map& m, std::vector<int2>* kind, int* n_rects, int* n_gedges) {
+// A simple convex polygon of at most kCPolyMax vertices: every turn
+// strictly the same way (cross products of consecutive edges, exact in
+// double for the coordinates a map holds) and one turn around in total (so
+// that a pentagram, whose turns also agree, does not pass).  Returns +1
+// (counter-clockwise), -1 (clockwise) or 0 (not such a polygon).
+int convex_turn(const float* v, int m) {
+  if (m < 3 || m > kCPolyMax) return 0;
+  int sign = 0;
+  double turn = 0.0;
+  for (int j = 0; j < m; ++j) {
+    const double ax = v[2 * j], ay = v[2 * j + 1];
+    const double bx = v[2 * ((j + 1) % m)], by = v[2 * ((j + 1) % m) + 1];
+    const double cx = v[2 * ((j + 2) % m)], cy = v[2 * ((j + 2) % m) + 1];
+    const double cr = (bx - ax) * (cy - by) - (by - ay) * (cx - bx);
+    const int sg = cr > 0.0 ? 1 : cr < 0.0 ? -1 : 0;
+    if (sg == 0 || (sign != 0 && sg != sign)) return 0;
+    sign = sg;
+    double a = std::atan2(cy - by, cx - bx) - std::atan2(by - ay, bx - ax);
+    while (a > M_PI) a -= 2.0 * M_PI;
+    while (a < -M_PI) a += 2.0 * M_PI;
+    turn += a;
+  }
+  return std::fabs(std::fabs(turn) - 2.0 * M_PI) < 1.0 ? sign : 0;
+}
+
+// Per polygon of a map: (1, slot among rectangles), (2 counter-clockwise or
+// 3 clockwise, slot among convex polygons) or (0, first slot among the
+// other polygons' edges).
+void classify_polys(const sepso_map& m, std::vector<int2>* kind, int* n_rects, int* n_gedges,
+                    int* n_cpolys) {
   kind->assign(m.n_polys, make_int2(0, 0));
-  int nr = 0, ne = 0;
+  int nr = 0, ne = 0, nc = 0;
   for (int q = 0; q < m.n_polys; ++q) {
     const int v0 = m.poly_ptr[q], cnt = m.poly_ptr[q + 1] - v0;
     if (is_axis_rect(m.verts + 2 * v0, cnt)) {
       (*kind)[q] = make_int2(1, nr++);
+    } else if (const int turn = convex_turn(m.verts + 2 * v0, cnt)) {
+      (*kind)[q] = make_int2(turn > 0 ? 2 : 3, nc++);
     } else {
       (*kind)[q] = make_int2(0, ne);
       ne += cnt;
@@ -128,6 +157,7 @@ void classify_polys(const sepso_map& m, std::vector<int2>* kind, int* n_rects, i
   }
   *n_rects = nr;
   *n_gedges = ne;
+  if (n_cpolys) *n_cpolys = nc;
 }
 
 Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vector<InstDesc>* desc) {
@@ -137,17 +167,20 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   for (int i = 0; i < n; ++i) {
     const int G = sw[i].groups, N = sw[i].particles, W = sw[i].waypoints, D = 2 * W;
     const int64_t P = (int64_t)G * N;
-    int n_rects = 0, n_gedges = 0;
-    classify_polys(maps[i], &kind, &n_rects, &n_gedges);
+    int n_rects = 0, n_gedges = 0, n_cpolys = 0;
+    classify_polys(maps[i], &kind, &n_rects, &n_gedges, &n_cpolys);
     if (desc) {
       InstDesc& d = (*desc)[i];
       d.n_rects = n_rects;
       d.n_gedges = n_gedges;
+      d.n_cpolys = n_cpolys;
       d.ro = (int32_t)L.sumR;
       d.geo = (int32_t)L.sumGE;
+      d.cpo = (int32_t)L.sumCP;
     }
     L.sumR += (n_rects + 3) & ~3;  // whole 64-byte quads per instance
     L.sumGE += n_gedges;
+    L.sumCP += n_cpolys;
     if (desc) {
       InstDesc& d = (*desc)[i];
       d.G = G;
@@ -210,6 +243,7 @@ Layout plan_layout(const sepso_map* maps, const sepso_swarm* sw, int n, std::vec
   L.Q = take(4 * L.sumP);
   L.PQ = take(4 * L.sumP);
   L.edges = take(sizeof(EdgeRec) * L.sumGE);
+  L.cpolys = take(sizeof(CPoly) * L.sumCP);
   L.rects = take(32 * L.sumR);  // boxes, then centres and half sides
   L.pkind = take(8 * L.sumPoly);
   L.verts = take(8 * L.sumE);
@@ -475,6 +509,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
   pl.Q = at<int32_t>(b, L.Q);
   pl.PQ = at<int32_t>(b, L.PQ);
   pl.edges = at<EdgeRec>(b, L.edges);
+  pl.cpolys = at<CPoly>(b, L.cpolys);
   pl.rects = at<float4>(b, L.rects);
   pl.rect_c = pl.rects + L.sumR;
   pl.pkind = at<int2>(b, L.pkind);
@@ -509,7 +544,7 @@ sepso_status create_batch(const sepso_map* maps, const sepso_swarm* sw, int n, v
     {
       std::vector<int2> kind;
       int nr = 0, ne = 0;
-      classify_polys(maps[i], &kind, &nr, &ne);
+      classify_polys(maps[i], &kind, &nr, &ne, nullptr);
       for (int q = 0; q < d.n_polys; ++q) pkind[d.pvo + q] = kind[q];
       if (i == 0) b->h_kind = kind;
     }
@@ -890,10 +925,10 @@ sepso_status sepso_plan_frame(sepso_ctx* ctx, const sepso_map* next, sepso_frame
     {
       std::vector<int2> kind;
       int nr = 0, ne = 0;
-      classify_polys(*next, &kind, &nr, &ne);
+      classify_polys(*next, &kind, &nr, &ne, nullptr);
       for (int q = 0; q < d.n_polys; ++q)
         if (kind[q].x != b->h_kind[q].x)
-          return fail(SEPSO_E_ARG, "next map: polygon %d changed between rectangle and general", q);
+          return fail(SEPSO_E_ARG, "next map: polygon %d changed kind (rectangle, convex, general)", q);
     }
     std::vector<float> e4 = {next->start[0], next->start[1], next->target[0], next->target[1]};
     HIPCHK(b, hipMemcpyAsync(b->pl.verts + d.eo, next->verts, 8 * (size_t)d.n_edges,

@@ -43,6 +43,22 @@ struct EdgeRec {
 };
 static_assert(sizeof(EdgeRec) == 32, "EdgeRec is 32 bytes");
 
+// One convex polygon of at most kCPolyMax vertices (every turn strictly the
+// same way), 192 bytes read through the scalar cache: integer keys of its
+// bounding box (ordering as the floats do), its vertex count, then per edge
+// the line coefficients oriented so that the interior is on the positive
+// side -- ev(p) = ex * p.y + ney * p.x + nce -- and per vertex its
+// coordinates.
+constexpr int kCPolyMax = 8;
+struct CPoly {
+  int32_t kx0, ky0, kx1, ky1;
+  int32_t n;
+  int32_t pad[3];
+  float ex[kCPolyMax], ney[kCPolyMax], nce[kCPolyMax];
+  float vx[kCPolyMax], vy[kCPolyMax];
+};
+static_assert(sizeof(CPoly) == 192, "CPoly is 192 bytes");
+
 // Read-only description of one instance (sizes, constants, pool offsets).
 struct InstDesc {
   int32_t G, N, W, T;
@@ -61,7 +77,9 @@ struct InstDesc {
   int64_t po;            // per-particle pools: G*N
   int32_t eo;            // vertices (n_edges float2)
   int32_t n_rects;       // polygons that are axis-aligned rectangles
-  int32_t n_gedges;      // edges of the other polygons
+  int32_t n_gedges;      // edges of the other non-convex polygons
+  int32_t n_cpolys;      // convex polygons (other than rectangles)
+  int32_t cpo;           // their records (n_cpolys CPoly)
   int32_t ro;            // rectangle records (n_rects float4: x0, y0, x1, y1)
   int32_t geo;           // general edge records (n_gedges)
   int32_t plo;           // poly_ptr pool (n_polys+1)
@@ -111,9 +129,10 @@ struct Pools {
   float *f, *L, *Pf, *PL;
   int32_t *Q, *PQ;
   EdgeRec* edges;    // general polygons' edges
+  CPoly* cpolys;     // convex polygons
   float4* rects;     // axis-aligned rectangles (x0, y0, x1, y1), x0 < x1, y0 < y1
   float4* rect_c;    // their centres and half sides (xc, yc, w/2, h/2)
-  int2* pkind;       // per polygon: (1 = rectangle / 0 = general, slot in its pool)
+  int2* pkind;       // per polygon: (1 = rectangle / 2, 3 = convex, counter-clockwise or not / 0 = general, slot in its pool)
   float2* verts;
   int32_t* poly_ptr;
   float2* poly_vel;

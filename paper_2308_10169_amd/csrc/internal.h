@@ -30,8 +30,8 @@ struct Layout {
   size_t desc, ctl, X, V, P, f, L, Pf, PL, Q, PQ, edges, verts, pptr, pvel, ends, endv, gbn, gbf, hyper, ohyper, ov, op, opf, gpos, tpos, prev, prop, blkt, blki, total;
   int64_t sumPD = 0, sumP = 0, sumTilesMax = 0;
   int64_t sumE = 0, sumPP = 0, sumPoly = 0, sumG = 0, sumGD = 0, sumD = 0, initBlocks = 0;
-  int64_t sumR = 0, sumGE = 0;  // rectangles, edges of other polygons
-  size_t rects = 0, pkind = 0;
+  int64_t sumR = 0, sumGE = 0, sumCP = 0;  // rectangles, edges of other polygons, convex polygons
+  size_t rects = 0, pkind = 0, cpolys = 0;
 };
 
 }  // namespace sepso

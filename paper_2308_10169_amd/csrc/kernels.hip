@@ -21,6 +21,12 @@ __device__ __forceinline__ bool better(float fa, int na, float fb, int nb) {
   return fa < fb || (fa == fb && na < nb);
 }
 
+// Integer key of a float that orders as the values do (-0 just below +0).
+__device__ __forceinline__ int float_key(float x) {
+  const int b = __float_as_int(x);
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+
 // ---------------------------------------------------------------------------
 // Geometry: obstacles translate by their per-frame velocity and bounce off
 // the map border (velocity component reversed, overshoot mirrored); start
@@ -97,6 +103,30 @@ __global__ __launch_bounds__(256) void geom_kernel(Pools pl, int move) {
       // centre and half sides (exact: the corners lie on a 1/256 grid)
       pl.rect_c[d.ro + ks.y] = make_float4((x0 + x1) * 0.5f, (y0 + y1) * 0.5f, (x1 - x0) * 0.5f,
                                            (y1 - y0) * 0.5f);
+      continue;
+    }
+    if (ks.x >= 2) {  // convex: box keys, lines with the interior on their positive side, vertices
+      CPoly& c = pl.cpolys[d.cpo + ks.y];
+      const float sg = ks.x == 2 ? 1.f : -1.f;
+      float x0 = verts[v0].x, y0 = verts[v0].y, x1 = x0, y1 = y0;
+      for (int j = 0; j < m; ++j) {
+        const float2 a = verts[v0 + j], b = verts[v0 + (j + 1 == m ? 0 : j + 1)];
+        const float ex = b.x - a.x, ey = b.y - a.y;
+        c.ex[j] = sg * ex;
+        c.ney[j] = sg * -ey;
+        c.nce[j] = sg * -fmaf(ex, a.y, -(ey * a.x));
+        c.vx[j] = a.x;
+        c.vy[j] = a.y;
+        x0 = fminf(x0, a.x);
+        x1 = fmaxf(x1, a.x);
+        y0 = fminf(y0, a.y);
+        y1 = fmaxf(y1, a.y);
+      }
+      c.kx0 = float_key(x0);
+      c.ky0 = float_key(y0);
+      c.kx1 = float_key(x1);
+      c.ky1 = float_key(y1);
+      c.n = m;
       continue;
     }
     EdgeRec* er = pl.edges + d.geo + ks.y;
@@ -452,11 +482,6 @@ __global__ __launch_bounds__(512) void reduce_kernel(Pools pl, int flags) {
   }
 }
 
-// Integer key of a float that orders as the values do (-0 just below +0).
-__device__ __forceinline__ int float_key(float x) {
-  const int b = __float_as_int(x);
-  return b ^ ((b >> 31) & 0x7fffffff);
-}
 
 // Direct global -> LDS loads (no registers on the way): lane i of the wave
 // writes its word at dst_wave + i, dst_wave the same for the whole wave.
@@ -544,11 +569,13 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
   // are o(centre) +- |dx| h/2 +- |dy| w/2), by two FMAs for o(centre) and
   // two for the difference, within the degenerate band of the exact value.
   // Where a test is degenerate the count may resolve it either way.
+  const int kx0 = __builtin_amdgcn_readfirstlane(float_key(bx0));
+  const int kx1 = __builtin_amdgcn_readfirstlane(float_key(bx1));
+  const int ky0 = __builtin_amdgcn_readfirstlane(float_key(by0));
+  const int ky1 = __builtin_amdgcn_readfirstlane(float_key(by1));
+  constexpr uint32_t kOnes = (2u << K) - 1u;
+  const uint32_t segmask = active ? (kOnes & ~1u) : 0u;
   {
-    const int kx0 = __builtin_amdgcn_readfirstlane(float_key(bx0));
-    const int kx1 = __builtin_amdgcn_readfirstlane(float_key(bx1));
-    const int ky0 = __builtin_amdgcn_readfirstlane(float_key(by0));
-    const int ky1 = __builtin_amdgcn_readfirstlane(float_key(by1));
     // lo < c < hi as one unsigned comparison of the coordinate's bits (the
     // box is not empty here; a coordinate of -0 lies on the map's border,
     // its bits test as outside).
@@ -556,9 +583,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
     auto inside = [](float c, int lo, uint32_t n) { return (uint32_t)(__float_as_int(c) - lo - 1) < n; };
     // Words: bit K - s for point s; segment s (points s, s + 1) at bit K - s,
     // so its second point is the word shifted left by one.  Bits 1..K are the
-    // segments; inactive lanes keep none.
-    constexpr uint32_t kOnes = (2u << K) - 1u;
-    const uint32_t segmask = active ? (kOnes & ~1u) : 0u;
+    // segments (segmask); inactive lanes keep none.
     // sign bits of (c - p_s) (sub_c_p) or of (p_s - c)
     auto side_word = [&](const float (&p)[K + 1], float c, bool sub_c_p) {
       uint32_t w = 0;
@@ -614,6 +639,65 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       count(thr);
       count(thr);
       }
+    }
+  }
+  // C3. convex polygons other than rectangles, records read through the
+  // scalar cache and dealt over the wave groups like the rectangles, culled
+  // on their box keys.  The same in/out form: a segment crosses a convex
+  // boundary once when exactly one end point is strictly inside (on the
+  // positive side of every edge line), never when both are, and twice when
+  // both are outside and no line separates it from the polygon -- neither
+  // an edge line with both end points strictly outside (a whole polygon lies
+  // on the inner side of each of its edge lines), nor the segment's own line
+  // with every vertex on one side.  Point sides are the edge-line tests the
+  // edge-by-edge path makes, vertex sides its segment-line tests (the
+  // latter only for waves holding a candidate segment); where one is
+  // degenerate the count may resolve it either way.
+  {
+    typedef __attribute__((address_space(4))) const CPoly ConstCPoly;
+    typedef int ci8 __attribute__((ext_vector_type(8)));
+    typedef float cf8 __attribute__((ext_vector_type(8)));
+    typedef __attribute__((address_space(4))) const ci8 ConstCI8;
+    typedef __attribute__((address_space(4))) const cf8 ConstCF8;
+    ConstCPoly* cp = (ConstCPoly*)(pl.cpolys + d.cpo);
+    for (int q = rg; q < d.n_cpolys; q += R) {
+      ConstCPoly& c = cp[q];
+      const ci8 h = *(ConstCI8*)&c.kx0;  // box keys and vertex count in one load
+      if (h[2] <= kx0 || h[0] >= kx1 || h[3] <= ky0 || h[1] >= ky1) continue;
+      const int n = h[4];
+      // every slot is loaded (those past n hold no edge and are not used),
+      // so that the loads go out together
+      const cf8 cex = *(ConstCF8*)c.ex, cney = *(ConstCF8*)c.ney, cnce = *(ConstCF8*)c.nce;
+      uint32_t outw = 0, sepe = 0;  // some edge line / the same edge line has the point outside
+#pragma unroll
+      for (int e = 0; e < kCPolyMax; ++e) {
+        if (e >= n) break;
+        const float ex = cex[e], ney = cney[e], nce = cnce[e];
+        uint32_t ow = 0;
+#pragma unroll
+        for (int s = 0; s <= K; ++s) {
+          const float ev = fmaf(ex, py[s], fmaf(ney, px[s], nce));
+          ow = __builtin_amdgcn_alignbit(ow, __float_as_uint(ev), 31);
+        }
+        outw |= ow;
+        sepe |= ow & (ow << 1);
+      }
+      const uint32_t in = ~outw & kOnes;
+      count((in ^ (in << 1)) & segmask);  // one end strictly inside
+      const uint32_t cand = ~(in | (in << 1)) & ~sepe & segmask;
+      if (__builtin_amdgcn_ballot_w64(cand != 0u) == 0ull) continue;
+      uint32_t allneg = ~0u, allpos = ~0u;  // bit K - 1 - s: every vertex on one side of segment s's line
+      const cf8 cvx = *(ConstCF8*)c.vx, cvy = *(ConstCF8*)c.vy;
+#pragma unroll
+      for (int v = 0; v < kCPolyMax; ++v) {
+        if (v >= n) break;
+        const uint32_t vw = pack_seg_sides<K>(cvx[v], cvy[v], dx, ndy, nc);
+        allneg &= vw;
+        allpos &= ~vw;
+      }
+      const uint32_t thr = cand & ~((allneg | allpos) << 1);
+      count(thr);
+      count(thr);
     }
   }
   // C2. other polygons, edge by edge, by wave group 0 (consecutive edges

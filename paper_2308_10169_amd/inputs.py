@@ -175,6 +175,32 @@ def random_stars(rng, width, height, n, r_lo, r_hi, spikes=(5, 8)):
     return out
 
 
+def random_convex(rng, width, height, n, r_lo, r_hi, sides=(3, 8)):
+    """n convex polygons of 3-8 vertices: sorted jittered angles on a circle
+    of radius ~ U[r_lo, r_hi] centred inside the map; every other one listed
+    clockwise."""
+    out = []
+    for k in range(n):
+        m = int(rng.integers(sides[0], sides[1] + 1))
+        r = rng.uniform(r_lo, r_hi)
+        cx, cy = rng.uniform(r, width - r), rng.uniform(r, height - r)
+        th = (np.arange(m) + rng.uniform(-0.3, 0.3, m)) * (2.0 * math.pi / m)
+        q = np.stack([cx + r * np.cos(th), cy + r * np.sin(th)], axis=1)
+        q = np.clip(snap(q), 0.0, [width, height])
+        out.append(q[::-1].copy() if k % 2 else q)
+    return out
+
+
+def convex_map(seed, S=200.0, n_rects=6, n_convex=12):
+    """Rectangles and convex polygons of 3-8 vertices in both orientations,
+    start and target in opposite corners."""
+    rng = np.random.default_rng(seed)
+    s, t = snap([0.04 * S, 0.06 * S]), snap([0.96 * S, 0.94 * S])
+    rects = random_rects(rng, S, S, n_rects, 0.04 * S, 0.15 * S, avoid=(s, t))
+    polys = random_convex(rng, S, S, n_convex, 0.04 * S, 0.12 * S)
+    return make_map(S, S, list(rects) + polys, s, t)
+
+
 def nonconvex_map(seed, S=200.0, n_rects=6, n_stars=6):
     """Mixed obstacle set: rectangles and non-convex stars (a variant the
     polygon representation allows), start and target in opposite corners."""

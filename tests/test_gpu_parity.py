@@ -91,6 +91,31 @@ def test_nonconvex_polygons_every_step(sp):
     assert stats["paths"] == 2 * 10 * 4 * 48
 
 
+def test_convex_polygons_every_step(sp):
+    # Rectangles mixed with convex polygons of 3-8 vertices listed in both
+    # orientations: the convex in/out path (and any polygon that snapping left
+    # not strictly convex, on the edge-by-edge path), ragged W = 11.
+    stats = {}
+    for seed in (0, 1, 2):
+        spec = I.convex_map(seed)
+        sw = I.dynamic_swarm(spec.scale, seed=seed, groups=4, particles=48, waypoints=11)
+        _run_injected(sp, spec, sw, 10, stats)
+    print("parity stats", stats)
+    assert stats["paths"] == 3 * 10 * 4 * 48
+
+
+def test_nonconvex_edges_over_several_passes(sp):
+    # 30 stars (about 400 edges): the edge records pass through LDS in more
+    # than one chunk.
+    stats = {}
+    spec = I.nonconvex_map(4, n_stars=30)
+    assert spec.poly_ptr[-1] - 4 * 6 > 256
+    sw = I.dynamic_swarm(spec.scale, seed=4, groups=4, particles=48, waypoints=11)
+    _run_injected(sp, spec, sw, 6, stats)
+    print("parity stats", stats)
+    assert stats["paths"] == 6 * 4 * 48
+
+
 def test_dynamic_shape_steps(sp):
     # Paper-shaped instance: 366 map, 30 rectangles, 8 x 170 particles, W = 20.
     spec = I.dynamic_map(0)
