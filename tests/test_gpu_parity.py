@@ -104,6 +104,27 @@ def test_convex_polygons_every_step(sp):
     assert stats["paths"] == 3 * 10 * 4 * 48
 
 
+def test_polygons_the_convex_form_must_refuse(sp):
+    # Polygons whose turns all agree but that are no simple convex polygon
+    # (a pentagram), with a straight angle (three collinear vertices), with
+    # more than eight vertices, and a convex one among them: only the last
+    # may take the convex form, and every step must match the oracle.
+    import math
+    S = 200.0
+    star = [(100 + 40 * math.cos(math.pi / 2 + 4 * math.pi * k / 5),
+             100 + 40 * math.sin(math.pi / 2 + 4 * math.pi * k / 5)) for k in range(5)]
+    flat = [(20, 120), (50, 120), (80, 120), (60, 170), (30, 160)]
+    ring = [(150 + 25 * math.cos(2 * math.pi * k / 12), 60 + 25 * math.sin(2 * math.pi * k / 12))
+            for k in range(12)]
+    tri = [(40, 40), (80, 50), (55, 85)]
+    spec = I.make_map(S, S, [I.snap(p) for p in (star, flat, ring, tri)], (8.0, 12.0), (192.0, 188.0))
+    sw = I.dynamic_swarm(spec.scale, seed=5, groups=4, particles=48, waypoints=11)
+    stats = {}
+    _run_injected(sp, spec, sw, 8, stats)
+    print("parity stats", stats)
+    assert stats["paths"] == 8 * 4 * 48
+
+
 def test_nonconvex_edges_over_several_passes(sp):
     # 30 stars (about 400 edges): the edge records pass through LDS in more
     # than one chunk.
