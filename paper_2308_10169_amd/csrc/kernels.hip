@@ -519,10 +519,11 @@ __device__ __forceinline__ void stage_records(const Pools& pl, const InstDesc& d
 }
 
 // Phase C of the fused iteration: crossings of this thread's K segments with
-// every obstacle edge of the instance.  Rectangles are read through the
-// scalar cache; the other polygons' edge records are staged through LDS
-// (s_stage: the first chunk was staged before the block's first barrier,
-// later ones are staged here by all threads of the block between barriers).  Crossing
+// every obstacle edge of the instance.  Rectangles and convex polygons are
+// read through the scalar cache; the other polygons' edge records are staged
+// through LDS (s_stage: the first chunk was staged before the block's first
+// barrier, later ones are staged here by all threads of the block between
+// barriers).  Crossing
 // words: bit K-1-s set when segment s properly crosses the edge (never for
 // masked slots); ct counts them.
 template <int K, int R>
@@ -553,7 +554,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
     by0 = fminf(by0, __shfl_xor(by0, m));
     by1 = fmaxf(by1, __shfl_xor(by1, m));
   }
-  // C1. axis-aligned rectangles, read through the scalar cache: a record is
+  // C.1 axis-aligned rectangles, read through the scalar cache: a record is
   // the same for every lane, so it stays in scalar registers and the culling
   // test runs on the scalar unit, on integer keys that order floats as their
   // values do (the key order puts -0 below +0, so it never culls more than
@@ -641,7 +642,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       }
     }
   }
-  // C3. convex polygons other than rectangles, records read through the
+  // C.2 convex polygons other than rectangles, records read through the
   // scalar cache and dealt over the wave groups like the rectangles, culled
   // on their box keys.  The same in/out form: a segment crosses a convex
   // boundary once when exactly one end point is strictly inside (on the
@@ -700,7 +701,7 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       count(thr);
     }
   }
-  // C2. other polygons, edge by edge, by wave group 0 (consecutive edges
+  // C.3 other polygons, edge by edge, by wave group 0 (consecutive edges
   // share vertex words; the other groups still take part in the staging
   // barriers).  An edge outside the wave's box is skipped like a rectangle (a
   // proper crossing lies strictly inside both the segment and the edge); the
@@ -773,10 +774,12 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
 //  B. a particle's W+1 segments are cut into C chunks of K; thread t takes
 //     chunk t / ppb of particle t mod ppb (slots past the last segment are
 //     masked out);
-//  C. crossings of the K segments with every obstacle edge (records staged
-//     in LDS): per edge, one packed side word of the edge's end vertex
-//     against the K segment lines and one of the K+1 points against the
-//     edge line; crossing bits = both straddle;
+//  C. crossings of the K segments with every obstacle edge: rectangles and
+//     convex polygons by their points' inside words (records through the
+//     scalar cache), other polygons edge by edge (records staged in LDS):
+//     one packed side word of the edge's end vertex against the K segment
+//     lines and one of the K+1 points against the edge line, crossing bits
+//     = both straddle;
 //  D. per-particle Q and L summed in chunk order (deterministic), fitness
 //     and Pbest; improved particles' positions go from LDS to P.
 // ---------------------------------------------------------------------------
