@@ -196,7 +196,11 @@ sepso_status sepso_step(sepso_ctx* ctx, int32_t n);
  * one step of the device motion model for frames after the first; swarm
  * init with Priori Initialization from the last frame's plan; iterations
  * with online HSEF until Auto Truncation or max_iters.  Synchronises once;
- * writes *out and the plan's 2W path values to out_path (may be NULL). */
+ * writes *out and the plan's 2W path values to out_path (may be NULL).
+ * A next map keeps the polygon structure: the same poly_ptr, and every
+ * polygon of the same kind as in the first map (axis-aligned rectangle;
+ * convex polygon of at most 8 vertices turning the same way; any other),
+ * else SEPSO_E_ARG and nothing runs. */
 sepso_status sepso_plan_frame(sepso_ctx* ctx, const sepso_map* next, sepso_frame_result* out,
                               float* out_path);
 
