@@ -58,6 +58,38 @@ def test_frame_result_is_consistent(sp):
     pl.close()
 
 
+def test_next_map_frames(sp):
+    # Frames on caller-supplied maps: the convex map moved by half a cell
+    # plans a frame whose path scores as reported (the device rebuilt the
+    # convex records from the new vertices); a next map in which a convex
+    # polygon is no longer convex (two vertices swapped: a bow tie) is
+    # refused with SEPSO_E_ARG.
+    spec = I.convex_map(1)
+    sw = I.dynamic_swarm(spec.scale, seed=1, groups=4, particles=48, waypoints=10, iters=10)
+    pl = sp.Planner(spec, sw)
+    pl.plan_frame()
+    nxt = spec.copy()
+    d = 0.5 if nxt.verts.max() + 0.5 <= spec.width else -0.5
+    assert nxt.verts.min() + d >= 0.0
+    nxt.verts = nxt.verts + d
+    r = pl.plan_frame(nxt)
+    chk = orc.fitness(orc.Map(nxt), r["path"][None, :].astype(np.float64), sw.waypoints,
+                      sw.alpha, sw.beta)
+    assert chk["q_yes"][0] <= r["crossings"] <= chk["q_yes"][0] + chk["n_deg"][0]
+    if chk["n_deg"][0] == 0:
+        assert abs(chk["f"][0] - r["cost"]) <= REL * max(chk["f"][0], 1.0)
+    bad = spec.copy()
+    p = next(q for q in range(6, len(bad.poly_ptr) - 1)
+             if bad.poly_ptr[q + 1] - bad.poly_ptr[q] >= 4)
+    a = bad.poly_ptr[p]
+    bad.verts = bad.verts.copy()
+    bad.verts[[a, a + 1]] = bad.verts[[a + 1, a]]
+    with pytest.raises(sp.SepsoError) as ei:
+        pl.plan_frame(bad)
+    assert ei.value.status == sp.E_ARG
+    pl.close()
+
+
 @pytest.mark.parametrize("waypoints", [10, 9])  # D % 4 == 0 and 2
 def test_priori_initialization(sp, waypoints):
     spec = I.dynamic_map(3)
