@@ -27,6 +27,31 @@ __device__ __forceinline__ int float_key(float x) {
   return b ^ ((b >> 31) & 0x7fffffff);
 }
 
+// The float of a key (the map is its own inverse).
+__device__ __forceinline__ float key_float(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+
+// Minimum (maximum) of v over the wave's 64 lanes, every lane taking part:
+// pairs and quads (quad permutations), eights and sixteens (half-row and row
+// mirrors) fold into the min/max instructions as DPP operands, so that every
+// lane of a row of 16 holds the row's value; the four rows meet on the
+// scalar unit.
+__device__ __forceinline__ int wave_min_key(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));  // row_half_mirror
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));  // row_mirror
+  return min(min(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             min(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+__device__ __forceinline__ int wave_max_key(int v) {
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));
+  return max(max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+
 // ---------------------------------------------------------------------------
 // Geometry: obstacles translate by their per-frame velocity and bounce off
 // the map border (velocity component reversed, overshoot mirrored); start
@@ -547,13 +572,16 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
       by1 = fmaxf(by1, py[s]);
     }
   }
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
-    bx0 = fminf(bx0, __shfl_xor(bx0, m));
-    bx1 = fmaxf(bx1, __shfl_xor(bx1, m));
-    by0 = fminf(by0, __shfl_xor(by0, m));
-    by1 = fmaxf(by1, __shfl_xor(by1, m));
-  }
+  // Reduced over the wave as integer keys, then mapped back: the keys'
+  // order is the floats' (-0 just below +0).
+  const int kx0 = wave_min_key(float_key(bx0));
+  const int kx1 = wave_max_key(float_key(bx1));
+  const int ky0 = wave_min_key(float_key(by0));
+  const int ky1 = wave_max_key(float_key(by1));
+  bx0 = key_float(kx0);
+  bx1 = key_float(kx1);
+  by0 = key_float(ky0);
+  by1 = key_float(ky1);
   // C.1 axis-aligned rectangles, read through the scalar cache: a record is
   // the same for every lane, so it stays in scalar registers and the culling
   // test runs on the scalar unit, on integer keys that order floats as their
@@ -570,10 +598,6 @@ __device__ __forceinline__ void crossings(const Pools& pl, const InstDesc& d, fl
   // are o(centre) +- |dx| h/2 +- |dy| w/2), by two FMAs for o(centre) and
   // two for the difference, within the degenerate band of the exact value.
   // Where a test is degenerate the count may resolve it either way.
-  const int kx0 = __builtin_amdgcn_readfirstlane(float_key(bx0));
-  const int kx1 = __builtin_amdgcn_readfirstlane(float_key(bx1));
-  const int ky0 = __builtin_amdgcn_readfirstlane(float_key(by0));
-  const int ky1 = __builtin_amdgcn_readfirstlane(float_key(by1));
   constexpr uint32_t kOnes = (2u << K) - 1u;
   const uint32_t segmask = active ? (kOnes & ~1u) : 0u;
   {
