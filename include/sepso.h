@@ -277,8 +277,8 @@ sepso_status sepso_autotune(sepso_batch* b, sepso_tune* best);
  * "<key> <K> <block_threads>", the key a 64-bit hash (16 hex digits) of the
  * device architecture name, a fingerprint of the library's device-code
  * sources (a rebuilt library does not reuse another build's tiles) and every
- * instance's groups, particles, waypoints, rectangles and other-polygon
- * edges.  When the file holds this
+ * instance's groups, particles, waypoints, rectangles, convex polygons and
+ * other-polygon edges.  When the file holds this
  * batch's key with a valid tile, that tile is applied without timing
  * (and the batch is reset as after sepso_autotune);
  * otherwise the batch is autotuned and a line is appended.  A missing file is

@@ -1186,7 +1186,7 @@ uint64_t tune_key(const sepso_batch* b) {
   mix(&src, sizeof(src));
   mix(&b->n, sizeof(b->n));
   for (const InstDesc& d : b->desc) {
-    const int32_t f[5] = {d.G, d.N, d.W, d.n_rects, d.n_gedges};
+    const int32_t f[6] = {d.G, d.N, d.W, d.n_rects, d.n_cpolys, d.n_gedges};
     mix(f, sizeof(f));
   }
   return h;
@@ -1319,7 +1319,7 @@ uint64_t bucket_key(const sepso_batch* b, const TileBucket& bk) {
   mix(&n, sizeof(n));
   for (int i : bk.inst) {
     const InstDesc& d = b->desc[i];
-    const int32_t f[5] = {d.G, d.N, d.W, d.n_rects, d.n_gedges};
+    const int32_t f[6] = {d.G, d.N, d.W, d.n_rects, d.n_cpolys, d.n_gedges};
     mix(f, sizeof(f));
   }
   return h;
