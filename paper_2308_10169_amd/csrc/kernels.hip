@@ -1089,7 +1089,7 @@ __device__ __forceinline__ void iteration(const Pools& pl, int flags) {
     int j = (4 * t) / D, dd = 4 * t - j * D;
     for (int gi = t; gi < ng; gi += B) {
       const int e = 4 * gi;
-      const int jl = j + (dd + 3) / D;  // particle of the group's last element
+      const int jl = j + (dd + 3 >= D ? 1 : 0);  // particle of the group's last element (dd + 3 < 2D)
       if (e + 4 <= nel && s_imp[j] && s_imp[jl]) {
         P4w[gi] = B4[gi];
       } else if (s_imp[j] || (jl < np && s_imp[jl])) {
