@@ -334,8 +334,18 @@ __global__ __launch_bounds__(256) void splitk_epi_kernel(const float* __restrict
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, MN = (int64_t)M * N;
   if (i >= MN) return;
   float v = part[i];
-  for (int z = 1; z < S; ++z) v += part[z * MN + i];
-  apply_epi(ep, (int)(i / N), (int)(i % N), v);
+  int z = 1;
+  for (; z + 4 <= S; z += 4) {  // four loads in flight, the sum still in slice order
+    const float a = part[z * MN + i], b = part[(z + 1) * MN + i];
+    const float c = part[(z + 2) * MN + i], e = part[(z + 3) * MN + i];
+    v += a;
+    v += b;
+    v += c;
+    v += e;
+  }
+  for (; z < S; ++z) v += part[z * MN + i];
+  const int ii = (int)i, row = ii / N;  // M N <= the split-K workspace, far below 2^31
+  apply_epi(ep, row, ii - row * N, v);
 }
 
 // dy = 2 (y - target) / (B * n) (FP32 and BF16) and per-row squared-error
